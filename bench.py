@@ -1,0 +1,217 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the RoadRunner light-curve path on one MI355X.
+
+Workload: the population evaluation -- 512 parameter vectors drawn from a
+fixed seed (k ~ U(0.05, 0.2), a ~ U(5, 20), b ~ U(0, 0.9), e ~ U(0, 0.3),
+w ~ U(0, 2 pi), P ~ U(1, 10) d, t0 ~ U(0, P)) over 20 000 times at 2-min
+cadence (27.8 d), one power-2 limb-darkening profile tabulated at 200 mu,
+no supersampling, default table grid.  One step is one rr_evaluate call
+(per-vector setup kernel + forward kernel) over the whole population with
+inputs and tables resident in HBM.  The mixed-precision path (FP64 time
+reduction, FP32 bulk) gives the headline value; the FP64 path is timed the
+same way and reported beside it.
+
+Prints one JSON line.  --gpus above 1 exits with a message: this benchmark
+measures one GPU.
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "light-curve points/s (npv×npt×nss) FP32 vs FP64 at 1 ppm; p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+PVCONST_BYTES = 144
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="budget of the CPU-oracle baseline leg")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for f in ("rr_forward.hip", "rr_device.h", "rr_internal.h"):
+        with open(os.path.join(ROOT, "paper_2009_08500_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(kernel, out_bytes_per_launch):
+    """HBM bytes per launch from the committed PMC summary, if it was taken on
+    the current kernel sources; otherwise None."""
+    path = os.path.join(ROOT, "profiles", "forward_population_counters.json")
+    try:
+        with open(path) as fh:
+            prof = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if prof.get("source_hash") != source_hash():
+        return None
+    k = prof.get("kernels", {}).get(kernel)
+    if not k:
+        return None
+    return k.get("hbm_bytes_per_launch")
+
+
+def time_path(rr, tab, series, pv, prec, out, steps, warmup, lib):
+    import torch
+    for _ in range(warmup):
+        rr.evaluate(tab, series, pv, prec, out)
+    torch.cuda.synchronize()
+    step_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(steps)]
+    kern_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(steps)]
+    for a, b in kern_ev:          # materialise the event handles
+        a.record()
+        b.record()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        step_ev[i][0].record()
+        lib.rr_set_kernel_events(kern_ev[i][0].cuda_event, kern_ev[i][1].cuda_event)
+        rr.evaluate(tab, series, pv, prec, out)
+        step_ev[i][1].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lib.rr_set_kernel_events(None, None)
+    step_ms = [a.elapsed_time(b) for a, b in step_ev]
+    kern_ms = [a.elapsed_time(b) for a, b in kern_ev]
+    return wall, step_ms, kern_ms
+
+
+def pct(x, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(x), q))
+
+
+def cpu_baseline(w, grid, budget_s, gpu_out64, gpu_out32):
+    """The FP64 oracle, untuned, on the host: whole population passes over
+    parameter-row chunks until the time budget is used.  Tables are built
+    outside the timed region, as on the GPU side."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    from oracle import roadrunner as orr
+    otab = orr.Tables(w["mu_s"], w["I_s"], **grid)
+    npv = w["pv"].shape[0]
+    chunk = 32
+    done_rows = 0
+    t_used = 0.0
+    err64 = err32 = 0.0
+    with threadpool_limits(limits=1):
+        while t_used < budget_s:
+            r0 = done_rows % npv
+            rows = slice(r0, min(npv, r0 + chunk))
+            t0 = time.perf_counter()
+            ref = orr.evaluate(otab, w["times"], w["pv"][rows])
+            t_used += time.perf_counter() - t0
+            done_rows += ref.shape[0]
+            if done_rows <= npv:
+                err64 = max(err64, float(np.abs(gpu_out64[rows] - ref).max()))
+                err32 = max(err32, float(np.abs(gpu_out32[rows] - ref).max()))
+    pts = done_rows * w["times"].size
+    sample = (f"{done_rows} parameter rows of the same population (chunks of {chunk}, "
+              f"cycling through all {npv}) x {w['times'].size} times, "
+              f"{t_used:.1f} s of single-thread NumPy FP64")
+    return dict(value=pts / t_used, unit="points/s", cores=1, kind="oracle", sample=sample), \
+        dict(rows_checked=min(done_rows, npv), max_abs_err_fp64=err64,
+             max_abs_err_mixed_ppm=err32 * 1e6)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: every run here has a single MI355X; "
+              "the path would shard over parameter vectors (one slice per GPU, "
+              "tables replicated) -- see the design notes.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2009_08500_amd as rr
+    import workloads as wl
+
+    torch.cuda.set_device(0)
+    lib = rr.lib()
+    w = wl.population()
+    grid = wl.DEFAULT_GRID
+    npv, npt = w["pv"].shape[0], w["times"].size
+    nss = 1
+    tab = rr.Tables(w["mu_s"], w["I_s"], grid)
+    series = rr.TimeSeries(w["times"])
+    pv = torch.as_tensor(w["pv"], device="cuda")
+    out32 = torch.empty((npv, npt), dtype=torch.float32, device="cuda")
+    out64 = torch.empty((npv, npt), dtype=torch.float64, device="cuda")
+
+    res = {}
+    for prec, out in (("mixed", out32), ("fp64", out64)):
+        wall, step_ms, kern_ms = time_path(rr, tab, series, pv, prec, out,
+                                           args.steps, args.warmup, lib)
+        res[prec] = dict(wall=wall, step_ms=step_ms, kern_ms=kern_ms)
+    points = npv * npt * nss
+
+    def summary(prec, out_bytes):
+        r = res[prec]
+        ms = 1e3 * r["wall"] / args.steps
+        kern = float(np.mean(r["kern_ms"]))
+        traffic_alg = npv * npt * out_bytes + npt * 8 + npv * (8 * pv.shape[1] + PVCONST_BYTES)
+        return dict(value=points / (ms / 1e3), ms_per_step=ms,
+                    latency_ms=dict(p50=pct(r["step_ms"], 50), p99=pct(r["step_ms"], 99)),
+                    kernel_ms=dict(mean=kern, p50=pct(r["kern_ms"], 50), p99=pct(r["kern_ms"], 99)),
+                    alg_bytes=traffic_alg)
+
+    m = summary("mixed", 4)
+    d = summary("fp64", 8)
+    achieved = m["alg_bytes"] / (m["kernel_ms"]["mean"] / 1e3) / 1e9
+    traffic = traffic_from_profile("k_forward<float>", m["alg_bytes"])
+    roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=achieved / HBM_PEAK_GBS, traffic=traffic,
+                kernel="k_forward<float>", alg_bytes_per_launch=m["alg_bytes"],
+                kernel_ms=m["kernel_ms"]["mean"])
+    achieved64 = d["alg_bytes"] / (d["kernel_ms"]["mean"] / 1e3) / 1e9
+
+    line = dict(
+        metric=METRIC, value=m["value"], unit="points/s", n_gpus=1, steps=args.steps,
+        warmup=args.warmup, ms_per_step=m["ms_per_step"], higher_is_better=True,
+        scaling="weak", vs_baseline=None, dtype="f32", data="synthetic",
+        config=dict(workload=f"population evaluation npv={npv} npt={npt} nss={nss}, "
+                             "2-min cadence, power-2 LD tabulated at 200 mu",
+                    npv=npv, npt=npt, nss=nss, precision="mixed (FP64 time reduction, FP32 bulk)",
+                    grid=grid),
+        latency_ms=m["latency_ms"],
+        fp64=dict(value=d["value"], ms_per_step=d["ms_per_step"], latency_ms=d["latency_ms"],
+                  dtype="f64", roofline=dict(bound="hbm", achieved=achieved64,
+                                             peak=HBM_PEAK_GBS, unit="GB/s",
+                                             frac=achieved64 / HBM_PEAK_GBS,
+                                             kernel_ms=d["kernel_ms"]["mean"])),
+        roofline=roof,
+        in_transit_fraction=None,
+        source_hash=source_hash(),
+    )
+    o32 = out32.cpu().numpy().astype(np.float64)
+    o64 = out64.cpu().numpy()
+    line["in_transit_fraction"] = float(np.mean(o64 < 1.0))
+    if not args.no_cpu_baseline:
+        cb, acc = cpu_baseline(w, grid, args.cpu_seconds, o64, o32)
+        line["cpu_baseline"] = cb
+        line["accuracy_vs_oracle"] = acc
+    else:
+        line["cpu_baseline"] = None
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

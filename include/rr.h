@@ -1,0 +1,181 @@
+/*
+ * rr.h -- C ABI of the MI355X RoadRunner light-curve library (librr.so).
+ *
+ * RoadRunner (Parviainen 2020) evaluates limb-darkened transit light curves
+ * as F = (I_star - (w . l) a(z, k)) / I_star (Eq. 5): the occluded area
+ * a(z, k) of the stellar disk times the mean occluded surface brightness
+ * w . l, which is precomputed over a grid of radius ratios k and grazing
+ * values g = z / (1 + k) and interpolated (Sect. 3.1.2).  This library runs
+ * the whole path on one AMD Instinct MI355X (gfx950):
+ *
+ *   rr_prepare_ld   z-grid, annulus weights W over (k, g), LD profile at the
+ *                   bin means, I_star, LD-weighted tables T = W . l
+ *                   (Sect. 2, Sect. 3.1.1, Sect. 3.1.2, Sect. 3.2.2);
+ *   rr_evaluate     fluxes for a population of parameter vectors over a
+ *                   heterogeneous, supersampled time series (Sect. 4.1,
+ *                   Sect. 4.2): phase -> Kepler orbit -> separation z ->
+ *                   g-interpolation x lens area -> supersample mean;
+ *   rr_loglik_grad  Gaussian log-likelihood of observed fluxes and its
+ *                   gradient with respect to every parameter and to the
+ *                   LD profile samples (hand-written adjoint);
+ *   rr_server_*     a continuous-batching request loop over resident tables.
+ *
+ * Conventions shared by all entry points
+ * --------------------------------------
+ * Pointers named *_d are device pointers (memory of the current HIP device);
+ * others are host pointers.  The caller owns every buffer it passes; the
+ * library owns rr_tables and rr_server objects.  Calls that take a stream
+ * enqueue their device work on it and return without waiting, unless stated
+ * otherwise.  Return values are RR_OK (0) or a negative RR_E* code; argument
+ * errors are detected on the host before anything is enqueued.
+ *
+ * Parameter-vector rows (npar = 6 + npb doubles, row-major [npv][npar]):
+ *   [t0, P, a, b, e, w, k_0, ..., k_{npb-1}]
+ * t0  time of inferior conjunction (same unit as the times, normally days)
+ * P   orbital period, a  semi-major axis in stellar radii,
+ * b   impact parameter at conjunction, b = a cos(i) (1 - e^2)/(1 + e sin w),
+ * e   eccentricity, w  argument of periastron (radians),
+ * k_pb radius ratio in passband pb (chromatic radius ratios, Sect. 4.2).
+ * The planet transits at true anomaly pi/2 - w and occults only while it is
+ * in front of the star.  A row with a non-finite value, P <= 0, a <= 0,
+ * b < 0, e outside [0, 1), |cos i| > 1 or any k_pb outside the table's
+ * [k0, k1] produces a row of NaN; other rows are unaffected.
+ */
+#ifndef RR_H
+#define RR_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RR_API __attribute__((visibility("default")))
+
+/* Return codes. */
+#define RR_OK        0
+#define RR_EINVAL   -1   /* an argument is out of its documented range     */
+#define RR_ENOMEM   -2   /* a device or host allocation failed             */
+#define RR_EDEVICE  -3   /* a HIP call failed (message via rr_last_error)  */
+#define RR_ELIMIT   -4   /* a size exceeds a compiled-in limit below       */
+#define RR_EBUSY    -5   /* serving: the request does not fit right now    */
+#define RR_ENOTFOUND -6  /* serving: unknown request id                    */
+
+/* Compiled-in limits. */
+#define RR_MAX_PB    16   /* passbands per table set                        */
+#define RR_MAX_LC    64   /* light curves per rr_evaluate call              */
+#define RR_MAX_NSS   1024 /* subsamples per exposure                        */
+
+/* Precision policies for rr_evaluate / rr_loglik_grad. */
+#define RR_FP64  0  /* every step in FP64; output double                  */
+#define RR_MIXED 1  /* FP64 phase reduction, FP32 orbit/area/tables,
+                       output float (see the design notes for the bound)  */
+
+/* Table resolution (Sect. 3.1.1, Sect. 3.1.2, Sect. 3.3).
+ * zcut   radius dividing the inner region (bins of constant dz) from the
+ *        limb region (bins of constant dmu), 0 < zcut < 1;
+ * nzin   bins in the inner region, >= 1;  nzlimb  bins in the limb region,
+ *        >= 1 (nz = nzin + nzlimb <= 4096);
+ * ng     grazing-value nodes g_m = m / (ng - 1), 2 <= ng <= 4096;
+ * nk     radius-ratio nodes k_i = k0 + i (k1 - k0)/(nk - 1), 2 <= nk <= 4096;
+ * k0,k1  radius-ratio range, 0 < k0 < k1 < 1. */
+typedef struct rr_grid {
+    double  zcut;
+    int32_t nzin;
+    int32_t nzlimb;
+    int32_t ng;
+    int32_t nk;
+    double  k0;
+    double  k1;
+} rr_grid;
+
+typedef struct rr_tables rr_tables;   /* opaque, owned by the library */
+
+/* Build the LD tables for npb passbands from radial profiles given as
+ * samples prof[npb][nmu] at mu[nmu] (host arrays, FP64).  mu must be
+ * strictly increasing within [0, 1]; the profile is read as the
+ * piecewise-linear interpolant of the samples, constant beyond the first and
+ * last sample (the custom-profile case of Sect. 3.2.2), and I_star is that
+ * interpolant's exact disk integral (Eq. 2, Eq. 4).
+ * Builds, on the device: the z-grid, the weight table
+ * W[nk][nz][ng] (area of annulus j occluded by a planet of radius k_i at
+ * grazing value g_m over the total occluded area, Sect. 2), the profile at
+ * the bin means, I_star and the LD-weighted tables T[npb][nk][ng] in FP64
+ * and FP32.  Device memory ~ 8 nk nz ng + 12 npb nk ng bytes.
+ * Synchronous: returns when the tables are ready for use on any stream.
+ * 2 <= nmu <= 65536, 1 <= npb <= RR_MAX_PB.  On success *out receives a new
+ * handle; release it with rr_free_tables. */
+RR_API int rr_prepare_ld(const double* mu, const double* prof, int32_t nmu,
+                         int32_t npb, const rr_grid* grid, rr_tables** out);
+
+/* Replace the profile samples of an existing handle (same mu grid, same
+ * npb) with prof_d[npb][nmu], a device array, and rebuild I_star and T on
+ * `stream` without any host synchronisation.  W is reused.  Work enqueued
+ * on other streams that reads the tables must be ordered after this call by
+ * the caller. */
+RR_API int rr_set_profile(rr_tables* t, const double* prof_d,
+                          hipStream_t stream);
+
+/* Fluxes for npv parameter vectors at npt mid-exposure times.
+ * times_d[npt]   device FP64 mid-exposure times;
+ * lcids_d[npt]   device int32 light-curve index of each time, each in
+ *                [0, nlc) (values outside give NaN), or NULL for one light
+ *                curve (then nlc must be 1);
+ * pbids[nlc]     host int32 passband of each light curve, in [0, npb);
+ * nss[nlc]       host int32 subsamples per exposure, 1..RR_MAX_NSS;
+ * exptimes[nlc]  host FP64 exposure time of each light curve, >= 0;
+ *                subsample s of an exposure at t is evaluated at
+ *                t + exptime ((s + 1/2)/nss - 1/2) and the exposure flux is
+ *                the mean over its subsamples (Sect. 4.1);
+ * pv_d[npv][npar] device FP64 parameter rows (layout above),
+ *                npar == 6 + npb of the tables;
+ * precision      RR_FP64 (out_d is double[npv][npt]) or RR_MIXED
+ *                (out_d is float[npv][npt]);
+ * out_d          device output, row-major, times contiguous.
+ * npt >= 0, npv >= 0 (zero sizes enqueue nothing), 1 <= nlc <= RR_MAX_LC.
+ * Temporary device memory (~160 bytes per parameter vector) comes from the
+ * stream-ordered allocator and is released on the stream. */
+RR_API int rr_evaluate(const rr_tables* t, const double* times_d,
+                       const int32_t* lcids_d, int32_t npt,
+                       const int32_t* pbids, const int32_t* nss,
+                       const double* exptimes, int32_t nlc,
+                       const double* pv_d, int32_t npv, int32_t npar,
+                       int32_t precision, void* out_d, hipStream_t stream);
+
+/* Instrumentation: the next rr_evaluate / rr_loglik_grad calls made by the
+ * calling thread record `before` on their stream immediately before
+ * launching their main kernel and `after` immediately after it, so the event
+ * pair brackets that one kernel (the per-parameter-vector setup kernel that
+ * precedes it is outside the pair).  Both events must be created by the
+ * caller on the device of the tables; NULL, NULL turns this off.  Returns
+ * RR_EINVAL if exactly one of them is NULL. */
+RR_API int rr_set_kernel_events(hipEvent_t before, hipEvent_t after);
+
+/* Release a handle (device and host memory).  The caller must make sure no
+ * enqueued work still reads it.  NULL is ignored. */
+RR_API void rr_free_tables(rr_tables* t);
+
+/* Table introspection for tests and tools: copy one table to host memory.
+ * which: 0 ze[nz+1], 1 W[nk][nz][ng], 2 ldp[npb][nz], 3 istar[npb],
+ *        4 T64[npb][nk][ng], 5 T32[npb][nk][ng] (float), 6 zm[nz].
+ * Writes at most `capacity` elements and stores the element count in *count.
+ * Synchronous. */
+RR_API int rr_tables_copy(const rr_tables* t, int32_t which, void* host_dst,
+                          int64_t capacity, int64_t* count);
+
+/* Grid and sizes of a handle: sizes[0..5] = nz, ng, nk, npb, nmu, nzin. */
+RR_API int rr_tables_info(const rr_tables* t, rr_grid* grid, int32_t* sizes);
+
+/* Static description of a return code. */
+RR_API const char* rr_strerror(int code);
+
+/* Text of the most recent RR_EDEVICE / RR_EINVAL condition of the calling
+ * thread (empty if none). */
+RR_API const char* rr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RR_H */

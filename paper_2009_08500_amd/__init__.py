@@ -1,0 +1,13 @@
+"""MI355X-native RoadRunner transit light curves (Parviainen 2020).
+
+The light-curve path runs in hand-written HIP kernels for gfx950 behind the C
+ABI of ``librr.so`` (declared in ``include/rr.h``); this package is the thin
+Python binding over it.  Importing it loads the library and fails loudly if
+the library has not been built.
+"""
+
+from ._lib import (RR_FP64, RR_MIXED, RRError, lib)  # noqa: F401
+from .api import (DEFAULT_GRID, Tables, TimeSeries, evaluate,  # noqa: F401
+                  make_grid)
+
+lib()  # load now: a missing build is an import error, never a fallback

@@ -1,0 +1,176 @@
+"""Python binding of librr.so: argument marshalling only.
+
+PyTorch supplies device memory and streams; every step of the light-curve
+path runs in the library's HIP kernels.  Arrays given as NumPy are copied to
+the current CUDA/HIP device; device tensors of the right dtype and layout are
+passed through without copies.
+"""
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import RR_FP64, RR_MIXED, RRGrid, check
+
+# Default table resolution: z-grid cut, inner and limb bins, g and k nodes,
+# k range (Sect. 3.1.1, Sect. 3.1.2, Sect. 3.3).
+DEFAULT_GRID = dict(zcut=0.8, nzin=60, nzlimb=120, ng=512, nk=256, k0=0.01, k1=0.30)
+
+TABLE_IDS = {"ze": 0, "W": 1, "ldp": 2, "istar": 3, "T64": 4, "T32": 5, "zm": 6}
+
+PRECISIONS = {"fp64": RR_FP64, "mixed": RR_MIXED, RR_FP64: RR_FP64, RR_MIXED: RR_MIXED}
+
+
+def _stream(stream):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev(x, dtype):
+    """A contiguous device tensor of ``dtype`` holding ``x``."""
+    if isinstance(x, torch.Tensor):
+        if x.is_cuda and x.dtype == dtype and x.is_contiguous():
+            return x
+        return x.to(device="cuda", dtype=dtype).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype, device="cuda")
+
+
+def _host(x, dtype, n=None):
+    a = np.ascontiguousarray(np.asarray(x, dtype=dtype))
+    if n is not None:
+        a = np.ascontiguousarray(np.broadcast_to(a, (n,)))
+    return a
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def make_grid(**kw):
+    g = dict(DEFAULT_GRID)
+    g.update(kw)
+    return RRGrid(float(g["zcut"]), int(g["nzin"]), int(g["nzlimb"]), int(g["ng"]),
+                  int(g["nk"]), float(g["k0"]), float(g["k1"]))
+
+
+class Tables:
+    """LD tables on the device (rr_prepare_ld): z-grid, weights, I_star and
+    the LD-weighted tables for ``npb`` radial profiles sampled at ``mu``."""
+
+    def __init__(self, mu, prof, grid=None):
+        L = _lib.lib()
+        mu = _host(mu, np.float64)
+        prof = np.ascontiguousarray(np.atleast_2d(np.asarray(prof, np.float64)))
+        self.npb, self.nmu = prof.shape
+        if mu.size != self.nmu:
+            raise ValueError("prof must have shape (npb, len(mu))")
+        self.grid = make_grid(**(grid or {}))
+        h = ctypes.c_void_p()
+        check(L.rr_prepare_ld(_ptr(mu), _ptr(prof), self.nmu, self.npb,
+                              ctypes.byref(self.grid), ctypes.byref(h)), "rr_prepare_ld")
+        self._h = h
+        self.mu = mu
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("tables already freed")
+        return self._h
+
+    @property
+    def npar(self):
+        return 6 + self.npb
+
+    def set_profile(self, prof_d, stream=None):
+        """Rebuild I_star and T from device profile samples [npb][nmu]."""
+        prof_d = _dev(prof_d, torch.float64)
+        if prof_d.numel() != self.npb * self.nmu:
+            raise ValueError("profile has the wrong size")
+        check(_lib.lib().rr_set_profile(self.handle, ctypes.c_void_p(prof_d.data_ptr()),
+                                        _stream(stream)), "rr_set_profile")
+        return prof_d
+
+    def copy(self, name):
+        """Copy one device table to a NumPy array (synchronous)."""
+        L = _lib.lib()
+        which = TABLE_IDS[name]
+        n = ctypes.c_int64()
+        check(L.rr_tables_copy(self.handle, which, None, 0, ctypes.byref(n)), "rr_tables_copy")
+        out = np.empty(n.value, np.float32 if name == "T32" else np.float64)
+        check(L.rr_tables_copy(self.handle, which, _ptr(out), n.value, ctypes.byref(n)),
+              "rr_tables_copy")
+        sizes = self.sizes()
+        nz, ng, nk, npb = sizes[0], sizes[1], sizes[2], sizes[3]
+        shapes = {"W": (nk, nz, ng), "ldp": (npb, nz), "T64": (npb, nk, ng),
+                  "T32": (npb, nk, ng)}
+        return out.reshape(shapes.get(name, out.shape))
+
+    def sizes(self):
+        arr = (ctypes.c_int32 * 6)()
+        check(_lib.lib().rr_tables_info(self.handle, None, arr), "rr_tables_info")
+        return list(arr)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            _lib.lib().rr_free_tables(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class TimeSeries:
+    """Device-resident description of a (heterogeneous) time series
+    (Sect. 4.2): mid-exposure times, light-curve ids, and per light curve
+    the passband, supersampling factor and exposure time."""
+
+    def __init__(self, times, lcids=None, pbids=None, nss=None, exptimes=None):
+        self.times = _dev(times, torch.float64)
+        self.npt = self.times.numel()
+        if lcids is None:
+            self.lcids = None
+            nlc = 1 if pbids is None else len(np.atleast_1d(pbids))
+        else:
+            self.lcids = _dev(lcids, torch.int32)
+            if pbids is None:
+                nlc = int(self.lcids.max().item()) + 1 if self.npt else 1
+            else:
+                nlc = len(np.atleast_1d(pbids))
+        self.nlc = nlc
+        self.pbids = _host(0 if pbids is None else pbids, np.int32, nlc)
+        self.nss = _host(1 if nss is None else nss, np.int32, nlc)
+        self.exptimes = _host(0.0 if exptimes is None else exptimes, np.float64, nlc)
+
+    def lc_args(self):
+        lc = ctypes.c_void_p(self.lcids.data_ptr()) if self.lcids is not None else None
+        return (lc, self.npt, _ptr(self.pbids), _ptr(self.nss), _ptr(self.exptimes), self.nlc)
+
+
+def evaluate(tables, series, pv, precision="fp64", out=None, stream=None):
+    """Fluxes (npv, npt) for parameter rows ``pv`` (npv, 6 + npb):
+    [t0, P, a, b, e, w, k_0 .. k_{npb-1}] (rr_evaluate).  Returns a device
+    tensor, float64 for "fp64" and float32 for "mixed"."""
+    prec = PRECISIONS[precision]
+    if not isinstance(series, TimeSeries):
+        series = TimeSeries(series)
+    pv = _dev(pv, torch.float64)
+    if pv.dim() == 1:
+        pv = pv.unsqueeze(0)
+    npv, npar = pv.shape
+    dtype = torch.float64 if prec == RR_FP64 else torch.float32
+    if out is None:
+        out = torch.empty((npv, series.npt), dtype=dtype, device=pv.device)
+    elif out.dtype != dtype or not out.is_contiguous() or out.numel() != npv * series.npt:
+        raise ValueError("out has the wrong dtype, layout or size")
+    lc, npt, pb, nss, ex, nlc = series.lc_args()
+    check(_lib.lib().rr_evaluate(tables.handle, ctypes.c_void_p(series.times.data_ptr()),
+                                 lc, npt, pb, nss, ex, nlc,
+                                 ctypes.c_void_p(pv.data_ptr()), npv, npar, prec,
+                                 ctypes.c_void_p(out.data_ptr()), _stream(stream)),
+          "rr_evaluate")
+    return out

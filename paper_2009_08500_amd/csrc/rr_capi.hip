@@ -1,0 +1,301 @@
+// rr_capi.hip -- the C ABI: argument validation, handle lifetime, launches.
+//
+// Every argument check happens on the host before any HIP call, so invalid
+// calls return an error code and enqueue nothing.
+#include <math.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+#include <vector>
+
+#include "rr_internal.h"
+
+namespace rr {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+KernelEvents& kernel_events() {
+    static thread_local KernelEvents ev;
+    return ev;
+}
+
+int hip_fail(hipError_t err, const char* what) {
+    set_error(std::string(what) + ": " + hipGetErrorString(err));
+    return RR_EDEVICE;
+}
+
+static int einval(const char* msg) {
+    set_error(msg);
+    return RR_EINVAL;
+}
+
+static int elimit(const char* msg) {
+    set_error(msg);
+    return RR_ELIMIT;
+}
+
+static int check_grid(const rr_grid* g) {
+    if (!g) return einval("grid is NULL");
+    if (!(g->zcut > 0.0 && g->zcut < 1.0)) return einval("grid.zcut must be in (0, 1)");
+    if (g->nzin < 1 || g->nzlimb < 1) return einval("grid.nzin and grid.nzlimb must be >= 1");
+    if (int64_t(g->nzin) + g->nzlimb > 4096) return einval("grid.nzin + grid.nzlimb must be <= 4096");
+    if (g->ng < 2 || g->ng > 4096) return einval("grid.ng must be in [2, 4096]");
+    if (g->nk < 2 || g->nk > 4096) return einval("grid.nk must be in [2, 4096]");
+    if (!(g->k0 > 0.0 && g->k0 < g->k1 && g->k1 < 1.0))
+        return einval("grid k range must satisfy 0 < k0 < k1 < 1");
+    return RR_OK;
+}
+
+static void free_tables(rr_tables* t) {
+    if (!t) return;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(t->device);
+    void* bufs[] = {t->mu_s, t->prof, t->ze, t->zm, t->ldp, t->istar,
+                    t->W, t->T64, t->T32, t->inv_istar};
+    for (void* b : bufs)
+        if (b) (void)hipFree(b);
+    (void)hipSetDevice(cur);
+    delete t;
+}
+
+// Common checks of rr_evaluate / rr_loglik_grad.
+int check_eval_args(const rr_tables* t, const double* times_d,
+                    const int32_t* lcids_d, int32_t npt, const int32_t* pbids,
+                    const int32_t* nss, const double* exptimes, int32_t nlc,
+                    const double* pv_d, int32_t npv, int32_t npar,
+                    int32_t precision, LcInfo* lc) {
+    if (!t) return einval("tables handle is NULL");
+    if (npt < 0 || npv < 0) return einval("npt and npv must be >= 0");
+    if (precision != RR_FP64 && precision != RR_MIXED)
+        return einval("precision must be RR_FP64 or RR_MIXED");
+    if (npar != 6 + t->npb) return einval("npar must equal 6 + npb of the tables");
+    if (nlc < 1) return einval("nlc must be >= 1");
+    if (nlc > RR_MAX_LC) return elimit("nlc exceeds RR_MAX_LC");
+    if (!lcids_d && nlc != 1) return einval("lcids may be NULL only when nlc == 1");
+    if (!pbids || !nss || !exptimes) return einval("pbids, nss and exptimes are required");
+    lc->nlc = nlc;
+    for (int i = 0; i < nlc; ++i) {
+        if (pbids[i] < 0 || pbids[i] >= t->npb) return einval("pbids entry outside [0, npb)");
+        if (nss[i] < 1) return einval("nss entries must be >= 1");
+        if (nss[i] > RR_MAX_NSS) return elimit("nss entry exceeds RR_MAX_NSS");
+        if (!(exptimes[i] >= 0.0) || !isfinite(exptimes[i]))
+            return einval("exptimes entries must be finite and >= 0");
+        lc->pb[i] = pbids[i];
+        lc->nss[i] = nss[i];
+        lc->exptime[i] = exptimes[i];
+    }
+    for (int i = nlc; i < RR_MAX_LC; ++i) {
+        lc->pb[i] = 0;
+        lc->nss[i] = 1;
+        lc->exptime[i] = 0.0;
+    }
+    if (npt > 0 && npv > 0) {
+        if (!times_d) return einval("times is NULL");
+        if (!pv_d) return einval("pv is NULL");
+    }
+    const size_t elt = precision == RR_FP64 ? sizeof(double) : sizeof(float);
+    if (elt * size_t(t->npb) * t->grid.ng > size_t(kMaxLdsBytes))
+        return elimit("npb * ng LD vectors exceed the 64 KiB LDS budget");
+    const int64_t ntiles = (int64_t(npt) + kTile - 1) / kTile;
+    if (ntiles * npv * kBlock >= (int64_t(1) << 32))
+        return elimit("npv * npt too large for one launch");
+    return RR_OK;
+}
+
+int check_device(const rr_tables* t) {
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (cur != t->device) return einval("tables live on another device than the current one");
+    return RR_OK;
+}
+
+}  // namespace rr
+
+using namespace rr;
+
+extern "C" {
+
+RR_API const char* rr_strerror(int code) {
+    switch (code) {
+        case RR_OK: return "success";
+        case RR_EINVAL: return "invalid argument";
+        case RR_ENOMEM: return "out of memory";
+        case RR_EDEVICE: return "HIP device error";
+        case RR_ELIMIT: return "size exceeds a compiled-in limit";
+        case RR_EBUSY: return "request does not fit the serving budget now";
+        case RR_ENOTFOUND: return "unknown request id";
+        default: return "unknown error code";
+    }
+}
+
+RR_API const char* rr_last_error(void) { return g_last_error.c_str(); }
+
+RR_API int rr_prepare_ld(const double* mu, const double* prof, int32_t nmu,
+                         int32_t npb, const rr_grid* grid, rr_tables** out) {
+    if (!out) return einval("out is NULL");
+    *out = nullptr;
+    int rc = check_grid(grid);
+    if (rc) return rc;
+    if (!mu || !prof) return einval("mu and prof are required");
+    if (nmu < 2 || nmu > 65536) return einval("nmu must be in [2, 65536]");
+    if (npb < 1) return einval("npb must be >= 1");
+    if (npb > RR_MAX_PB) return elimit("npb exceeds RR_MAX_PB");
+    for (int i = 0; i < nmu; ++i) {
+        if (!(mu[i] >= 0.0 && mu[i] <= 1.0)) return einval("mu samples must lie in [0, 1]");
+        if (i && !(mu[i] > mu[i - 1])) return einval("mu samples must be strictly increasing");
+    }
+    for (int64_t i = 0; i < int64_t(npb) * nmu; ++i)
+        if (!isfinite(prof[i])) return einval("profile samples must be finite");
+
+    rr_tables* t = new (std::nothrow) rr_tables();
+    if (!t) return RR_ENOMEM;
+    t->grid = *grid;
+    t->nz = grid->nzin + grid->nzlimb;
+    t->npb = npb;
+    t->nmu = nmu;
+    t->dk = (grid->k1 - grid->k0) / (grid->nk - 1);
+    hipError_t e = hipGetDevice(&t->device);
+    if (e != hipSuccess) { delete t; return hip_fail(e, "hipGetDevice"); }
+
+    const int64_t nz = t->nz, ng = grid->ng, nk = grid->nk;
+    struct { void** p; size_t bytes; } allocs[] = {
+        {(void**)&t->mu_s, sizeof(double) * nmu},
+        {(void**)&t->prof, sizeof(double) * npb * nmu},
+        {(void**)&t->ze, sizeof(double) * (nz + 1)},
+        {(void**)&t->zm, sizeof(double) * nz},
+        {(void**)&t->ldp, sizeof(double) * npb * nz},
+        {(void**)&t->istar, sizeof(double) * npb},
+        {(void**)&t->inv_istar, sizeof(double) * npb},
+        {(void**)&t->W, sizeof(double) * nk * nz * ng},
+        {(void**)&t->T64, sizeof(double) * npb * nk * ng},
+        {(void**)&t->T32, sizeof(float) * npb * nk * ng},
+    };
+    for (auto& a : allocs) {
+        e = hipMalloc(a.p, a.bytes);
+        if (e != hipSuccess) {
+            free_tables(t);
+            set_error(std::string("hipMalloc: ") + hipGetErrorString(e));
+            return e == hipErrorOutOfMemory ? RR_ENOMEM : RR_EDEVICE;
+        }
+    }
+    hipStream_t s = nullptr;
+    e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e != hipSuccess) { free_tables(t); return hip_fail(e, "hipStreamCreate"); }
+    auto fail = [&](hipError_t err, const char* what) {
+        (void)hipStreamSynchronize(s);
+        (void)hipStreamDestroy(s);
+        free_tables(t);
+        return hip_fail(err, what);
+    };
+    e = hipMemcpyAsync(t->mu_s, mu, sizeof(double) * nmu, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return fail(e, "copy mu");
+    e = hipMemcpyAsync(t->prof, prof, sizeof(double) * npb * nmu, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return fail(e, "copy profile");
+    e = launch_prepare_grid_weights(t, s);
+    if (e != hipSuccess) return fail(e, "weight kernels");
+    e = launch_prepare_profile(t, s);
+    if (e != hipSuccess) return fail(e, "profile kernels");
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(e, "table construction");
+    (void)hipStreamDestroy(s);
+    *out = t;
+    return RR_OK;
+}
+
+RR_API int rr_set_profile(rr_tables* t, const double* prof_d, hipStream_t stream) {
+    if (!t) return einval("tables handle is NULL");
+    if (!prof_d) return einval("prof is NULL");
+    int rc = check_device(t);
+    if (rc) return rc;
+    hipError_t e = hipMemcpyAsync(t->prof, prof_d, sizeof(double) * t->npb * t->nmu,
+                                  hipMemcpyDeviceToDevice, stream);
+    if (e != hipSuccess) return hip_fail(e, "copy profile");
+    e = launch_prepare_profile(t, stream);
+    if (e != hipSuccess) return hip_fail(e, "profile kernels");
+    return RR_OK;
+}
+
+RR_API int rr_evaluate(const rr_tables* t, const double* times_d,
+                       const int32_t* lcids_d, int32_t npt,
+                       const int32_t* pbids, const int32_t* nss,
+                       const double* exptimes, int32_t nlc,
+                       const double* pv_d, int32_t npv, int32_t npar,
+                       int32_t precision, void* out_d, hipStream_t stream) {
+    LcInfo lc;
+    int rc = check_eval_args(t, times_d, lcids_d, npt, pbids, nss, exptimes, nlc,
+                             pv_d, npv, npar, precision, &lc);
+    if (rc) return rc;
+    if (npt == 0 || npv == 0) return RR_OK;
+    if (!out_d) return einval("out is NULL");
+    rc = check_device(t);
+    if (rc) return rc;
+    PvConst* pvc = nullptr;
+    hipError_t e = hipMallocAsync((void**)&pvc, sizeof(PvConst) * size_t(npv), stream);
+    if (e != hipSuccess) return e == hipErrorOutOfMemory ? RR_ENOMEM : hip_fail(e, "hipMallocAsync");
+    e = launch_pv_setup(t, pv_d, npv, npar, pvc, stream);
+    if (e == hipSuccess)
+        e = launch_forward(t, times_d, lcids_d, npt, lc, pv_d, npv, npar, pvc,
+                           precision, out_d, stream);
+    hipError_t ef = hipFreeAsync(pvc, stream);
+    if (e != hipSuccess) return hip_fail(e, "forward kernels");
+    if (ef != hipSuccess) return hip_fail(ef, "hipFreeAsync");
+    return RR_OK;
+}
+
+RR_API void rr_free_tables(rr_tables* t) { free_tables(t); }
+
+RR_API int rr_set_kernel_events(hipEvent_t before, hipEvent_t after) {
+    if ((before == nullptr) != (after == nullptr))
+        return einval("rr_set_kernel_events needs both events or neither");
+    kernel_events().before = before;
+    kernel_events().after = after;
+    return RR_OK;
+}
+
+RR_API int rr_tables_copy(const rr_tables* t, int32_t which, void* host_dst,
+                          int64_t capacity, int64_t* count) {
+    if (!t) return einval("tables handle is NULL");
+    const int64_t nz = t->nz, ng = t->grid.ng, nk = t->grid.nk, npb = t->npb;
+    const void* src = nullptr;
+    int64_t n = 0;
+    size_t elt = sizeof(double);
+    switch (which) {
+        case 0: src = t->ze; n = nz + 1; break;
+        case 1: src = t->W; n = nk * nz * ng; break;
+        case 2: src = t->ldp; n = npb * nz; break;
+        case 3: src = t->istar; n = npb; break;
+        case 4: src = t->T64; n = npb * nk * ng; break;
+        case 5: src = t->T32; n = npb * nk * ng; elt = sizeof(float); break;
+        case 6: src = t->zm; n = nz; break;
+        default: return einval("unknown table id");
+    }
+    if (count) *count = n;
+    if (!host_dst) return RR_OK;
+    if (capacity < n) return einval("capacity smaller than the table");
+    int rc = check_device(t);
+    if (rc) return rc;
+    hipError_t e = hipMemcpy(host_dst, src, elt * size_t(n), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "copy table to host");
+    return RR_OK;
+}
+
+RR_API int rr_tables_info(const rr_tables* t, rr_grid* grid, int32_t* sizes) {
+    if (!t) return einval("tables handle is NULL");
+    if (grid) *grid = t->grid;
+    if (sizes) {
+        sizes[0] = t->nz;
+        sizes[1] = t->grid.ng;
+        sizes[2] = t->grid.nk;
+        sizes[3] = t->npb;
+        sizes[4] = t->nmu;
+        sizes[5] = t->grid.nzin;
+    }
+    return RR_OK;
+}
+
+}  // extern "C"

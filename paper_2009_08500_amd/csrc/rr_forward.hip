@@ -1,0 +1,163 @@
+// rr_forward.hip -- population light-curve evaluation (Sect. 2 Eq. 5,
+// Sect. 3.1.1, Sect. 3.1.2, Sect. 4.1, Sect. 4.2).
+//
+// Two kernels per call:
+//
+//   k_pv_setup  one thread per parameter vector: validity, cos i from b,
+//               sin/cos of the eccentric anomaly at conjunction, and the
+//               transit window -- the range of time offsets outside which
+//               the planet is either behind the star or farther than 1 + k
+//               from its centre, so the flux is exactly 1;
+//   k_forward   one workgroup per (parameter vector, tile of 2048 times),
+//               lanes along time so loads of the shared time array and the
+//               stores of out[pv][t] are coalesced.  Pass 1 reduces each
+//               mid-exposure time to an offset from conjunction (FP64) and
+//               writes 1 for exposures entirely outside the window; if any
+//               exposure of the tile overlaps it, the workgroup builds the
+//               k-interpolated LD vectors of its parameter vector in LDS
+//               (Sect. 3.1.2) and pass 2 evaluates those exposures:
+//               per subsample, Kepler orbit -> z -> g-interpolation in LDS
+//               (Sect. 3.1.1) x lens area (Eq. 5) -> mean over subsamples.
+//
+// The kernels are templated on the bulk real type: double (RR_FP64) or float
+// (RR_MIXED: the time reduction stays FP64, the rest is FP32).
+#include "rr_device.h"
+
+namespace rr {
+namespace {
+
+__global__ void k_pv_setup(const double* __restrict__ pv, int32_t npv,
+                           int32_t npar, double k0, double k1,
+                           PvConst* __restrict__ out) {
+    const int ipv = blockIdx.x * blockDim.x + threadIdx.x;
+    if (ipv >= npv) return;
+    out[ipv] = make_pv_const(pv + int64_t(ipv) * npar, npar - 6, k0, k1);
+}
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_forward(
+    const double* __restrict__ times, const int32_t* __restrict__ lcids,
+    int32_t npt, LcInfo lc, const double* __restrict__ pv, int32_t npar,
+    const PvConst* __restrict__ pvc, GridDev g, const R* __restrict__ T,
+    const double* __restrict__ inv_istar, int32_t ntiles, R* __restrict__ out) {
+    extern __shared__ unsigned char smem_raw[];
+    R* ldw = reinterpret_cast<R*>(smem_raw);            // [npb][ng]
+
+    const int ipv = blockIdx.x / ntiles;
+    const int tile = blockIdx.x - ipv * ntiles;
+    const int tid = threadIdx.x;
+    const int t_base = tile * kTile + tid;
+    R* orow = out + int64_t(ipv) * npt;
+    const PvConst p = pvc[ipv];
+
+    if (!(p.flags & kValid)) {
+        for (int j = 0; j < kTimesPerThread; ++j) {
+            const int it = t_base + j * kBlock;
+            if (it < npt) orow[it] = R(NAN);
+        }
+        return;
+    }
+
+    // Pass 1: exposures that cannot overlap the star get F = 1 now.
+    uint32_t todo = 0;
+    for (int j = 0; j < kTimesPerThread; ++j) {
+        const int it = t_base + j * kBlock;
+        if (it >= npt) continue;
+        const int l = lcids ? lcids[it] : 0;
+        if (l < 0 || l >= lc.nlc) { orow[it] = R(NAN); continue; }
+        const double dtc = phase_offset(times[it], p);
+        if (in_window(dtc, p, 0.5 * lc.exptime[l])) todo |= 1u << j;
+        else orow[it] = R(1);
+    }
+    if (!__syncthreads_or(todo != 0)) return;
+
+    // k-interpolated LD-weighted vectors of this parameter vector, one per
+    // passband (Sect. 3.1.2): ldw = (1 - ak) T[ik] + ak T[ik+1].
+    for (int idx = tid; idx < g.npb * g.ng; idx += kBlock) {
+        const int pb = idx / g.ng, m = idx - pb * g.ng;
+        const double u = (pv[int64_t(ipv) * npar + 6 + pb] - g.k0) / g.dk;
+        int ik = int(floor(u));
+        ik = ik < 0 ? 0 : (ik > g.nk - 2 ? g.nk - 2 : ik);
+        const R ak = R(u - ik);
+        const R* t0r = T + (int64_t(pb) * g.nk + ik) * g.ng;
+        ldw[idx] = (R(1) - ak) * t0r[m] + ak * t0r[g.ng + m];
+    }
+    __syncthreads();
+
+    // Pass 2: exposures that may overlap the star.
+    const OrbitR<R> orb(p);
+    const R gscale = R(g.gscale);
+    while (todo) {
+        const int j = __builtin_ctz(todo);
+        todo &= todo - 1;
+        const int it = t_base + j * kBlock;
+        const int l = lcids ? lcids[it] : 0;
+        const int pb = lc.pb[l];
+        const int nss = lc.nss[l];
+        const double ex = lc.exptime[l];
+        const double t = times[it];
+        const R k = R(pv[int64_t(ipv) * npar + 6 + pb]);
+        const R onepk = R(1) + k;
+        const R inv1pk = R(1) / onepk;
+        const R istar_inv = R(inv_istar[pb]);
+        const R* lw = ldw + pb * g.ng;
+        R acc = R(0);
+        for (int s = 0; s < nss; ++s) {
+            const double ts = t + ex * ((s + 0.5) / nss - 0.5);
+            const double dt = phase_offset(ts, p);
+            if (!in_window(dt, p, 0.0)) continue;
+            bool front;
+            const R z = separation<R>(R(dt), orb, &front);
+            if (!front || !(z < onepk)) continue;
+            const R v = z * inv1pk * gscale;
+            int m = int(v);
+            m = m > g.ng - 2 ? g.ng - 2 : m;
+            const R al = v - R(m);
+            const R ip = (R(1) - al) * lw[m] + al * lw[m + 1];
+            acc += ip * lens_area<R>(R(1), k, z) * istar_inv;
+        }
+        orow[it] = R(1) - acc / R(nss);
+    }
+}
+
+inline unsigned nblocks(int64_t n) { return unsigned((n + kBlock - 1) / kBlock); }
+
+}  // namespace
+
+hipError_t launch_pv_setup(const rr_tables* t, const double* pv, int32_t npv,
+                           int32_t npar, PvConst* pvc, hipStream_t s) {
+    hipLaunchKernelGGL(k_pv_setup, dim3(nblocks(npv)), dim3(kBlock), 0, s, pv, npv,
+                       npar, t->grid.k0, t->grid.k1, pvc);
+    return hipGetLastError();
+}
+
+hipError_t launch_forward(const rr_tables* t, const double* times,
+                          const int32_t* lcids, int32_t npt, const LcInfo& lc,
+                          const double* pv, int32_t npv, int32_t npar,
+                          const PvConst* pvc, int32_t precision, void* out,
+                          hipStream_t s) {
+    const GridDev g = grid_dev(t);
+    const int32_t ntiles = (npt + kTile - 1) / kTile;
+    const dim3 grid(unsigned(int64_t(ntiles) * npv));
+    const KernelEvents ev = kernel_events();
+    if (ev.before) {
+        hipError_t e = hipEventRecord(ev.before, s);
+        if (e != hipSuccess) return e;
+    }
+    if (precision == RR_FP64) {
+        const size_t lds = sizeof(double) * size_t(g.npb) * g.ng;
+        hipLaunchKernelGGL(k_forward<double>, grid, dim3(kBlock), lds, s, times, lcids,
+                           npt, lc, pv, npar, pvc, g, t->T64, t->inv_istar, ntiles,
+                           static_cast<double*>(out));
+    } else {
+        const size_t lds = sizeof(float) * size_t(g.npb) * g.ng;
+        hipLaunchKernelGGL(k_forward<float>, grid, dim3(kBlock), lds, s, times, lcids,
+                           npt, lc, pv, npar, pvc, g, t->T32, t->inv_istar, ntiles,
+                           static_cast<float*>(out));
+    }
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && ev.after) e = hipEventRecord(ev.after, s);
+    return e;
+}
+
+}  // namespace rr

@@ -1,0 +1,92 @@
+// rr_internal.h -- structures shared by the translation units of librr.so.
+//
+// Not part of the public ABI.  Device-side layouts are plain structs of
+// FP64/int32 so that host code can fill and launch them.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "rr.h"
+
+namespace rr {
+
+constexpr int kBlock = 256;          // threads per workgroup (4 wave64)
+constexpr int kTimesPerThread = 8;   // times per thread in the forward kernel
+constexpr int kTile = kBlock * kTimesPerThread;
+constexpr int kMaxLdsBytes = 64 * 1024;   // LDS budget for the k-interpolated
+                                          // LD vectors of one workgroup
+
+// Per-parameter-vector orbit constants, computed once per call (FP64).
+struct PvConst {
+    double t0, P, invP, n;        // n = 2 pi / P (mean motion)
+    double a, e, cosw, sinw;
+    double sE, cE, q, rtr;        // sin/cos of E at conjunction, sqrt(1-e^2),
+                                  // star-planet distance at conjunction
+    double cosi, dtlo, dthi, kmax;  // transit window in time offset
+    int32_t flags;                // kValid | kAlways
+    int32_t pad[3];
+};
+constexpr int32_t kValid = 1;     // physical and inside the table's k range
+constexpr int32_t kAlways = 2;    // no usable transit window: evaluate every
+                                  // subsample in full
+
+// Per-light-curve description, passed by value to the kernels.
+struct LcInfo {
+    int32_t nlc;
+    int32_t pb[RR_MAX_LC];
+    int32_t nss[RR_MAX_LC];
+    double exptime[RR_MAX_LC];
+};
+
+// Scalars of the table grid needed on the device.
+struct GridDev {
+    int32_t nz, ng, nk, npb;
+    double k0, dk, inv_dk;        // k_i = k0 + i dk
+    double gscale;                // ng - 1: grazing value -> node coordinate
+};
+
+}  // namespace rr
+
+// Library-owned table handle (opaque in the ABI).
+struct rr_tables {
+    rr_grid grid;
+    int32_t nz, npb, nmu;
+    int device;
+    double dk;
+    // device buffers
+    double* mu_s = nullptr;      // [nmu]
+    double* prof = nullptr;      // [npb][nmu]
+    double* ze = nullptr;        // [nz+1]
+    double* zm = nullptr;        // [nz]
+    double* ldp = nullptr;       // [npb][nz]
+    double* istar = nullptr;     // [npb]
+    double* W = nullptr;         // [nk][nz][ng]
+    double* T64 = nullptr;       // [npb][nk][ng]
+    float* T32 = nullptr;        // [npb][nk][ng]
+    double* inv_istar = nullptr; // [npb]
+};
+
+namespace rr {
+
+void set_error(const std::string& msg);
+// Events bracketing the next main-kernel launch of this thread (or null).
+struct KernelEvents { hipEvent_t before = nullptr, after = nullptr; };
+KernelEvents& kernel_events();
+int hip_fail(hipError_t err, const char* what);
+rr::GridDev grid_dev(const rr_tables* t);
+
+// Kernel launchers (rr_prep.hip, rr_forward.hip).
+hipError_t launch_prepare_grid_weights(rr_tables* t, hipStream_t s);
+hipError_t launch_prepare_profile(rr_tables* t, hipStream_t s);
+hipError_t launch_pv_setup(const rr_tables* t, const double* pv, int32_t npv,
+                           int32_t npar, PvConst* pvc, hipStream_t s);
+hipError_t launch_forward(const rr_tables* t, const double* times,
+                          const int32_t* lcids, int32_t npt, const LcInfo& lc,
+                          const double* pv, int32_t npv, int32_t npar,
+                          const PvConst* pvc, int32_t precision, void* out,
+                          hipStream_t s);
+
+}  // namespace rr

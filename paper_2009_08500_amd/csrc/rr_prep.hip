@@ -1,0 +1,182 @@
+// rr_prep.hip -- table construction on the device (Sect. 2, Sect. 3.1.1,
+// Sect. 3.1.2, Sect. 3.2.2).
+//
+//   k_zgrid     annulus edges ze[nz+1] and means zm[nz]: constant dz on
+//               [0, zcut] and constant dmu on [zcut, 1] (Sect. 3.1.1);
+//   k_weights   W[nk][nz][ng]: area of annulus j occluded by a planet of
+//               radius k_i at separation c = g_m (1 + k_i), over the total
+//               occluded area (Sect. 2); g = 1 gets the zero-overlap limit,
+//               all weight in the limb annulus; g runs fastest so that the
+//               table contraction below reads W coalesced;
+//   k_profile   profile at the bin means, mu_m = sqrt(1 - zm^2): the
+//               piecewise-linear interpolant of the samples (Sect. 3.2.2);
+//   k_istar     I_star = 2 pi int_0^1 mu I(mu) dmu of that interpolant,
+//               exact per segment (Eq. 2, Eq. 4), fixed-order reduction;
+//   k_tables    T[pb][i][m] = sum_j W[i][j][m] ldp[pb][j] (Sect. 3.1.2), in
+//               FP64 and rounded to FP32 for the mixed path.
+#include "rr_device.h"
+
+namespace rr {
+namespace {
+
+__global__ void k_zgrid(int32_t nzin, int32_t nzlimb, double zcut,
+                        double* __restrict__ ze, double* __restrict__ zm) {
+    const int nz = nzin + nzlimb;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j > nz) return;
+    auto edge = [&](int jj) -> double {
+        if (jj < nzin) return jj * (zcut / nzin);
+        if (jj == nzin) return zcut;
+        if (jj == nz) return 1.0;
+        const double mucut = sqrt(1.0 - zcut * zcut);
+        const double mu = mucut + (jj - nzin) * ((0.0 - mucut) / nzlimb);
+        return sqrt(1.0 - mu * mu);
+    };
+    const double e0 = edge(j);
+    ze[j] = e0;
+    if (j < nz) zm[j] = 0.5 * (e0 + edge(j + 1));
+}
+
+__global__ void k_weights(const double* __restrict__ ze, GridDev g,
+                          double* __restrict__ W) {
+    const int64_t total = int64_t(g.nk) * g.nz * g.ng;
+    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= total) return;
+    const int m = int(idx % g.ng);
+    const int64_t r = idx / g.ng;
+    const int j = int(r % g.nz);
+    const int i = int(r / g.nz);
+    const double k = g.k0 + i * g.dk;
+    const double gv = double(m) / double(g.ng - 1);
+    const double c = gv * (1.0 + k);
+    const double tot = lens_area<double>(1.0, k, c);
+    double w;
+    if (tot > 0.0) {
+        const double hi = lens_area<double>(ze[j + 1], k, c);
+        const double lo = lens_area<double>(ze[j], k, c);
+        w = (hi - lo) / tot;
+    } else {
+        w = (j == g.nz - 1) ? 1.0 : 0.0;
+    }
+    W[idx] = w;
+}
+
+__global__ void k_profile(const double* __restrict__ mu_s,
+                          const double* __restrict__ prof, int32_t nmu,
+                          const double* __restrict__ zm, int32_t nz,
+                          int32_t npb, double* __restrict__ ldp) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nz * npb) return;
+    const int pb = idx / nz, j = idx - pb * nz;
+    const double z = zm[j];
+    const double mu = sqrt(1.0 - z * z);
+    const double* f = prof + int64_t(pb) * nmu;
+    double v;
+    if (mu <= mu_s[0]) {
+        v = f[0];
+    } else if (mu >= mu_s[nmu - 1]) {
+        v = f[nmu - 1];
+    } else {
+        int lo = 0, hi = nmu - 1;      // mu_s[lo] <= mu < mu_s[hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (mu_s[mid] <= mu) lo = mid; else hi = mid;
+        }
+        const double slope = (f[lo + 1] - f[lo]) / (mu_s[lo + 1] - mu_s[lo]);
+        v = slope * (mu - mu_s[lo]) + f[lo];
+    }
+    ldp[idx] = v;
+}
+
+// One workgroup per passband; per-thread partial sums over a fixed stride,
+// then a fixed-shape tree in LDS: deterministic.
+__global__ void k_istar(const double* __restrict__ mu_s,
+                        const double* __restrict__ prof, int32_t nmu,
+                        double* __restrict__ istar,
+                        double* __restrict__ inv_istar) {
+    __shared__ double part[kBlock];
+    const int pb = blockIdx.x;
+    const double* f = prof + int64_t(pb) * nmu;
+    double acc = 0.0;
+    for (int s = threadIdx.x; s < nmu - 1; s += blockDim.x) {
+        const double ma = mu_s[s], mb = mu_s[s + 1];
+        acc += (mb - ma) / 6.0 * (f[s] * (2.0 * ma + mb) + f[s + 1] * (ma + 2.0 * mb));
+    }
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double m0 = mu_s[0], m1 = mu_s[nmu - 1];
+        const double tot = part[0] + f[0] * 0.5 * m0 * m0 +
+                           f[nmu - 1] * 0.5 * (1.0 - m1 * m1);
+        const double is = 2.0 * Num<double>::pi * tot;
+        istar[pb] = is;
+        inv_istar[pb] = 1.0 / is;
+    }
+}
+
+__global__ void k_tables(const double* __restrict__ W,
+                         const double* __restrict__ ldp, GridDev g,
+                         double* __restrict__ T64, float* __restrict__ T32) {
+    const int64_t per = int64_t(g.nk) * g.ng;
+    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= per * g.npb) return;
+    const int pb = int(idx / per);
+    const int64_t r = idx - pb * per;
+    const int i = int(r / g.ng), m = int(r - int64_t(i) * g.ng);
+    const double* wrow = W + int64_t(i) * g.nz * g.ng + m;
+    const double* l = ldp + int64_t(pb) * g.nz;
+    double acc = 0.0;
+    for (int j = 0; j < g.nz; ++j) acc += wrow[int64_t(j) * g.ng] * l[j];
+    T64[idx] = acc;
+    T32[idx] = float(acc);
+}
+
+inline unsigned nblocks(int64_t n) { return unsigned((n + kBlock - 1) / kBlock); }
+
+}  // namespace
+
+GridDev grid_dev(const rr_tables* t) {
+    GridDev g;
+    g.nz = t->nz;
+    g.ng = t->grid.ng;
+    g.nk = t->grid.nk;
+    g.npb = t->npb;
+    g.k0 = t->grid.k0;
+    g.dk = t->dk;
+    g.inv_dk = 1.0 / t->dk;
+    g.gscale = double(t->grid.ng - 1);
+    return g;
+}
+
+hipError_t launch_prepare_grid_weights(rr_tables* t, hipStream_t s) {
+    const GridDev g = grid_dev(t);
+    hipLaunchKernelGGL(k_zgrid, dim3(nblocks(t->nz + 1)), dim3(kBlock), 0, s,
+                       t->grid.nzin, t->grid.nzlimb, t->grid.zcut, t->ze, t->zm);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t nw = int64_t(g.nk) * g.nz * g.ng;
+    hipLaunchKernelGGL(k_weights, dim3(nblocks(nw)), dim3(kBlock), 0, s, t->ze, g, t->W);
+    return hipGetLastError();
+}
+
+hipError_t launch_prepare_profile(rr_tables* t, hipStream_t s) {
+    const GridDev g = grid_dev(t);
+    hipLaunchKernelGGL(k_profile, dim3(nblocks(int64_t(t->nz) * t->npb)), dim3(kBlock), 0, s,
+                       t->mu_s, t->prof, t->nmu, t->zm, t->nz, t->npb, t->ldp);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_istar, dim3(t->npb), dim3(kBlock), 0, s, t->mu_s, t->prof,
+                       t->nmu, t->istar, t->inv_istar);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t nt = int64_t(g.npb) * g.nk * g.ng;
+    hipLaunchKernelGGL(k_tables, dim3(nblocks(nt)), dim3(kBlock), 0, s, t->W, t->ldp, g,
+                       t->T64, t->T32);
+    return hipGetLastError();
+}
+
+}  // namespace rr

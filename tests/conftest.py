@@ -16,3 +16,10 @@ def pytest_configure(config):
 @pytest.fixture(scope="session")
 def repo_root():
     return ROOT
+
+# Import torch at collection time so that its first (slow) import on a fresh
+# machine does not count against a test's time limit.
+try:  # noqa: E402
+    import torch  # noqa: F401
+except Exception:  # pragma: no cover
+    pass

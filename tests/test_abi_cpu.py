@@ -1,0 +1,113 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol
+include/rr.h declares, and rejects invalid arguments on the host with the
+documented error codes before touching the device."""
+
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2009_08500_amd", "librr.so")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_2009_08500_amd import build
+        build.build()
+    from paper_2009_08500_amd import _lib
+    return _lib.lib()
+
+
+def declared_symbols():
+    names = []
+    for h in os.listdir(os.path.join(ROOT, "include")):
+        if h.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", h)).read()
+            names += re.findall(r"RR_API\s+[\w\s\*]+?\b(rr_\w+)\s*\(", txt)
+    return sorted(set(names))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_symbols()
+    assert "rr_evaluate" in names and "rr_prepare_ld" in names
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (rr_\w+)", out))
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    for n in names:
+        assert hasattr(lib, n)
+    # nothing beyond the declared ABI leaks out
+    assert exported == set(names), exported - set(names)
+
+
+def test_strerror(lib):
+    from paper_2009_08500_amd import _lib
+    assert _lib.strerror(0) == "success"
+    assert "invalid" in _lib.strerror(_lib.RR_EINVAL)
+    assert "limit" in _lib.strerror(_lib.RR_ELIMIT)
+    assert _lib.strerror(12345) == "unknown error code"
+
+
+def _prepare(lib, mu, prof, grid, npb=None):
+    from paper_2009_08500_amd import _lib
+    mu = np.ascontiguousarray(mu, np.float64)
+    prof = np.ascontiguousarray(np.atleast_2d(prof), np.float64)
+    h = ctypes.c_void_p()
+    g = _lib.RRGrid(*grid)
+    rc = lib.rr_prepare_ld(mu.ctypes.data_as(ctypes.c_void_p), prof.ctypes.data_as(ctypes.c_void_p),
+                           mu.size, prof.shape[0] if npb is None else npb, ctypes.byref(g),
+                           ctypes.byref(h))
+    return rc, h
+
+
+GOOD = (0.7, 10, 10, 32, 8, 0.01, 0.3)
+
+
+@pytest.mark.parametrize("grid", [
+    (0.0, 10, 10, 32, 8, 0.01, 0.3),      # zcut out of range
+    (1.0, 10, 10, 32, 8, 0.01, 0.3),
+    (0.7, 0, 10, 32, 8, 0.01, 0.3),       # no inner bins
+    (0.7, 10, 0, 32, 8, 0.01, 0.3),
+    (0.7, 10, 10, 1, 8, 0.01, 0.3),       # ng < 2
+    (0.7, 10, 10, 32, 1, 0.01, 0.3),      # nk < 2
+    (0.7, 10, 10, 32, 8, 0.3, 0.01),      # k0 > k1
+    (0.7, 10, 10, 32, 8, 0.0, 0.3),
+    (0.7, 10, 10, 32, 8, 0.01, 1.0),
+    (0.7, 3000, 3000, 32, 8, 0.01, 0.3),  # nz > 4096
+])
+def test_prepare_rejects_bad_grid(lib, grid):
+    mu = np.linspace(0, 1, 11)
+    rc, h = _prepare(lib, mu, np.ones(11), grid)
+    assert rc == -1 and not h.value
+
+
+def test_prepare_rejects_bad_profiles(lib):
+    mu = np.linspace(0, 1, 11)
+    assert _prepare(lib, mu[::-1], np.ones(11), GOOD)[0] == -1          # decreasing mu
+    assert _prepare(lib, np.linspace(-0.1, 1, 11), np.ones(11), GOOD)[0] == -1
+    bad = np.ones(11); bad[3] = np.nan
+    assert _prepare(lib, mu, bad, GOOD)[0] == -1
+    assert _prepare(lib, mu[:1], np.ones(1), GOOD)[0] == -1             # nmu < 2
+    assert _prepare(lib, mu, np.ones((17, 11)), GOOD)[0] == -4          # npb > RR_MAX_PB
+    assert _prepare(lib, mu, np.ones(11), GOOD, npb=0)[0] == -1
+
+
+def test_evaluate_rejects_null_handle(lib):
+    one = np.ones(1, np.int32)
+    z = np.zeros(1)
+    rc = lib.rr_evaluate(None, None, None, 0, one.ctypes.data_as(ctypes.c_void_p),
+                         one.ctypes.data_as(ctypes.c_void_p), z.ctypes.data_as(ctypes.c_void_p),
+                         1, None, 0, 7, 0, None, None)
+    assert rc == -1
+    from paper_2009_08500_amd import _lib
+    assert "NULL" in _lib.last_error()
+
+
+def test_package_import_loads_native_library(lib):
+    import paper_2009_08500_amd as p
+    assert p.lib()._name == LIB

@@ -1,0 +1,243 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Tolerances (absolute, in flux):
+* RR_FP64 path: 1e-9 (a logic check; the observed gap is ~1e-14, rounding
+  order only), and exactly 1.0 wherever the oracle has no occultation.
+* RR_MIXED path: 1 ppm (1e-6), the contract for FP32 bulk arithmetic with an
+  FP64 time reduction.
+Tables: 1e-12 (W, T, I_star are FP64 on both sides; the lens area formulas
+differ, so agreement is to rounding, not bitwise).
+"""
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import roadrunner as orr
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-9
+TOL_MIXED = 1e-6
+
+
+@pytest.fixture(scope="module")
+def rr():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2009_08500_amd as rr
+    return rr
+
+
+def both(rr, tab, series, pv):
+    f64 = rr.evaluate(tab, series, pv, "fp64").cpu().numpy()
+    f32 = rr.evaluate(tab, series, pv, "mixed").cpu().numpy().astype(np.float64)
+    return f64, f32
+
+
+def check_parity(ref, f64, f32, tol32=TOL_MIXED):
+    assert f64.shape == ref.shape
+    nan = np.isnan(ref)
+    assert np.array_equal(nan, np.isnan(f64)) and np.array_equal(nan, np.isnan(f32))
+    r, a, b = ref[~nan], f64[~nan], f32[~nan]
+    err64 = np.abs(a - r).max(initial=0.0)
+    err32 = np.abs(b - r).max(initial=0.0)
+    assert err64 <= TOL64, err64
+    assert err32 <= tol32, err32
+    out = r == 1.0
+    assert np.all(a[out] == 1.0)                  # exactly 1 out of transit
+    assert np.all(b[out] == 1.0)
+    return err64, err32
+
+
+def test_tables_match_oracle(rr):
+    w = wl.heterogeneous(npv=1)
+    grid = wl.TEST_GRID
+    tab = rr.Tables(w["mu_s"], w["I_s"], grid)
+    o = orr.Tables(w["mu_s"], w["I_s"], **grid)
+    np.testing.assert_allclose(tab.copy("ze"), o.ze, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(tab.copy("zm"), o.zm, rtol=0, atol=1e-15)
+    W = tab.copy("W")                               # [nk][nz][ng]
+    np.testing.assert_allclose(W.transpose(0, 2, 1), o.W, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(tab.copy("ldp"), o.ldp, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(tab.copy("istar"), o.istar, rtol=1e-14)
+    np.testing.assert_allclose(tab.copy("T64"), o.T, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(tab.copy("T32"), o.T, rtol=1e-7, atol=0)
+
+
+def test_single_light_curve(rr):
+    w = wl.single_light_curve()
+    for grid in (wl.TEST_GRID, wl.DEFAULT_GRID):
+        tab = rr.Tables(w["mu_s"], w["I_s"], grid)
+        ref = orr.evaluate(orr.Tables(w["mu_s"], w["I_s"], **grid), w["times"], w["pv"])
+        f64, f32 = both(rr, tab, rr.TimeSeries(w["times"]), w["pv"])
+        check_parity(ref, f64, f32)
+        assert (f64 < 1).sum() == 316
+
+
+@pytest.mark.parametrize("npt", [1, 7, 2047, 2048, 2049, 5000])
+def test_population_ragged_sizes(rr, npt):
+    """Tiles of 2048 times per workgroup: sizes around the tile edge."""
+    w = wl.population(npv=24, npt=npt)
+    grid = wl.TEST_GRID
+    pv = w["pv"].copy()
+    pv[:, 0] = np.linspace(0.0, 0.02 * max(npt, 1), pv.shape[0])   # transits inside the window
+    tab = rr.Tables(w["mu_s"], w["I_s"], grid)
+    ref = orr.evaluate(orr.Tables(w["mu_s"], w["I_s"], **grid), w["times"], pv)
+    f64, f32 = both(rr, tab, rr.TimeSeries(w["times"]), pv)
+    check_parity(ref, f64, f32)
+
+
+def test_population_full_size(rr):
+    """The population workload at full size (512 x 20000, default grid), the
+    launch configuration the benchmark times; every output is compared."""
+    w = wl.population()
+    grid = wl.DEFAULT_GRID
+    tab = rr.Tables(w["mu_s"], w["I_s"], grid)
+    ref = orr.evaluate(orr.Tables(w["mu_s"], w["I_s"], **grid), w["times"], w["pv"])
+    f64, f32 = both(rr, tab, rr.TimeSeries(w["times"]), w["pv"])
+    e64, e32 = check_parity(ref, f64, f32)
+    print(f"population 512x20000: max|fp64-oracle| {e64:.2e}, max|mixed-oracle| {e32 * 1e6:.3f} ppm,"
+          f" in-transit fraction {np.mean(ref < 1):.4f}")
+
+
+def test_population_bjd_offset(rr):
+    """Times near BJD 2.459e6: the FP64 time reduction keeps the mixed path
+    within 1 ppm."""
+    w = wl.population(npv=64, npt=8000)
+    off = 2459000.0
+    times = w["times"] + off
+    pv = w["pv"].copy()
+    pv[:, 0] += off
+    grid = wl.TEST_GRID
+    tab = rr.Tables(w["mu_s"], w["I_s"], grid)
+    ref = orr.evaluate(orr.Tables(w["mu_s"], w["I_s"], **grid), times, pv)
+    f64, f32 = both(rr, tab, rr.TimeSeries(times), pv)
+    check_parity(ref, f64, f32)
+
+
+def test_heterogeneous_supersampled(rr):
+    """Four passbands, chromatic k, two supersampled 30-min light curves and
+    two 2-min light curves (Sect. 4.2); 6 days, 48 parameter vectors."""
+    w = wl.heterogeneous(npv=48, days=6.0)
+    grid = wl.TEST_GRID
+    tab = rr.Tables(w["mu_s"], w["I_s"], grid)
+    ref = orr.evaluate(orr.Tables(w["mu_s"], w["I_s"], **grid), w["times"], w["pv"],
+                       lcids=w["lcids"], pbids=w["pbids"], nss=w["nss"], exptimes=w["exptimes"])
+    ser = rr.TimeSeries(w["times"], w["lcids"], w["pbids"], w["nss"], w["exptimes"])
+    f64, f32 = both(rr, tab, ser, w["pv"])
+    check_parity(ref, f64, f32)
+
+
+def test_heterogeneous_full_size_sampled(rr):
+    """The heterogeneous workload at full size (256 x 41472, default grid);
+    32 sampled parameter rows are compared with the oracle."""
+    w = wl.heterogeneous()
+    grid = wl.DEFAULT_GRID
+    tab = rr.Tables(w["mu_s"], w["I_s"], grid)
+    ser = rr.TimeSeries(w["times"], w["lcids"], w["pbids"], w["nss"], w["exptimes"])
+    f64, f32 = both(rr, tab, ser, w["pv"])
+    rows = np.random.default_rng(5).choice(w["pv"].shape[0], 32, replace=False)
+    ref = orr.evaluate(orr.Tables(w["mu_s"], w["I_s"], **grid), w["times"], w["pv"][rows],
+                       lcids=w["lcids"], pbids=w["pbids"], nss=w["nss"], exptimes=w["exptimes"])
+    check_parity(ref, f64[rows], f32[rows])
+    assert np.all(f64 <= 1.0) and np.all(f64 > 0.9)
+
+
+def test_orbit_edge_cases(rr):
+    """Circular, grazing, central, boundary radius ratios, high eccentricity,
+    orbits whose transit window covers the whole period, and invalid rows."""
+    grid = wl.TEST_GRID
+    mu = np.linspace(0, 1, 50)
+    I = wl.profile_power2(mu, 0.7, 0.5)
+    t = np.linspace(-1.0, 1.0, 4001)
+    rows = [
+        [0.0, 3.0, 8.0, 0.0, 0.0, 0.0, 0.1],           # central
+        [0.0, 3.0, 8.0, 1.05, 0.0, 0.0, 0.1],          # grazing
+        [0.0, 3.0, 8.0, 1.1, 0.0, 0.0, 0.1],           # exactly touching
+        [0.0, 3.0, 8.0, 1.2, 0.0, 0.0, 0.1],           # miss
+        [0.0, 3.0, 8.0, 0.3, 0.0, 0.0, grid["k0"]],    # k at the table edges
+        [0.0, 3.0, 8.0, 0.3, 0.0, 0.0, grid["k1"]],
+        [0.1, 5.0, 30.0, 0.5, 0.9, 1.0, 0.1],          # high e
+        [0.1, 5.0, 30.0, 0.5, 0.95, 4.0, 0.2],
+        [0.0, 0.5, 1.3, 0.2, 0.0, 0.0, 0.25],          # window covers the whole period
+        [0.0, 0.6, 2.0, 0.1, 0.3, 2.0, 0.2],           # a(1-e) < 1 + k
+        [0.0, 3.0, 8.0, 0.3, 1.0, 0.0, 0.1],           # invalid: e = 1
+        [0.0, 3.0, 8.0, 0.3, 0.0, 0.0, 0.5],           # invalid: k > k1
+        [0.0, -3.0, 8.0, 0.3, 0.0, 0.0, 0.1],          # invalid: P < 0
+        [0.0, 3.0, 0.2, 0.3, 0.0, 0.0, 0.1],           # invalid: |cos i| > 1
+        [np.nan, 3.0, 8.0, 0.3, 0.0, 0.0, 0.1],        # invalid: NaN
+    ]
+    pv = np.array(rows)
+    tab = rr.Tables(mu, I, grid)
+    ref = orr.evaluate(orr.Tables(mu, I, **grid), t, pv)
+    assert np.isnan(ref[10:]).all() and np.isfinite(ref[:10]).all()
+    f64, f32 = both(rr, tab, rr.TimeSeries(t), pv)
+    check_parity(ref, f64, f32)
+    assert f64[3].min() == 1.0 and f64[0].min() < f64[1].min() < 1.0
+
+
+def test_supersampling_long_exposures(rr):
+    grid = wl.TEST_GRID
+    w = wl.population(npv=16, npt=3000)
+    tab = rr.Tables(w["mu_s"], w["I_s"], grid)
+    otab = orr.Tables(w["mu_s"], w["I_s"], **grid)
+    for nss, ex in [(2, 0.01), (30, 0.02), (200, 0.1), (1, 0.5)]:
+        ref = orr.evaluate(otab, w["times"], w["pv"], nss=nss, exptimes=ex)
+        f64, f32 = both(rr, tab, rr.TimeSeries(w["times"], nss=nss, exptimes=ex), w["pv"])
+        check_parity(ref, f64, f32)
+
+
+def test_invalid_light_curve_ids_give_nan(rr):
+    grid = wl.TEST_GRID
+    w = wl.population(npv=4, npt=100)
+    tab = rr.Tables(w["mu_s"], w["I_s"], grid)
+    lcids = np.zeros(100, np.int32)
+    lcids[[3, 50]] = [5, -1]
+    out = rr.evaluate(tab, rr.TimeSeries(w["times"], lcids, [0, 0], [1, 1], [0.0, 0.0]),
+                      w["pv"], "fp64").cpu().numpy()
+    assert np.isnan(out[:, [3, 50]]).all()
+    assert np.isfinite(np.delete(out, [3, 50], axis=1)).all()
+
+
+def test_zero_sizes_and_errors(rr):
+    import torch
+    grid = wl.TEST_GRID
+    w = wl.population(npv=4, npt=100)
+    tab = rr.Tables(w["mu_s"], w["I_s"], grid)
+    out = rr.evaluate(tab, rr.TimeSeries(np.zeros(0)), w["pv"], "fp64")
+    assert out.shape == (4, 0)
+    out = rr.evaluate(tab, rr.TimeSeries(w["times"]), np.zeros((0, 7)), "mixed")
+    assert out.shape == (0, 100)
+    with pytest.raises(rr.RRError) as e:
+        rr.evaluate(tab, rr.TimeSeries(w["times"]), np.zeros((2, 8)), "fp64")   # npar mismatch
+    assert e.value.code == -1
+    with pytest.raises(rr.RRError) as e:
+        rr.evaluate(tab, rr.TimeSeries(w["times"], np.zeros(100, np.int32), np.zeros(65, np.int32)),
+                    w["pv"], "fp64")
+    assert e.value.code == -4
+    with pytest.raises(rr.RRError):
+        rr.evaluate(tab, rr.TimeSeries(w["times"], nss=0), w["pv"], "fp64")
+    torch.cuda.synchronize()
+
+
+def test_set_profile_on_device(rr):
+    import torch
+    grid = wl.TEST_GRID
+    w = wl.population(npv=32, npt=4000)
+    tab = rr.Tables(w["mu_s"], w["I_s"], grid)
+    I2 = wl.profile_quadratic(w["mu_s"], 0.5, 0.1)[None, :]
+    tab.set_profile(torch.tensor(I2, device="cuda"))
+    ref = orr.evaluate(orr.Tables(w["mu_s"], I2, **grid), w["times"], w["pv"])
+    f64, f32 = both(rr, tab, rr.TimeSeries(w["times"]), w["pv"])
+    check_parity(ref, f64, f32)
+
+
+def test_deterministic(rr):
+    w = wl.population(npv=64, npt=6000)
+    tab = rr.Tables(w["mu_s"], w["I_s"], wl.TEST_GRID)
+    s = rr.TimeSeries(w["times"])
+    a = rr.evaluate(tab, s, w["pv"], "mixed").cpu().numpy()
+    b = rr.evaluate(tab, s, w["pv"], "mixed").cpu().numpy()
+    assert np.array_equal(a, b)
