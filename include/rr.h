@@ -143,6 +143,38 @@ RR_API int rr_evaluate(const rr_tables* t, const double* times_d,
                        const double* pv_d, int32_t npv, int32_t npar,
                        int32_t precision, void* out_d, hipStream_t stream);
 
+/* Gaussian log-likelihood of observed fluxes obs_d[npt] under each
+ * parameter vector, and its gradient, with the same time-series and
+ * parameter arguments as rr_evaluate:
+ *   logl_d[ipv] = -1/2 sum_t ((obs_t - F_t)/sigma)^2     (constant dropped)
+ * obs_d     device observed fluxes, double[npt] for RR_FP64 and float[npt]
+ *           for RR_MIXED (the residual itself is always formed in FP64);
+ * sigma     flux uncertainty, finite and > 0;
+ * logl_d    device double[npv], or NULL;
+ * grad_d    device double[npv][npar], or NULL: d logl_d[ipv] / d pv[ipv][*]
+ *           in the row layout (t0, P, a, b, e, w, k_0 ..);
+ * grad_prof_d device double[npb][nmu], or NULL: the gradient of
+ *           sum_ipv wprof[ipv] logl[ipv] with respect to the tables' LD
+ *           profile samples (through the profile interpolation, I_star and
+ *           T = W . ldp);
+ * wprof_d   device double[npv] weights for grad_prof_d, or NULL for ones.
+ * At least one output must be requested.  Invalid rows give NaN in logl
+ * and grad and contribute nothing to grad_prof.  logl and grad are summed
+ * in FP64 in a fixed order (bitwise reproducible); grad_prof accumulates
+ * through FP64 atomics, reproducible to rounding.  The adjoint keeps
+ * npb * ng * (2 sizeof(real) + 8) bytes of tables in LDS, at most 64 KiB
+ * (RR_ELIMIT beyond).  Temporary device memory, ~(160 + 8 (7 + npb) npt /
+ * 2048 + 8 npb ng) bytes per parameter vector, comes from the
+ * stream-ordered allocator. */
+RR_API int rr_loglik_grad(const rr_tables* t, const double* times_d,
+                          const int32_t* lcids_d, int32_t npt,
+                          const int32_t* pbids, const int32_t* nss,
+                          const double* exptimes, int32_t nlc,
+                          const double* pv_d, int32_t npv, int32_t npar,
+                          int32_t precision, const void* obs_d, double sigma,
+                          const double* wprof_d, double* logl_d, double* grad_d,
+                          double* grad_prof_d, hipStream_t stream);
+
 /* Instrumentation: the next rr_evaluate / rr_loglik_grad calls made by the
  * calling thread record `before` on their stream immediately before
  * launching their main kernel and `after` immediately after it, so the event

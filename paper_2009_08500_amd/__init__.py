@@ -7,7 +7,7 @@ the library has not been built.
 """
 
 from ._lib import (RR_FP64, RR_MIXED, RRError, lib)  # noqa: F401
-from .api import (DEFAULT_GRID, Tables, TimeSeries, evaluate,  # noqa: F401
-                  make_grid)
+from .api import (DEFAULT_GRID, RRLogLik, Tables, TimeSeries,  # noqa: F401
+                  evaluate, loglik_grad, make_grid)
 
 lib()  # load now: a missing build is an import error, never a fallback

@@ -78,7 +78,7 @@ def _declare(L):
     if hasattr(L, "rr_loglik_grad"):
         L.rr_loglik_grad.argtypes = [c_void_p, c_void_p, c_void_p, i32, c_void_p, c_void_p,
                                      c_void_p, i32, c_void_p, i32, i32, i32, c_void_p, dbl,
-                                     c_void_p, c_void_p, c_void_p, c_void_p]
+                                     c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
         L.rr_loglik_grad.restype = ctypes.c_int
     _ = dbl
 

@@ -174,3 +174,73 @@ def evaluate(tables, series, pv, precision="fp64", out=None, stream=None):
                                  ctypes.c_void_p(out.data_ptr()), _stream(stream)),
           "rr_evaluate")
     return out
+
+
+def loglik_grad(tables, series, pv, obs, sigma, precision="fp64", grad=True, profile=False,
+                wprof=None, stream=None):
+    """Gaussian log-likelihood of ``obs`` under each parameter row and its
+    gradients (rr_loglik_grad).  Returns (logl[npv], grad[npv, npar] or None,
+    grad_profile[npb, nmu] or None), float64 device tensors; grad_profile is
+    the gradient of sum(wprof * logl) (wprof = ones if None) with respect to
+    the tables' LD profile samples."""
+    prec = PRECISIONS[precision]
+    if not isinstance(series, TimeSeries):
+        series = TimeSeries(series)
+    pv = _dev(pv, torch.float64)
+    if pv.dim() == 1:
+        pv = pv.unsqueeze(0)
+    npv, npar = pv.shape
+    obs = _dev(obs, torch.float64 if prec == RR_FP64 else torch.float32)
+    if obs.numel() != series.npt:
+        raise ValueError("obs must have one value per time")
+    logl = torch.empty(npv, dtype=torch.float64, device=pv.device)
+    g = torch.empty((npv, npar), dtype=torch.float64, device=pv.device) if grad else None
+    gp = (torch.empty((tables.npb, tables.nmu), dtype=torch.float64, device=pv.device)
+          if profile else None)
+    w = _dev(wprof, torch.float64) if wprof is not None else None
+
+    def p(t):
+        return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+    lc, npt, pb, nss, ex, nlc = series.lc_args()
+    check(_lib.lib().rr_loglik_grad(tables.handle, p(series.times), lc, npt, pb, nss, ex, nlc,
+                                    p(pv), npv, npar, prec, p(obs), float(sigma), p(w),
+                                    p(logl), p(g), p(gp), _stream(stream)),
+          "rr_loglik_grad")
+    return logl, g, gp
+
+
+class RRLogLik(torch.autograd.Function):
+    """logL[npv] = rr_loglik_grad(...) as a differentiable function of the
+    parameter rows ``pv`` [npv, npar] and the LD profile samples ``profile``
+    [npb, nmu] (written into ``tables`` on the current stream); backward
+    returns the hand-written adjoint's gradients."""
+
+    @staticmethod
+    def forward(ctx, pv, profile, tables, series, obs, sigma, precision):
+        if profile is not None:
+            tables.set_profile(profile.detach())
+        want_prof = profile is not None and profile.requires_grad
+        logl, g, gp = loglik_grad(tables, series, pv.detach(), obs, sigma, precision,
+                                  grad=True, profile=want_prof)
+        ctx.tables, ctx.series, ctx.sigma, ctx.precision = tables, series, sigma, precision
+        ctx.want_prof = want_prof
+        ctx.save_for_backward(pv.detach(), profile.detach() if profile is not None else None,
+                              obs if isinstance(obs, torch.Tensor) else torch.as_tensor(obs),
+                              g, gp)
+        return logl
+
+    @staticmethod
+    def backward(ctx, gout):
+        pv, profile, obs, g, gp = ctx.saved_tensors
+        gpv = gout[:, None] * g
+        gprof = None
+        if ctx.want_prof:
+            if bool(torch.all(gout == gout[0])):
+                gprof = gp * gout[0]
+            else:
+                ctx.tables.set_profile(profile)
+                _, _, gprof = loglik_grad(ctx.tables, ctx.series, pv, obs, ctx.sigma,
+                                          ctx.precision, grad=False, profile=True,
+                                          wprof=gout.detach())
+        return gpv, gprof, None, None, None, None, None

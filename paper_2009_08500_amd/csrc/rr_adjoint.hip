@@ -1,0 +1,540 @@
+// rr_adjoint.hip -- Gaussian log-likelihood of the population light curves
+// and its hand-written adjoint: gradients with respect to every parameter
+// of each row and to the shared LD profile samples.
+//
+//   logL_pv = -1/2 sum_t ((d_t - F_t)/sigma)^2,   psi_t = (d_t - F_t)/sigma^2
+//   dlogL/dtheta = sum_t psi_t dF_t/dtheta,       F_t = 1 - mean_s delta_s
+//   delta = ip(g, k) a(z, k) / I_star                               (Eq. 5)
+//
+// k_adjoint     one workgroup per (parameter vector, tile of 2048 times),
+//               the forward kernel's layout.  Out-of-window exposures only
+//               add their residual to logL.  For the others the subsample
+//               loop evaluates delta together with d delta/dz and
+//               d delta/dk, and z's derivatives through the transit-centred
+//               Kepler solution (dE/dM = 1/(1 - e cos E),
+//               dE/de = sin E/(1 - e cos E)); the lens area gives
+//               da/dz = -chord and da/dk = 2 k kappa_0.  Per-lane sums are
+//               FP64 and reduced in a fixed order (butterfly within the wave,
+//               then waves in order) to one partial per workgroup.  With the
+//               profile gradient requested, a second subsample loop scatters
+//               psi-weighted lerp weights into the workgroup's LDS copy of
+//               d logL / d ldw and d logL / d I_star, which are added to per
+//               parameter vector buffers.
+//   k_adjoint_reduce   per parameter vector, the workgroup partials in tile
+//               order -> logL and the gradient row.
+//   k_table_grad d logL / d T[pb][i][m] from the per-vector d logL / d ldw
+//               through the k-interpolation weights, vectors in order.
+//   k_ldp_grad   d logL / d ldp = sum_{i,m} W[i][j][m] dT[i][m] (fixed tree).
+//   k_prof_grad  back through the profile interpolation and I_star (both
+//               linear in the samples) to d logL / d I_s.
+#include "rr_device.h"
+
+namespace rr {
+namespace {
+
+constexpr int kNq = 7;   // logL + 6 orbit parameters (k gradients follow)
+
+// Lens area and its partial derivatives for the unit star (R = 1).
+template <typename R>
+__device__ inline R lens_area_grad(R k, R z, R* Az, R* Ak) {
+    using N = Num<R>;
+    if (z >= R(1) + k) { *Az = R(0); *Ak = R(0); return R(0); }
+    if (z <= R(1) - k) { *Az = R(0); *Ak = R(2) * N::pi * k; return N::pi * k * k; }
+    if (z <= k - R(1)) { *Az = R(0); *Ak = R(0); return N::pi; }
+    R a = R(1), b = k, s = z, tmp;
+    if (a < b) { tmp = a; a = b; b = tmp; }
+    if (b < s) { tmp = b; b = s; s = tmp; }
+    if (a < b) { tmp = a; a = b; b = tmp; }
+    R prod = (a + (b + s)) * (s - (a - b)) * (s + (a - b)) * (a + (b - s));
+    prod = prod > R(0) ? prod : R(0);
+    const R area2 = R(0.5) * N::sqrt_(prod);
+    const R h = area2 / z;
+    const R x1 = (z * z + (R(1) - k) * (R(1) + k)) / (R(2) * z);
+    const R x0 = z - x1;
+    const R k1 = N::atan2_(h, x1);
+    const R k0 = N::atan2_(h, x0);
+    *Az = R(-2) * h;
+    *Ak = R(2) * k * k0;
+    return k1 + k * k * k0 - area2;
+}
+
+// Per-vector derivative constants (FP64, from the row and its PvConst).
+struct PvDeriv {
+    double dMtr_de, dMtr_dw, dci_da, dci_db, dci_de, dci_dw, dq_de;
+};
+
+__device__ inline PvDeriv make_pv_deriv(const PvConst& p, double b) {
+    PvDeriv d;
+    const double e = p.e, sw = p.sinw, cw = p.cosw, q = p.q, a = p.a;
+    const double den = 1.0 + e * sw, ome2 = 1.0 - e * e;
+    const double dEtr_dw = -(1.0 - e * p.cE) / q;
+    const double dEtr_de = -cw / (den * q);
+    d.dMtr_dw = (1.0 - e * p.cE) * dEtr_dw;
+    d.dMtr_de = (1.0 - e * p.cE) * dEtr_de - p.sE;
+    d.dci_da = -p.cosi / a;
+    d.dci_db = den / (a * ome2);
+    d.dci_de = b / a * (sw * ome2 + 2.0 * e * den) / (ome2 * ome2);
+    d.dci_dw = b * e * cw / (a * ome2);
+    d.dq_de = -e / q;
+    return d;
+}
+
+template <typename R>
+struct DerivR {
+    R dMtr_de, dMtr_dw, dci_da, dci_db, dci_de, dci_dw, dq_de;
+    __device__ explicit DerivR(const PvDeriv& d)
+        : dMtr_de(R(d.dMtr_de)), dMtr_dw(R(d.dMtr_dw)), dci_da(R(d.dci_da)),
+          dci_db(R(d.dci_db)), dci_de(R(d.dci_de)), dci_dw(R(d.dci_dw)),
+          dq_de(R(d.dq_de)) {}
+};
+
+// Separation and dz/d(t0, P, a, b, e, w) for one subsample.  x = t_s - t0
+// (for dM/dP = -n x / P).  Same transit-centred solve as the forward path.
+template <typename R>
+__device__ inline R separation_grad(R dt, R x, const OrbitR<R>& o,
+                                    const DerivR<R>& dv, R invP, bool* front,
+                                    R dz[6]) {
+    using N = Num<R>;
+    const R dM = o.n * dt;
+    R d = dM;
+    R s2, c2;
+    if (o.e > R(0)) {
+        R lo = dM - R(2) * o.e, hi = dM + R(2) * o.e;
+        d = dM / (R(1) - o.e * o.cE);
+        d = d < lo ? lo : (d > hi ? hi : d);
+        for (int it = 0; it < N::kepler_maxit; ++it) {
+            N::sincos_(R(0.5) * d, &s2, &c2);
+            const R sd = R(2) * s2 * c2;
+            const R cm1 = R(-2) * s2 * s2;
+            const R h = d - o.e * (o.sE * cm1 + o.cE * sd) - dM;
+            if (h < R(0)) lo = d; else hi = d;
+            const R hp = R(1) - o.e * (o.cE * (R(1) + cm1) - o.sE * sd);
+            const R hpp = o.e * (o.sE * (R(1) + cm1) + o.cE * sd);
+            R dn = d - h / (hp - R(0.5) * h * hpp / hp);
+            if (!(dn >= lo && dn <= hi)) dn = R(0.5) * (lo + hi);
+            const R step = dn - d;
+            d = dn;
+            if (N::abs_(step) < N::kepler_stop) break;
+        }
+    }
+    N::sincos_(R(0.5) * d, &s2, &c2);
+    const R sd = R(2) * s2 * c2;
+    const R cm1 = R(-2) * s2 * s2;
+    const R dc = o.cE * cm1 - o.sE * sd;
+    const R ds = o.sE * cm1 + o.cE * sd;
+    const R X = -o.a * (dc * o.cosw - o.q * ds * o.sinw);
+    const R rho = o.rtr + o.a * (dc * o.sinw + o.q * ds * o.cosw);
+    const R Y = -rho * o.cosi;
+    *front = rho > R(0);
+    const R z = N::sqrt_(X * X + Y * Y);
+    // derivatives (absolute cos E, sin E are fine here)
+    const R cE = o.cE + dc, sE = o.sE + ds;
+    const R iE = R(1) / (R(1) - o.e * cE);
+    const R XE = o.a * (sE * o.cosw + o.q * cE * o.sinw);
+    const R rE = o.a * (o.q * cE * o.cosw - sE * o.sinw);
+    const R Xe = o.a * (o.cosw + dv.dq_de * sE * o.sinw);
+    const R re = o.a * (dv.dq_de * sE * o.cosw - o.sinw);
+    const R inva = R(1) / o.a;
+    const R iz = z > R(0) ? R(1) / z : R(0);
+    // dE/dtheta for t0, P, e, w
+    const R dE_t0 = -o.n * iE;
+    const R dE_P = -o.n * (x * invP) * iE;
+    const R dE_e = (dv.dMtr_de + sE) * iE;
+    const R dE_w = dv.dMtr_dw * iE;
+    auto dzdt = [&](R dX, R drho, R dci) {
+        const R dY = -o.cosi * drho - rho * dci;
+        return (X * dX + Y * dY) * iz;
+    };
+    dz[0] = dzdt(XE * dE_t0, rE * dE_t0, R(0));
+    dz[1] = dzdt(XE * dE_P, rE * dE_P, R(0));
+    dz[2] = dzdt(X * inva, rho * inva, dv.dci_da);
+    dz[3] = dzdt(R(0), R(0), dv.dci_db);
+    dz[4] = dzdt(XE * dE_e + Xe, rE * dE_e + re, dv.dci_de);
+    dz[5] = dzdt(XE * dE_w + rho, rE * dE_w - X, dv.dci_dw);
+    return z;
+}
+
+template <typename T>
+__device__ inline T wave_sum(T v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+template <typename R, int NPBT>
+__global__ __launch_bounds__(kBlock) void k_adjoint(
+    const double* __restrict__ times, const int32_t* __restrict__ lcids,
+    int32_t npt, LcInfo lc, const double* __restrict__ pv, int32_t npar,
+    const PvConst* __restrict__ pvc, GridDev g, const R* __restrict__ T,
+    const double* __restrict__ inv_istar, const R* __restrict__ obs,
+    double inv_sig2, int32_t ntiles, int32_t want_grad, int32_t want_prof,
+    const double* __restrict__ wprof, double* __restrict__ partials,
+    double* __restrict__ gldw_pv, double* __restrict__ gist_pv) {
+    extern __shared__ unsigned char smem_raw[];
+    const int npb = g.npb, ng = g.ng;
+    R* ldw = reinterpret_cast<R*>(smem_raw);                    // [npb][ng]
+    R* dTk = ldw + npb * ng;                                    // [npb][ng]
+    double* gw = reinterpret_cast<double*>(                     // [npb][ng]
+        smem_raw + ((2 * sizeof(R) * npb * ng + 7) / 8) * 8);
+    double* gi = gw + npb * ng;                                 // [npb]
+    __shared__ double red[kBlock / 64][kNq + NPBT];
+
+    const int ipv = blockIdx.x / ntiles;
+    const int tile = blockIdx.x - ipv * ntiles;
+    const int tid = threadIdx.x;
+    const int t_base = tile * kTile + tid;
+    const int nq = kNq + npb;
+    double* part = partials + int64_t(blockIdx.x) * nq;
+    const PvConst p = pvc[ipv];
+
+    if (!(p.flags & kValid)) {
+        if (tid < nq) part[tid] = NAN;
+        return;
+    }
+
+    double ll = 0.0;
+    double ga[6] = {0, 0, 0, 0, 0, 0};
+    double gk[NPBT];
+#pragma unroll
+    for (int q = 0; q < NPBT; ++q) gk[q] = 0.0;
+
+    // Pass 1: residuals of exposures that cannot overlap the star.
+    uint32_t todo = 0;
+    for (int j = 0; j < kTimesPerThread; ++j) {
+        const int it = t_base + j * kBlock;
+        if (it >= npt) continue;
+        const int l = lcids ? lcids[it] : 0;
+        if (l < 0 || l >= lc.nlc) { ll = NAN; continue; }
+        const double dtc = phase_offset(times[it], p);
+        if (in_window(dtc, p, 0.5 * lc.exptime[l])) {
+            todo |= 1u << j;
+        } else {
+            const double r = double(obs[it]) - 1.0;
+            ll -= 0.5 * r * r * inv_sig2;
+        }
+    }
+    const bool any = __syncthreads_or(todo != 0);
+
+    if (any) {
+        for (int idx = tid; idx < npb * ng; idx += kBlock) {
+            const int pb = idx / ng, m = idx - pb * ng;
+            const double u = (pv[int64_t(ipv) * npar + 6 + pb] - g.k0) / g.dk;
+            int ik = int(floor(u));
+            ik = ik < 0 ? 0 : (ik > g.nk - 2 ? g.nk - 2 : ik);
+            const R ak = R(u - ik);
+            const R* t0r = T + (int64_t(pb) * g.nk + ik) * ng;
+            ldw[idx] = (R(1) - ak) * t0r[m] + ak * t0r[ng + m];
+            dTk[idx] = (t0r[ng + m] - t0r[m]) * R(g.inv_dk);
+            gw[idx] = 0.0;
+        }
+        if (tid < npb) gi[tid] = 0.0;
+        __syncthreads();
+
+        const OrbitR<R> orb(p);
+        const DerivR<R> dv(make_pv_deriv(p, pv[int64_t(ipv) * npar + 3]));
+        const R gscale = R(g.gscale);
+        const R invP = R(p.invP);
+        const double wrow = wprof ? wprof[ipv] : 1.0;
+        while (todo) {
+            const int j = __builtin_ctz(todo);
+            todo &= todo - 1;
+            const int it = t_base + j * kBlock;
+            const int l = lcids ? lcids[it] : 0;
+            const int pb = lc.pb[l];
+            const int nss = lc.nss[l];
+            const double ex = lc.exptime[l];
+            const double t = times[it];
+            const R k = R(pv[int64_t(ipv) * npar + 6 + pb]);
+            const R onepk = R(1) + k;
+            const R inv1pk = R(1) / onepk;
+            const R istar_inv = R(inv_istar[pb]);
+            const R* lw = ldw + pb * ng;
+            const R* dk_ = dTk + pb * ng;
+            R acc = R(0);
+            R gt[6] = {0, 0, 0, 0, 0, 0};
+            R gkt = R(0);
+            for (int s = 0; s < nss; ++s) {
+                const double ts = t + ex * ((s + 0.5) / nss - 0.5);
+                const double dt = phase_offset(ts, p);
+                if (!in_window(dt, p, 0.0)) continue;
+                bool front;
+                R dz[6];
+                const R z = separation_grad<R>(R(dt), R(ts - p.t0), orb, dv, invP,
+                                               &front, dz);
+                if (!front || !(z < onepk)) continue;
+                const R v = z * inv1pk * gscale;
+                int m = int(v);
+                m = m > ng - 2 ? ng - 2 : m;
+                const R al = v - R(m);
+                const R ip = (R(1) - al) * lw[m] + al * lw[m + 1];
+                R Az, Ak;
+                const R A = lens_area_grad<R>(k, z, &Az, &Ak);
+                acc += ip * A * istar_inv;
+                if (want_grad) {
+                    const R slope = (lw[m + 1] - lw[m]) * gscale;
+                    const R ddz = (slope * inv1pk * A + ip * Az) * istar_inv;
+                    const R ipk = slope * (-z * inv1pk * inv1pk) +
+                                  (R(1) - al) * dk_[m] + al * dk_[m + 1];
+                    gkt += (ipk * A + ip * Ak) * istar_inv;
+#pragma unroll
+                    for (int q = 0; q < 6; ++q) gt[q] += ddz * dz[q];
+                }
+            }
+            // residual in FP64: d - F = (d - 1) + mean delta
+            const double mean_delta = double(acc) / nss;
+            const double r = (double(obs[it]) - 1.0) + mean_delta;
+            ll -= 0.5 * r * r * inv_sig2;
+            const double wgt = -(r * inv_sig2) / nss;       // dlogL / d delta_s
+            if (want_grad) {
+#pragma unroll
+                for (int q = 0; q < 6; ++q) ga[q] += wgt * double(gt[q]);
+#pragma unroll
+                for (int q = 0; q < NPBT; ++q) gk[q] += (q == pb) ? wgt * double(gkt) : 0.0;
+            }
+            if (want_prof) {
+                const double cw = wgt * wrow;
+                for (int s = 0; s < nss; ++s) {
+                    const double ts = t + ex * ((s + 0.5) / nss - 0.5);
+                    const double dt = phase_offset(ts, p);
+                    if (!in_window(dt, p, 0.0)) continue;
+                    bool front;
+                    const R z = separation<R>(R(dt), orb, &front);
+                    if (!front || !(z < onepk)) continue;
+                    const R v = z * inv1pk * gscale;
+                    int m = int(v);
+                    m = m > ng - 2 ? ng - 2 : m;
+                    const double al = double(v - R(m));
+                    const double A = double(lens_area<R>(R(1), k, z)) * double(istar_inv);
+                    const double c = cw * A;
+                    atomicAdd(&gw[pb * ng + m], (1.0 - al) * c);
+                    atomicAdd(&gw[pb * ng + m + 1], al * c);
+                    const double ip = (1.0 - al) * double(lw[m]) + al * double(lw[m + 1]);
+                    atomicAdd(&gi[pb], -cw * ip * A * double(istar_inv));
+                }
+            }
+        }
+        if (want_prof) {
+            __syncthreads();
+            for (int idx = tid; idx < npb * ng; idx += kBlock) {
+                const double v = gw[idx];
+                if (v != 0.0) atomicAdd(&gldw_pv[int64_t(ipv) * npb * ng + idx], v);
+            }
+            if (tid < npb && gi[tid] != 0.0)
+                atomicAdd(&gist_pv[int64_t(ipv) * npb + tid], gi[tid]);
+        }
+    }
+
+    // fixed-order reduction of the per-lane sums
+    const int wave = tid >> 6, lane = tid & 63;
+    double vals[kNq + NPBT];
+    vals[0] = ll;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) vals[1 + q] = ga[q];
+#pragma unroll
+    for (int q = 0; q < NPBT; ++q) vals[kNq + q] = gk[q];
+#pragma unroll
+    for (int q = 0; q < kNq + NPBT; ++q) {
+        const double v = wave_sum(vals[q]);
+        if (lane == 0) red[wave][q] = v;
+    }
+    __syncthreads();
+    if (tid < nq) {
+        double s = 0.0;
+        for (int w = 0; w < kBlock / 64; ++w) s += red[w][tid];
+        part[tid] = s;
+    }
+}
+
+__global__ void k_fill(double* __restrict__ p, int64_t n) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0;
+}
+
+__global__ void k_adjoint_reduce(const double* __restrict__ partials, int32_t npv,
+                                 int32_t ntiles, int32_t npb, double* __restrict__ logl,
+                                 double* __restrict__ grad) {
+    const int nq = kNq + npb;
+    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= int64_t(npv) * nq) return;
+    const int ipv = int(idx / nq), q = int(idx - int64_t(ipv) * nq);
+    double s = 0.0;
+    for (int tl = 0; tl < ntiles; ++tl) s += partials[(int64_t(ipv) * ntiles + tl) * nq + q];
+    if (q == 0) {
+        if (logl) logl[ipv] = s;
+    } else if (grad) {
+        grad[int64_t(ipv) * (6 + npb) + (q - 1)] = s;
+    }
+}
+
+// dlogL/dT[pb][i][m] = sum_pv [(ik == i)(1 - ak) + (ik + 1 == i) ak] dlogL/dldw_pv[pb][m]
+__global__ void k_table_grad(const double* __restrict__ gldw_pv,
+                             const double* __restrict__ pv, int32_t npv, int32_t npar,
+                             const PvConst* __restrict__ pvc, GridDev g,
+                             double* __restrict__ GT) {
+    const int64_t per = int64_t(g.nk) * g.ng;
+    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= per * g.npb) return;
+    const int pb = int(idx / per);
+    const int64_t r = idx - pb * per;
+    const int i = int(r / g.ng), m = int(r - int64_t(i) * g.ng);
+    double s = 0.0;
+    for (int ipv = 0; ipv < npv; ++ipv) {
+        if (!(pvc[ipv].flags & kValid)) continue;
+        const double u = (pv[int64_t(ipv) * npar + 6 + pb] - g.k0) / g.dk;
+        int ik = int(floor(u));
+        ik = ik < 0 ? 0 : (ik > g.nk - 2 ? g.nk - 2 : ik);
+        if (i != ik && i != ik + 1) continue;
+        const double ak = u - ik;
+        const double w = (i == ik) ? 1.0 - ak : ak;
+        s += w * gldw_pv[(int64_t(ipv) * g.npb + pb) * g.ng + m];
+    }
+    GT[idx] = s;
+}
+
+// dlogL/dldp[pb][j] = sum_{i,m} W[i][j][m] dlogL/dT[pb][i][m]; one
+// workgroup per (pb, j), fixed-shape tree.
+__global__ void k_ldp_grad(const double* __restrict__ W, const double* __restrict__ GT,
+                           GridDev g, double* __restrict__ gldp) {
+    __shared__ double part[kBlock];
+    const int pb = blockIdx.x / g.nz, j = blockIdx.x - pb * g.nz;
+    const int64_t per = int64_t(g.nk) * g.ng;
+    double s = 0.0;
+    for (int64_t r = threadIdx.x; r < per; r += kBlock) {
+        const int i = int(r / g.ng), m = int(r - int64_t(i) * g.ng);
+        s += W[(int64_t(i) * g.nz + j) * g.ng + m] * GT[pb * per + r];
+    }
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) gldp[blockIdx.x] = part[0];
+}
+
+// dlogL/dI_s[pb][s]: back through ldp = interp(mu_m; mu_s, I_s) and
+// I_star = 2 pi sum of exact segment integrals (both linear in I_s).
+__global__ void k_prof_grad(const double* __restrict__ gldp, const double* __restrict__ gist_pv,
+                            int32_t npv, const PvConst* __restrict__ pvc,
+                            const double* __restrict__ mu_s, int32_t nmu,
+                            const double* __restrict__ zm, int32_t nz, int32_t npb,
+                            double* __restrict__ out) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= npb * nmu) return;
+    const int pb = idx / nmu, s = idx - pb * nmu;
+    double acc = 0.0;
+    for (int j = 0; j < nz; ++j) {
+        const double z = zm[j];
+        const double mu = sqrt(1.0 - z * z);
+        double w = 0.0;
+        if (mu <= mu_s[0]) {
+            w = (s == 0) ? 1.0 : 0.0;
+        } else if (mu >= mu_s[nmu - 1]) {
+            w = (s == nmu - 1) ? 1.0 : 0.0;
+        } else {
+            int lo = 0, hi = nmu - 1;
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (mu_s[mid] <= mu) lo = mid; else hi = mid;
+            }
+            const double tau = (mu - mu_s[lo]) / (mu_s[lo + 1] - mu_s[lo]);
+            if (s == lo) w = 1.0 - tau;
+            else if (s == lo + 1) w = tau;
+        }
+        if (w != 0.0) acc += w * gldp[pb * nz + j];
+    }
+    // I_star weight of sample s
+    double qs = 0.0;
+    if (s < nmu - 1) {
+        const double ma = mu_s[s], mb = mu_s[s + 1];
+        qs += (mb - ma) / 6.0 * (2.0 * ma + mb);
+    }
+    if (s > 0) {
+        const double ma = mu_s[s - 1], mb = mu_s[s];
+        qs += (mb - ma) / 6.0 * (ma + 2.0 * mb);
+    }
+    if (s == 0) qs += 0.5 * mu_s[0] * mu_s[0];
+    if (s == nmu - 1) qs += 0.5 * (1.0 - mu_s[nmu - 1] * mu_s[nmu - 1]);
+    qs *= 2.0 * Num<double>::pi;
+    double gist = 0.0;
+    for (int ipv = 0; ipv < npv; ++ipv)
+        if (pvc[ipv].flags & kValid) gist += gist_pv[int64_t(ipv) * npb + pb];
+    out[idx] = acc + qs * gist;
+}
+
+inline unsigned nblocks(int64_t n) { return unsigned((n + kBlock - 1) / kBlock); }
+
+template <typename R, int NPBT>
+void launch_adjoint_t(const AdjointArgs& A, size_t lds, hipStream_t s) {
+    hipLaunchKernelGGL((k_adjoint<R, NPBT>), dim3(unsigned(int64_t(A.ntiles) * A.npv)),
+                       dim3(kBlock), lds, s, A.times, A.lcids, A.npt, *A.lc, A.pv, A.npar,
+                       A.pvc, A.g, static_cast<const R*>(A.T), A.inv_istar,
+                       static_cast<const R*>(A.obs), A.inv_sig2, A.ntiles, A.want_grad,
+                       A.want_prof, A.wprof, A.partials, A.gldw_pv, A.gist_pv);
+}
+
+template <typename R>
+void launch_adjoint_r(const AdjointArgs& A, size_t lds, hipStream_t s) {
+    if (A.g.npb <= 1) launch_adjoint_t<R, 1>(A, lds, s);
+    else if (A.g.npb <= 4) launch_adjoint_t<R, 4>(A, lds, s);
+    else launch_adjoint_t<R, 16>(A, lds, s);
+}
+
+}  // namespace
+
+hipError_t launch_fill(double* p, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill, dim3(nblocks(n)), dim3(kBlock), 0, s, p, n);
+    return hipGetLastError();
+}
+
+size_t adjoint_lds_bytes(int32_t precision, int32_t npb, int32_t ng) {
+    const size_t elt = precision == RR_FP64 ? sizeof(double) : sizeof(float);
+    return ((2 * elt * size_t(npb) * ng + 7) / 8) * 8 + sizeof(double) * (size_t(npb) * ng + npb);
+}
+
+hipError_t launch_adjoint(const AdjointArgs& A, int32_t precision, hipStream_t s) {
+    const size_t lds = adjoint_lds_bytes(precision, A.g.npb, A.g.ng);
+    if (A.want_prof) {
+        const int64_t n1 = int64_t(A.npv) * A.g.npb * A.g.ng, n2 = int64_t(A.npv) * A.g.npb;
+        hipLaunchKernelGGL(k_fill, dim3(nblocks(n1)), dim3(kBlock), 0, s, A.gldw_pv, n1);
+        hipLaunchKernelGGL(k_fill, dim3(nblocks(n2)), dim3(kBlock), 0, s, A.gist_pv, n2);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    const KernelEvents ev = kernel_events();
+    if (ev.before) {
+        hipError_t e = hipEventRecord(ev.before, s);
+        if (e != hipSuccess) return e;
+    }
+    if (precision == RR_FP64) launch_adjoint_r<double>(A, lds, s);
+    else launch_adjoint_r<float>(A, lds, s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (ev.after) {
+        e = hipEventRecord(ev.after, s);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_adjoint_reduce, dim3(nblocks(int64_t(A.npv) * (kNq + A.g.npb))),
+                       dim3(kBlock), 0, s, A.partials, A.npv, A.ntiles, A.g.npb, A.logl,
+                       A.grad);
+    return hipGetLastError();
+}
+
+hipError_t launch_profile_grad(const rr_tables* t, const AdjointArgs& A, double* GT,
+                               double* gldp, double* out, hipStream_t s) {
+    const GridDev g = A.g;
+    const int64_t nt = int64_t(g.npb) * g.nk * g.ng;
+    hipLaunchKernelGGL(k_table_grad, dim3(nblocks(nt)), dim3(kBlock), 0, s, A.gldw_pv, A.pv,
+                       A.npv, A.npar, A.pvc, g, GT);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_ldp_grad, dim3(unsigned(g.npb * g.nz)), dim3(kBlock), 0, s, t->W, GT, g,
+                       gldp);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_prof_grad, dim3(nblocks(int64_t(g.npb) * t->nmu)), dim3(kBlock), 0, s,
+                       gldp, A.gist_pv, A.npv, A.pvc, t->mu_s, t->nmu, t->zm, t->nz, g.npb, out);
+    return hipGetLastError();
+}
+
+}  // namespace rr

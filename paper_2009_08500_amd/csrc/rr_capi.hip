@@ -247,6 +247,70 @@ RR_API int rr_evaluate(const rr_tables* t, const double* times_d,
     return RR_OK;
 }
 
+RR_API int rr_loglik_grad(const rr_tables* t, const double* times_d,
+                          const int32_t* lcids_d, int32_t npt,
+                          const int32_t* pbids, const int32_t* nss,
+                          const double* exptimes, int32_t nlc,
+                          const double* pv_d, int32_t npv, int32_t npar,
+                          int32_t precision, const void* obs_d, double sigma,
+                          const double* wprof_d, double* logl_d, double* grad_d,
+                          double* grad_prof_d, hipStream_t stream) {
+    LcInfo lc;
+    int rc = check_eval_args(t, times_d, lcids_d, npt, pbids, nss, exptimes, nlc,
+                             pv_d, npv, npar, precision, &lc);
+    if (rc) return rc;
+    if (!(sigma > 0.0) || !isfinite(sigma)) return einval("sigma must be finite and > 0");
+    if (npt > 0 && npv > 0 && !obs_d) return einval("obs is NULL");
+    if (npv > 0 && !logl_d && !grad_d && !grad_prof_d) return einval("no output requested");
+    if (adjoint_lds_bytes(precision, t->npb, t->grid.ng) > size_t(kMaxLdsBytes))
+        return elimit("npb * ng adjoint LDS tables exceed the 64 KiB budget");
+    rc = check_device(t);
+    if (rc) return rc;
+    hipError_t e;
+    if (npv == 0) {
+        if (grad_prof_d) {
+            e = launch_fill(grad_prof_d, int64_t(t->npb) * t->nmu, stream);
+            if (e != hipSuccess) return hip_fail(e, "fill");
+        }
+        return RR_OK;
+    }
+    const int32_t ntiles = npt > 0 ? (npt + kTile - 1) / kTile : 1;
+    const int32_t nq = 7 + t->npb;
+    const bool prof = grad_prof_d != nullptr;
+    const GridDev g = grid_dev(t);
+    // one stream-ordered allocation for every temporary
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off += (bytes + 255) / 256 * 256; return o; };
+    const size_t o_pvc = take(sizeof(PvConst) * size_t(npv));
+    const size_t o_part = take(sizeof(double) * size_t(npv) * ntiles * nq);
+    const size_t o_gldw = prof ? take(sizeof(double) * size_t(npv) * t->npb * g.ng) : 0;
+    const size_t o_gist = prof ? take(sizeof(double) * size_t(npv) * t->npb) : 0;
+    const size_t o_gt = prof ? take(sizeof(double) * size_t(t->npb) * g.nk * g.ng) : 0;
+    const size_t o_gldp = prof ? take(sizeof(double) * size_t(t->npb) * t->nz) : 0;
+    char* base = nullptr;
+    e = hipMallocAsync((void**)&base, off, stream);
+    if (e != hipSuccess) return e == hipErrorOutOfMemory ? RR_ENOMEM : hip_fail(e, "hipMallocAsync");
+    AdjointArgs A;
+    A.times = times_d; A.lcids = lcids_d; A.npt = npt; A.lc = &lc; A.pv = pv_d;
+    A.npv = npv; A.npar = npar; A.pvc = reinterpret_cast<PvConst*>(base + o_pvc); A.g = g;
+    A.T = precision == RR_FP64 ? static_cast<const void*>(t->T64) : static_cast<const void*>(t->T32);
+    A.inv_istar = t->inv_istar; A.obs = obs_d; A.inv_sig2 = 1.0 / (sigma * sigma);
+    A.ntiles = ntiles; A.want_grad = grad_d != nullptr; A.want_prof = prof; A.wprof = wprof_d;
+    A.partials = reinterpret_cast<double*>(base + o_part);
+    A.gldw_pv = prof ? reinterpret_cast<double*>(base + o_gldw) : nullptr;
+    A.gist_pv = prof ? reinterpret_cast<double*>(base + o_gist) : nullptr;
+    A.logl = logl_d; A.grad = grad_d;
+    e = launch_pv_setup(t, pv_d, npv, npar, const_cast<PvConst*>(A.pvc), stream);
+    if (e == hipSuccess) e = launch_adjoint(A, precision, stream);
+    if (e == hipSuccess && prof)
+        e = launch_profile_grad(t, A, reinterpret_cast<double*>(base + o_gt),
+                                reinterpret_cast<double*>(base + o_gldp), grad_prof_d, stream);
+    hipError_t ef = hipFreeAsync(base, stream);
+    if (e != hipSuccess) return hip_fail(e, "log-likelihood kernels");
+    if (ef != hipSuccess) return hip_fail(ef, "hipFreeAsync");
+    return RR_OK;
+}
+
 RR_API void rr_free_tables(rr_tables* t) { free_tables(t); }
 
 RR_API int rr_set_kernel_events(hipEvent_t before, hipEvent_t after) {

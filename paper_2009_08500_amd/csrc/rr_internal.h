@@ -48,6 +48,29 @@ struct GridDev {
     double gscale;                // ng - 1: grazing value -> node coordinate
 };
 
+// Arguments of the adjoint launch (rr_adjoint.hip).
+struct AdjointArgs {
+    const double* times;
+    const int32_t* lcids;
+    int32_t npt;
+    const LcInfo* lc;
+    const double* pv;
+    int32_t npv, npar;
+    const PvConst* pvc;
+    GridDev g;
+    const void* T;            // T64 or T32 by precision
+    const double* inv_istar;
+    const void* obs;          // double (RR_FP64) or float (RR_MIXED)
+    double inv_sig2;
+    int32_t ntiles, want_grad, want_prof;
+    const double* wprof;      // per-vector weights of the profile gradient
+    double* partials;         // [npv * ntiles][7 + npb]
+    double* gldw_pv;          // [npv][npb][ng]
+    double* gist_pv;          // [npv][npb]
+    double* logl;             // [npv] or null
+    double* grad;             // [npv][npar] or null
+};
+
 }  // namespace rr
 
 // Library-owned table handle (opaque in the ABI).
@@ -83,6 +106,11 @@ hipError_t launch_prepare_grid_weights(rr_tables* t, hipStream_t s);
 hipError_t launch_prepare_profile(rr_tables* t, hipStream_t s);
 hipError_t launch_pv_setup(const rr_tables* t, const double* pv, int32_t npv,
                            int32_t npar, PvConst* pvc, hipStream_t s);
+size_t adjoint_lds_bytes(int32_t precision, int32_t npb, int32_t ng);
+hipError_t launch_adjoint(const AdjointArgs& a, int32_t precision, hipStream_t s);
+hipError_t launch_profile_grad(const rr_tables* t, const AdjointArgs& a, double* GT,
+                               double* gldp, double* out, hipStream_t s);
+hipError_t launch_fill(double* p, int64_t n, hipStream_t s);
 hipError_t launch_forward(const rr_tables* t, const double* times,
                           const int32_t* lcids, int32_t npt, const LcInfo& lc,
                           const double* pv, int32_t npv, int32_t npar,
