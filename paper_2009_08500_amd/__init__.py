@@ -10,4 +10,6 @@ from ._lib import (RR_FP64, RR_MIXED, RRError, lib)  # noqa: F401
 from .api import (DEFAULT_GRID, RRLogLik, Tables, TimeSeries,  # noqa: F401
                   evaluate, loglik_grad, make_grid)
 
+from .serving import Server  # noqa: F401,E402
+
 lib()  # load now: a missing build is an import error, never a fallback

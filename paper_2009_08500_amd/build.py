@@ -18,7 +18,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "librr.so")
 
-SOURCES = ["rr_capi.hip", "rr_prep.hip", "rr_forward.hip", "rr_adjoint.hip"]
+SOURCES = ["rr_capi.hip", "rr_prep.hip", "rr_forward.hip", "rr_adjoint.hip", "rr_serve.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

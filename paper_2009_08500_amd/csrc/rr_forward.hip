@@ -34,21 +34,20 @@ __global__ void k_pv_setup(const double* __restrict__ pv, int32_t npv,
     out[ipv] = make_pv_const(pv + int64_t(ipv) * npar, npar - 6, k0, k1);
 }
 
+// The work of one workgroup: population row ipv, time tile `tile`.
 template <typename R>
-__global__ __launch_bounds__(kBlock) void k_forward(
-    const double* __restrict__ times, const int32_t* __restrict__ lcids,
-    int32_t npt, LcInfo lc, const double* __restrict__ pv, int32_t npar,
-    const PvConst* __restrict__ pvc, GridDev g, const R* __restrict__ T,
-    const double* __restrict__ inv_istar, int32_t ntiles, R* __restrict__ out) {
-    extern __shared__ unsigned char smem_raw[];
-    R* ldw = reinterpret_cast<R*>(smem_raw);            // [npb][ng]
-
-    const int ipv = blockIdx.x / ntiles;
-    const int tile = blockIdx.x - ipv * ntiles;
+__device__ inline void forward_block(const FwdJob& job, const LcInfo& lc, int ipv,
+                                     int tile, const GridDev& g,
+                                     const R* __restrict__ T,
+                                     const double* __restrict__ inv_istar, R* ldw) {
     const int tid = threadIdx.x;
+    const int npt = job.npt, npar = job.npar;
+    const double* __restrict__ times = job.times;
+    const int32_t* __restrict__ lcids = job.lcids;
+    const double* __restrict__ pv = job.pv;
     const int t_base = tile * kTile + tid;
-    R* orow = out + int64_t(ipv) * npt;
-    const PvConst p = pvc[ipv];
+    R* orow = static_cast<R*>(job.out) + int64_t(ipv) * npt;
+    const PvConst p = job.pvc[ipv];
 
     if (!(p.flags & kValid)) {
         for (int j = 0; j < kTimesPerThread; ++j) {
@@ -120,6 +119,46 @@ __global__ __launch_bounds__(kBlock) void k_forward(
     }
 }
 
+// One population (rr_evaluate): workgroup b -> row b / ntiles, tile b % ntiles.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_forward(FwdJob job, LcInfo lc, GridDev g,
+                                                    const R* __restrict__ T,
+                                                    const double* __restrict__ inv_istar) {
+    extern __shared__ unsigned char smem_raw[];
+    const int ipv = blockIdx.x / job.ntiles;
+    const int tile = blockIdx.x - ipv * job.ntiles;
+    forward_block<R>(job, lc, ipv, tile, g, T, inv_istar, reinterpret_cast<R*>(smem_raw));
+}
+
+// Grouped launch (serving): workgroup b belongs to the last job whose
+// block0 <= b; jobs come from several requests and time series.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_forward_jobs(JobTable jt, GridDev g,
+                                                         const R* __restrict__ T,
+                                                         const double* __restrict__ inv_istar) {
+    extern __shared__ unsigned char smem_raw[];
+    const int b = blockIdx.x;
+    int jj = 0;
+    for (int q = 1; q < jt.njobs; ++q)
+        if (jt.j[q].block0 <= b) jj = q;
+    const FwdJob& job = jt.j[jj];
+    const int local = b - job.block0;
+    const int ipv = job.pv0 + local / job.ntiles;
+    const int tile = local - (local / job.ntiles) * job.ntiles;
+    forward_block<R>(job, *job.lc, ipv, tile, g, T, inv_istar, reinterpret_cast<R*>(smem_raw));
+}
+
+__global__ void k_pv_setup_jobs(SetupTable st, double k0, double k1) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    int jj = 0;
+    for (int q = 1; q < st.njobs; ++q)
+        if (st.j[q].thread0 <= t) jj = q;
+    const SetupJob& sj = st.j[jj];
+    const int ipv = t - sj.thread0;
+    if (ipv < 0 || ipv >= sj.npv) return;
+    sj.pvc[ipv] = make_pv_const(sj.pv + int64_t(ipv) * sj.npar, sj.npar - 6, k0, k1);
+}
+
 inline unsigned nblocks(int64_t n) { return unsigned((n + kBlock - 1) / kBlock); }
 
 }  // namespace
@@ -137,8 +176,11 @@ hipError_t launch_forward(const rr_tables* t, const double* times,
                           const PvConst* pvc, int32_t precision, void* out,
                           hipStream_t s) {
     const GridDev g = grid_dev(t);
-    const int32_t ntiles = (npt + kTile - 1) / kTile;
-    const dim3 grid(unsigned(int64_t(ntiles) * npv));
+    FwdJob job;
+    job.times = times; job.lcids = lcids; job.lc = nullptr; job.pv = pv; job.pvc = pvc;
+    job.out = out; job.npt = npt; job.npar = npar; job.pv0 = 0; job.npv = npv;
+    job.ntiles = (npt + kTile - 1) / kTile; job.block0 = 0;
+    const dim3 grid(unsigned(int64_t(job.ntiles) * npv));
     const KernelEvents ev = kernel_events();
     if (ev.before) {
         hipError_t e = hipEventRecord(ev.before, s);
@@ -146,18 +188,40 @@ hipError_t launch_forward(const rr_tables* t, const double* times,
     }
     if (precision == RR_FP64) {
         const size_t lds = sizeof(double) * size_t(g.npb) * g.ng;
-        hipLaunchKernelGGL(k_forward<double>, grid, dim3(kBlock), lds, s, times, lcids,
-                           npt, lc, pv, npar, pvc, g, t->T64, t->inv_istar, ntiles,
-                           static_cast<double*>(out));
+        hipLaunchKernelGGL(k_forward<double>, grid, dim3(kBlock), lds, s, job, lc, g, t->T64,
+                           t->inv_istar);
     } else {
         const size_t lds = sizeof(float) * size_t(g.npb) * g.ng;
-        hipLaunchKernelGGL(k_forward<float>, grid, dim3(kBlock), lds, s, times, lcids,
-                           npt, lc, pv, npar, pvc, g, t->T32, t->inv_istar, ntiles,
-                           static_cast<float*>(out));
+        hipLaunchKernelGGL(k_forward<float>, grid, dim3(kBlock), lds, s, job, lc, g, t->T32,
+                           t->inv_istar);
     }
     hipError_t e = hipGetLastError();
     if (e == hipSuccess && ev.after) e = hipEventRecord(ev.after, s);
     return e;
+}
+
+hipError_t launch_forward_jobs(const rr_tables* t, const JobTable& jt, int32_t nblocks_total,
+                               int32_t precision, hipStream_t s) {
+    if (nblocks_total <= 0 || jt.njobs <= 0) return hipSuccess;
+    const GridDev g = grid_dev(t);
+    if (precision == RR_FP64) {
+        const size_t lds = sizeof(double) * size_t(g.npb) * g.ng;
+        hipLaunchKernelGGL(k_forward_jobs<double>, dim3(unsigned(nblocks_total)), dim3(kBlock),
+                           lds, s, jt, g, t->T64, t->inv_istar);
+    } else {
+        const size_t lds = sizeof(float) * size_t(g.npb) * g.ng;
+        hipLaunchKernelGGL(k_forward_jobs<float>, dim3(unsigned(nblocks_total)), dim3(kBlock),
+                           lds, s, jt, g, t->T32, t->inv_istar);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_pv_setup_jobs(const rr_tables* t, const SetupTable& st, int32_t nthreads,
+                                hipStream_t s) {
+    if (nthreads <= 0 || st.njobs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pv_setup_jobs, dim3(nblocks(nthreads)), dim3(kBlock), 0, s, st,
+                       t->grid.k0, t->grid.k1);
+    return hipGetLastError();
 }
 
 }  // namespace rr

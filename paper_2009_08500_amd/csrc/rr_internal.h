@@ -41,6 +41,33 @@ struct LcInfo {
     double exptime[RR_MAX_LC];
 };
 
+// One forward job: rows [pv0, pv0 + npv) of a population over one time
+// series, workgroups [block0, block0 + npv * ntiles) of a launch.  pv, pvc
+// and out are indexed by the population row; out is [rows][npt].
+struct FwdJob {
+    const double* times;
+    const int32_t* lcids;
+    const LcInfo* lc;          // device copy (serving); unused by rr_evaluate
+    const double* pv;
+    const PvConst* pvc;
+    void* out;
+    int32_t npt, npar, pv0, npv, ntiles, block0;
+};
+constexpr int kMaxJobs = 24;   // jobs per grouped launch (kernel arguments)
+struct JobTable {
+    int32_t njobs;
+    FwdJob j[kMaxJobs];
+};
+struct SetupJob {
+    const double* pv;
+    PvConst* pvc;
+    int32_t npv, npar, thread0, pad;
+};
+struct SetupTable {
+    int32_t njobs;
+    SetupJob j[kMaxJobs];
+};
+
 // Scalars of the table grid needed on the device.
 struct GridDev {
     int32_t nz, ng, nk, npb;
@@ -111,6 +138,10 @@ hipError_t launch_adjoint(const AdjointArgs& a, int32_t precision, hipStream_t s
 hipError_t launch_profile_grad(const rr_tables* t, const AdjointArgs& a, double* GT,
                                double* gldp, double* out, hipStream_t s);
 hipError_t launch_fill(double* p, int64_t n, hipStream_t s);
+hipError_t launch_forward_jobs(const rr_tables* t, const JobTable& jt,
+                               int32_t nblocks_total, int32_t precision, hipStream_t s);
+hipError_t launch_pv_setup_jobs(const rr_tables* t, const SetupTable& st,
+                                int32_t nthreads, hipStream_t s);
 hipError_t launch_forward(const rr_tables* t, const double* times,
                           const int32_t* lcids, int32_t npt, const LcInfo& lc,
                           const double* pv, int32_t npv, int32_t npar,

@@ -111,3 +111,14 @@ def test_evaluate_rejects_null_handle(lib):
 def test_package_import_loads_native_library(lib):
     import paper_2009_08500_amd as p
     assert p.lib()._name == LIB
+
+
+def test_server_rejects_bad_arguments_on_host(lib):
+    from paper_2009_08500_amd import serving
+    serving._declare(lib)
+    h = ctypes.c_void_p()
+    assert lib.rr_server_create(None, 1 << 30, 64, ctypes.byref(h)) == -1
+    assert not h.value
+    assert lib.rr_server_submit(None, 0, None, 1, 7, 0, None, None) == -1
+    assert lib.rr_server_poll(None, 1, None, None) == -1
+    lib.rr_server_destroy(None)

@@ -1,0 +1,104 @@
+"""The continuous-batching server on the GPU: results are the same alone and
+in a mix (the same kernel code as rr_evaluate, independent of batching),
+match the oracle, and the arena admits requests as memory frees up."""
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import roadrunner as orr
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2009_08500_amd as rr
+    het = wl.heterogeneous(npv=1)
+    grid = wl.TEST_GRID
+    tab = rr.Tables(het["mu_s"], het["I_s"], grid)
+    otab = orr.Tables(het["mu_s"], het["I_s"], **grid)
+    series, reqs = wl.serving_mix(40, nseries=6, max_npv=256, max_npt=20000, seed_extra=1)
+    return rr, tab, otab, series, reqs
+
+
+def evaluate_direct(rr, tab, se, pv, prec):
+    ser = rr.TimeSeries(se["times"], se["lcids"], se["pbids"], se["nss"], se["exptimes"])
+    return rr.evaluate(tab, ser, pv, prec).cpu().numpy()
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_alone_equals_in_mix(env, prec):
+    rr, tab, otab, series, reqs = env
+    srv = rr.Server(tab, budget_bytes=1 << 30, max_tick_blocks=512)
+    sids = [srv.add_series(s["times"], s["lcids"], s["pbids"], s["nss"], s["exptimes"])
+            for s in series]
+    probe = reqs[0]
+    a = srv.submit(sids[probe["series"]], probe["pv"], prec)
+    alone = srv.wait(a).numpy().copy()
+    handles = []
+    for i, r in enumerate(reqs):
+        handles.append(srv.submit(sids[r["series"]], r["pv"], prec))
+        if i == len(reqs) // 2:
+            mid = srv.submit(sids[probe["series"]], probe["pv"], prec)
+    outs = [srv.wait(h).numpy().copy() for h in handles]
+    in_mix = srv.wait(mid).numpy()
+    assert np.abs(in_mix.astype(np.float64) - alone).max() <= 1e-6
+    assert np.array_equal(in_mix, alone)          # bitwise: batching changes nothing
+    for r, o in zip(reqs, outs):
+        direct = evaluate_direct(rr, tab, series[r["series"]], r["pv"], prec)
+        assert np.array_equal(o, direct)
+    st = srv.stats()
+    assert st["completed"] == len(reqs) + 2 and st["last_error"] == 0
+    lat = np.array([h.latency for h in handles])
+    assert np.all(lat > 0)
+    print(f"serving {prec}: {len(reqs)} requests, {st['ticks']} ticks, "
+          f"p50 {np.percentile(lat, 50) * 1e3:.2f} ms p99 {np.percentile(lat, 99) * 1e3:.2f} ms")
+    srv.close()
+
+
+def test_served_results_match_oracle(env):
+    rr, tab, otab, series, reqs = env
+    srv = rr.Server(tab, budget_bytes=1 << 30)
+    sids = [srv.add_series(s["times"], s["lcids"], s["pbids"], s["nss"], s["exptimes"])
+            for s in series]
+    for r in reqs[:4]:
+        se = series[r["series"]]
+        pv = r["pv"][:3]
+        h64 = srv.submit(sids[r["series"]], pv, "fp64")
+        h32 = srv.submit(sids[r["series"]], pv, "mixed")
+        f64, f32 = srv.wait(h64).numpy(), srv.wait(h32).numpy().astype(np.float64)
+        ref = orr.evaluate(otab, se["times"], pv, lcids=se["lcids"], pbids=se["pbids"],
+                           nss=se["nss"], exptimes=se["exptimes"])
+        assert np.abs(f64 - ref).max() <= 1e-9
+        assert np.abs(f32 - ref).max() <= 1e-6
+    srv.close()
+
+
+def test_admission_by_footprint(env):
+    """A 4 MiB arena: requests whose combined footprint is many times the
+    budget all complete (admitted as memory frees up); one larger than the
+    whole budget is refused at submission."""
+    rr, tab, otab, series, reqs = env
+    srv = rr.Server(tab, budget_bytes=4 << 20, max_tick_blocks=64)
+    se = series[0]
+    sid = srv.add_series(se["times"], se["lcids"], se["pbids"], se["nss"], se["exptimes"])
+    npt = se["times"].size
+    rows_fit = max(1, int((3 << 20) / (npt * 4 + 300)))
+    pv = wl.draw_orbits(np.random.default_rng(0), rows_fit, npb=4, chromatic=0.05)
+    hs = [srv.submit(sid, pv, "mixed") for _ in range(12)]
+    direct = evaluate_direct(rr, tab, se, pv, "mixed")
+    for h in hs:
+        assert np.array_equal(srv.wait(h).numpy(), direct)
+    big = wl.draw_orbits(np.random.default_rng(1), 4 * rows_fit + 64, npb=4, chromatic=0.05)
+    with pytest.raises(rr.RRError) as e:
+        srv.submit(sid, big, "mixed")
+    assert e.value.code == -4
+    with pytest.raises(rr.RRError):
+        srv.submit(sid + 99, pv, "mixed")                 # unknown series
+    with pytest.raises(rr.RRError):
+        srv.submit(sid, pv[:, :7], "mixed")               # npar mismatch
+    srv.close()

@@ -139,29 +139,34 @@ def heterogeneous(npv=256, days=27.0, seed_extra=0):
                      name=f"heterogeneous_npv{npv}")
 
 
-def serving_requests(nreq, seed_extra=0, max_npv=2048, max_npt=100000,
-                     min_npt=1000):
-    """Request mix for the serving loop: npv ~ logU(1, max_npv),
-    npt ~ logU(min_npt, max_npt), nss in {1, 5, 10}, npb in {1..4} using the
-    resident passbands 0..npb-1; each request's times are split evenly into
-    one 2-min-cadence light curve per passband with exptime = cadence."""
+def serving_mix(nreq, nseries=12, seed_extra=0, max_npv=2048, max_npt=100000,
+                min_npt=1000):
+    """Request mix for the serving loop.  ``nseries`` resident time series,
+    each with npt ~ logU(min_npt, max_npt), nss in {1, 5, 10} and npb in
+    {1..4} passbands (the resident passbands 0..npb-1), its times split
+    evenly into one 2-min-cadence light curve per passband with
+    exptime = cadence.  ``nreq`` requests, each picking a series at random
+    with npv ~ logU(1, max_npv) parameter rows drawn as in ``population``
+    (chromatic k within 5 %).  Returns (series, requests)."""
     rng = rng_for(4, seed_extra)
-    reqs = []
-    for _ in range(nreq):
-        npv = int(np.exp(rng.uniform(0.0, np.log(max_npv))))
+    series = []
+    for _ in range(nseries):
         npt = int(np.exp(rng.uniform(np.log(min_npt), np.log(max_npt))))
         nss = int(rng.choice([1, 5, 10]))
         npb = int(rng.integers(1, 5))
         per = max(1, npt // npb)
-        times = np.concatenate([np.arange(per) * (2.0 * MINUTE)
-                                for _ in range(npb)])
-        lcids = np.repeat(np.arange(npb), per)
-        pv = draw_orbits(rng, npv, npb=npb, chromatic=0.05)
-        reqs.append(dict(times=times, lcids=lcids.astype(np.int32),
-                         pbids=np.arange(npb, dtype=np.int32),
-                         nss=np.full(npb, nss, np.int32),
-                         exptimes=np.full(npb, 2.0 * MINUTE), pv=pv))
-    return reqs
+        times = np.concatenate([np.arange(per) * (2.0 * MINUTE) for _ in range(npb)])
+        lcids = np.repeat(np.arange(npb), per).astype(np.int32)
+        series.append(dict(times=times, lcids=lcids, pbids=np.arange(npb, dtype=np.int32),
+                           nss=np.full(npb, nss, np.int32),
+                           exptimes=np.full(npb, 2.0 * MINUTE), npb=npb))
+    reqs = []
+    for _ in range(nreq):
+        sid = int(rng.integers(0, nseries))
+        npv = int(np.exp(rng.uniform(0.0, np.log(max_npv))))
+        pv = draw_orbits(rng, npv, npb=4, chromatic=0.05)
+        reqs.append(dict(series=sid, pv=pv))
+    return series, reqs
 
 
 def loglik_walkers(npv=1024, npt=50000, nss=5, seed_extra=0):
