@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="budget of the CPU-oracle baseline leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=240)
     return ap.parse_args()
 
 
@@ -131,6 +133,70 @@ def cpu_baseline(w, grid, budget_s, gpu_out64, gpu_out32):
              max_abs_err_mixed_ppm=err32 * 1e6)
 
 
+def serving_leg(rr, wl, nreq):
+    """Serving: a Poisson stream of population requests against resident
+    tables (the four heterogeneous-workload passbands) and 12 resident time
+    series (npt ~ logU(1e3, 1e5), nss in {1, 5, 10}, 1-4 passbands), each
+    request with npv ~ logU(1, 2048) rows, mixed precision, outputs copied to
+    page-locked host memory.  First a burst of a quarter of the requests
+    measures the saturated rate; the rest arrive at 0.7 x that rate and give
+    the latency percentiles (submission to output in host memory)."""
+    import numpy as np
+    het = wl.heterogeneous(npv=1)
+    tab = rr.Tables(het["mu_s"], het["I_s"], wl.DEFAULT_GRID)
+    series, reqs = wl.serving_mix(nreq)
+    srv = rr.Server(tab, budget_bytes=16 << 30, max_tick_blocks=8192)
+    sids = [srv.add_series(se["times"], se["lcids"], se["pbids"], se["nss"], se["exptimes"])
+            for se in series]
+    nsub = [int(np.sum(se["nss"][se["lcids"]])) for se in series]
+    work = [r["pv"].shape[0] * nsub[r["series"]] for r in reqs]
+    nburst = max(4, nreq // 4)
+    # burst: saturated throughput
+    t0 = time.perf_counter()
+    hs = [srv.submit(sids[r["series"]], r["pv"], "mixed") for r in reqs[:nburst]]
+    for h in hs:
+        srv.wait(h)
+    t_burst = time.perf_counter() - t0
+    sat_rps = nburst / t_burst
+    del hs
+    # Poisson stream at 0.7 x the saturated rate
+    rate = 0.7 * sat_rps
+    rng = np.random.default_rng(2009085004)
+    gaps = rng.exponential(1.0 / rate, nreq - nburst)
+    stream = reqs[nburst:]
+    handles = []
+
+    t1 = time.perf_counter()
+    next_t = t1
+    for r, gap in zip(stream, gaps):
+        next_t += gap
+        d = next_t - time.perf_counter()
+        if d > 0:
+            time.sleep(d)
+        handles.append(srv.submit(sids[r["series"]], r["pv"], "mixed"))
+    lat = []
+    for h in handles:
+        srv.wait(h)
+        lat.append(h.latency)
+        h.out = None
+    t_stream = time.perf_counter() - t1
+    st = srv.stats()
+    srv.close()
+    tab.close()
+    pts_stream = float(np.sum(work[nburst:]))
+    return dict(
+        workload="Poisson stream, npv~logU(1,2048), npt~logU(1e3,1e5), nss in {1,5,10}, "
+                 "1-4 passbands, mixed precision, outputs to pinned host memory",
+        requests=nreq, burst_requests=nburst, saturated_requests_per_s=sat_rps,
+        saturated_points_per_s=float(np.sum(work[:nburst])) / t_burst,
+        arrival_rate_per_s=rate, stream_points_per_s=pts_stream / t_stream,
+        latency_ms=dict(p50=1e3 * float(np.percentile(lat, 50)),
+                        p99=1e3 * float(np.percentile(lat, 99)),
+                        max=1e3 * float(np.max(lat))),
+        mean_points_per_request=float(np.mean(work)), grouped_launches=st["ticks"],
+        device_errors=st["last_error"])
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -204,6 +270,8 @@ def main():
     o32 = out32.cpu().numpy().astype(np.float64)
     o64 = out64.cpu().numpy()
     line["in_transit_fraction"] = float(np.mean(o64 < 1.0))
+    if not args.no_serving:
+        line["serving"] = serving_leg(rr, wl, args.serving_requests)
     if not args.no_cpu_baseline:
         cb, acc = cpu_baseline(w, grid, args.cpu_seconds, o64, o32)
         line["cpu_baseline"] = cb
