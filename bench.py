@@ -40,6 +40,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=240)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device-to-device copy --steps times "
+                         "(the reference kernel for scaling HBM byte counters)")
     return ap.parse_args()
 
 
@@ -211,6 +214,15 @@ def main():
     import workloads as wl
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(args.steps):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps(dict(copy_bytes_read=src.numel() * 4, copy_bytes_written=dst.numel() * 4,
+                              launches=args.steps)), flush=True)
+        return
     lib = rr.lib()
     w = wl.population()
     grid = wl.DEFAULT_GRID

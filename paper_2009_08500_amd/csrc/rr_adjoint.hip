@@ -204,8 +204,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(
         if (it >= npt) continue;
         const int l = lcids ? lcids[it] : 0;
         if (l < 0 || l >= lc.nlc) { ll = NAN; continue; }
-        const double dtc = phase_offset(times[it], p);
-        if (in_window(dtc, p, 0.5 * lc.exptime[l])) {
+        if (in_phase_window((times[it] - p.t0) * p.invP, p, 0.5 * lc.exptime[l] * p.invP)) {
             todo |= 1u << j;
         } else {
             const double r = double(obs[it]) - 1.0;
@@ -253,13 +252,13 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(
             R gt[6] = {0, 0, 0, 0, 0, 0};
             R gkt = R(0);
             for (int s = 0; s < nss; ++s) {
-                const double ts = t + ex * ((s + 0.5) / nss - 0.5);
-                const double dt = phase_offset(ts, p);
-                if (!in_window(dt, p, 0.0)) continue;
+                const double x = (t + ex * ((s + 0.5) / nss - 0.5)) - p.t0;
+                const double u = x * p.invP;
+                if (!in_phase_window(u, p, 0.0)) continue;
+                const double dt = x - p.P * rint(u);
                 bool front;
                 R dz[6];
-                const R z = separation_grad<R>(R(dt), R(ts - p.t0), orb, dv, invP,
-                                               &front, dz);
+                const R z = separation_grad<R>(R(dt), R(x), orb, dv, invP, &front, dz);
                 if (!front || !(z < onepk)) continue;
                 const R v = z * inv1pk * gscale;
                 int m = int(v);
@@ -293,9 +292,10 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(
             if (want_prof) {
                 const double cw = wgt * wrow;
                 for (int s = 0; s < nss; ++s) {
-                    const double ts = t + ex * ((s + 0.5) / nss - 0.5);
-                    const double dt = phase_offset(ts, p);
-                    if (!in_window(dt, p, 0.0)) continue;
+                    const double x = (t + ex * ((s + 0.5) / nss - 0.5)) - p.t0;
+                    const double u = x * p.invP;
+                    if (!in_phase_window(u, p, 0.0)) continue;
+                    const double dt = x - p.P * rint(u);
                     bool front;
                     const R z = separation<R>(R(dt), orb, &front);
                     if (!front || !(z < onepk)) continue;

@@ -158,6 +158,8 @@ __device__ inline PvConst make_pv_const(const double* row, int npb, double k0,
     c.rtr = a * (1.0 - e * e) / den;
     c.kmax = kmax;
     int32_t flags = ok ? kValid : 0;
+    c.flo = 0.0;
+    c.wn = 2.0;                      // covers every phase unless narrowed below
     if (ok) {
         // The planet can overlap the star only while r |cos(w + f)| < 1 + k
         // and sin(w + f) > 0.  With r >= a (1 - e) that confines f to
@@ -178,30 +180,28 @@ __device__ inline PvConst make_pv_const(const double* row, int npb, double k0,
                 return E - e * sin(E);
             };
             const double m0 = mean_of_true(ftr);
-            const double margin = 1e-9 * P;
-            c.dtlo = (mean_of_true(ftr - theta) - m0) / c.n - margin;
-            c.dthi = (mean_of_true(ftr + theta) - m0) / c.n + margin;
-            if (c.dthi - c.dtlo >= P) flags |= kAlways;
+            const double inv2pi = 0.5 / Num<double>::pi;
+            // window in phase units (mean anomaly / 2 pi) around conjunction,
+            // widened by 1e-9 of a period on each side for rounding
+            const double lo = (mean_of_true(ftr - theta) - m0) * inv2pi - 1e-9;
+            const double hi = (mean_of_true(ftr + theta) - m0) * inv2pi + 1e-9;
+            if (hi - lo < 1.0) {
+                c.flo = lo;
+                c.wn = hi - lo;
+            } else {
+                flags |= kAlways;
+            }
         }
     }
     c.flags = flags;
     return c;
 }
 
-// Time offset from the nearest conjunction, FP64 (the step that needs FP64
-// over long baselines whatever the bulk precision).
-__device__ inline double phase_offset(double t, const PvConst& p) {
-    const double x = t - p.t0;
-    return x - p.P * rint(x * p.invP);
-}
-
-// Is the offset inside the transit window (or any window a period away)?
-// `hw` widens the window on both sides (half an exposure).
-__device__ inline bool in_window(double dt, const PvConst& p, double hw) {
-    if (p.flags & kAlways) return true;
-    const double lo = p.dtlo - hw, hi = p.dthi + hw;
-    if (hi - lo >= p.P) return true;
-    return (dt >= lo && dt <= hi) || (dt - p.P >= lo) || (dt + p.P <= hi);
+// Is phase u = (t - t0)/P inside the transit window (repeated every
+// period), widened by hw_phase (half an exposure, in periods) on each side?
+__device__ inline bool in_phase_window(double u, const PvConst& p, double hw_phase) {
+    const double g = u - (p.flo - hw_phase);
+    return (g - floor(g)) < p.wn + 2.0 * hw_phase;
 }
 
 }  // namespace rr

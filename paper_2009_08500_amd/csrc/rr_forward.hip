@@ -7,7 +7,8 @@
 //               sin/cos of the eccentric anomaly at conjunction, and the
 //               transit window -- the range of time offsets outside which
 //               the planet is either behind the star or farther than 1 + k
-//               from its centre, so the flux is exactly 1;
+//               from its centre, so the flux is exactly 1 (kept in phase
+//               units, so the test is frac(phase - lo) < width);
 //   k_forward   one workgroup per (parameter vector, tile of 2048 times),
 //               lanes along time so loads of the shared time array and the
 //               stores of out[pv][t] are coalesced.  Pass 1 reduces each
@@ -46,7 +47,7 @@ __device__ inline void forward_block(const FwdJob& job, const LcInfo& lc, int ip
     const int32_t* __restrict__ lcids = job.lcids;
     const double* __restrict__ pv = job.pv;
     const int t_base = tile * kTile + tid;
-    R* orow = static_cast<R*>(job.out) + int64_t(ipv) * npt;
+    R* __restrict__ orow = static_cast<R*>(job.out) + int64_t(ipv) * npt;
     const PvConst p = job.pvc[ipv];
 
     if (!(p.flags & kValid)) {
@@ -57,29 +58,40 @@ __device__ inline void forward_block(const FwdJob& job, const LcInfo& lc, int ip
         return;
     }
 
-    // Pass 1: exposures that cannot overlap the star get F = 1 now.
+    // Pass 1: exposures that cannot overlap the star get F = 1 now.  All
+    // loads first, so the wave has them in flight together.
+    double tv[kTimesPerThread];
+    int lv[kTimesPerThread];
+#pragma unroll
+    for (int j = 0; j < kTimesPerThread; ++j) {
+        const int it = t_base + j * kBlock;
+        tv[j] = it < npt ? times[it] : 0.0;
+        lv[j] = (lcids && it < npt) ? lcids[it] : 0;
+    }
+    const double hw0 = 0.5 * lc.exptime[0] * p.invP;
     uint32_t todo = 0;
+#pragma unroll
     for (int j = 0; j < kTimesPerThread; ++j) {
         const int it = t_base + j * kBlock;
         if (it >= npt) continue;
-        const int l = lcids ? lcids[it] : 0;
+        const int l = lv[j];
         if (l < 0 || l >= lc.nlc) { orow[it] = R(NAN); continue; }
-        const double dtc = phase_offset(times[it], p);
-        if (in_window(dtc, p, 0.5 * lc.exptime[l])) todo |= 1u << j;
+        const double hw = lcids ? 0.5 * lc.exptime[l] * p.invP : hw0;
+        if (in_phase_window((tv[j] - p.t0) * p.invP, p, hw)) todo |= 1u << j;
         else orow[it] = R(1);
     }
     if (!__syncthreads_or(todo != 0)) return;
 
     // k-interpolated LD-weighted vectors of this parameter vector, one per
     // passband (Sect. 3.1.2): ldw = (1 - ak) T[ik] + ak T[ik+1].
-    for (int idx = tid; idx < g.npb * g.ng; idx += kBlock) {
-        const int pb = idx / g.ng, m = idx - pb * g.ng;
+    for (int pb = 0; pb < g.npb; ++pb) {
         const double u = (pv[int64_t(ipv) * npar + 6 + pb] - g.k0) / g.dk;
         int ik = int(floor(u));
         ik = ik < 0 ? 0 : (ik > g.nk - 2 ? g.nk - 2 : ik);
         const R ak = R(u - ik);
         const R* t0r = T + (int64_t(pb) * g.nk + ik) * g.ng;
-        ldw[idx] = (R(1) - ak) * t0r[m] + ak * t0r[g.ng + m];
+        for (int m = tid; m < g.ng; m += kBlock)
+            ldw[pb * g.ng + m] = (R(1) - ak) * t0r[m] + ak * t0r[g.ng + m];
     }
     __syncthreads();
 
@@ -90,8 +102,8 @@ __device__ inline void forward_block(const FwdJob& job, const LcInfo& lc, int ip
         const int j = __builtin_ctz(todo);
         todo &= todo - 1;
         const int it = t_base + j * kBlock;
-        const int l = lcids ? lcids[it] : 0;
-        const int pb = lc.pb[l];
+        const int l = lcids ? lcids[it] : 0;          // reloaded: keeps pass 1's
+        const int pb = lc.pb[l];                      // registers free here
         const int nss = lc.nss[l];
         const double ex = lc.exptime[l];
         const double t = times[it];
@@ -102,9 +114,10 @@ __device__ inline void forward_block(const FwdJob& job, const LcInfo& lc, int ip
         const R* lw = ldw + pb * g.ng;
         R acc = R(0);
         for (int s = 0; s < nss; ++s) {
-            const double ts = t + ex * ((s + 0.5) / nss - 0.5);
-            const double dt = phase_offset(ts, p);
-            if (!in_window(dt, p, 0.0)) continue;
+            const double x = (t + ex * ((s + 0.5) / nss - 0.5)) - p.t0;
+            const double u = x * p.invP;
+            if (!in_phase_window(u, p, 0.0)) continue;
+            const double dt = x - p.P * rint(u);
             bool front;
             const R z = separation<R>(R(dt), orb, &front);
             if (!front || !(z < onepk)) continue;

@@ -25,7 +25,8 @@ struct PvConst {
     double a, e, cosw, sinw;
     double sE, cE, q, rtr;        // sin/cos of E at conjunction, sqrt(1-e^2),
                                   // star-planet distance at conjunction
-    double cosi, dtlo, dthi, kmax;  // transit window in time offset
+    double cosi, flo, wn, kmax;   // transit window in phase units: inside iff
+                                  // frac((t - t0)/P - flo) < wn
     int32_t flags;                // kValid | kAlways
     int32_t pad[3];
 };

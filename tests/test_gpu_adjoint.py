@@ -55,6 +55,8 @@ def test_loglik_and_gradients_match_oracle(rr, precision, rel_ll, rel_g):
     ll, g, gp = rr.loglik_grad(tab, ser, w["pv"], obs, w["sigma"], precision, grad=True,
                                profile=True)
     ll, g, gp = ll.cpu().numpy(), g.cpu().numpy(), gp.cpu().numpy()
+    if precision == "mixed":
+        obs = obs.astype(np.float32).astype(np.float64)   # the input the kernel sees
     oll, og, ogp = ogr.loglik_grad(otab, w["times"], w["pv"], obs, w["sigma"], nss=w["nss"],
                                    exptimes=w["exptimes"])
     np.testing.assert_allclose(ll, oll, rtol=rel_ll)
