@@ -134,8 +134,10 @@ RR_API int rr_set_profile(rr_tables* t, const double* prof_d,
  *                (out_d is float[npv][npt]);
  * out_d          device output, row-major, times contiguous.
  * npt >= 0, npv >= 0 (zero sizes enqueue nothing), 1 <= nlc <= RR_MAX_LC.
- * Temporary device memory (~160 bytes per parameter vector) comes from the
- * stream-ordered allocator and is released on the stream. */
+ * Temporary device memory (144 bytes per parameter vector) is a per-stream
+ * buffer kept by the tables handle: it grows (with a synchronising
+ * reallocation) when a call needs more, is reused without waiting by later
+ * calls on the same stream, and is freed by rr_free_tables. */
 RR_API int rr_evaluate(const rr_tables* t, const double* times_d,
                        const int32_t* lcids_d, int32_t npt,
                        const int32_t* pbids, const int32_t* nss,

@@ -7,8 +7,8 @@ the library has not been built.
 """
 
 from ._lib import (RR_FP64, RR_MIXED, RRError, lib)  # noqa: F401
-from .api import (DEFAULT_GRID, RRLogLik, Tables, TimeSeries,  # noqa: F401
-                  evaluate, loglik_grad, make_grid)
+from .api import (DEFAULT_GRID, Evaluator, RRLogLik, Tables,  # noqa: F401
+                  TimeSeries, evaluate, loglik_grad, make_grid)
 
 from .serving import Server  # noqa: F401,E402
 

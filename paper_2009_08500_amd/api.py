@@ -176,6 +176,39 @@ def evaluate(tables, series, pv, precision="fp64", out=None, stream=None):
     return out
 
 
+class Evaluator:
+    """rr_evaluate for repeated calls with populations of one size over one
+    time series (the MCMC pattern): every argument except the parameter
+    rows is marshalled once, and the output buffer is reused.  Calls enqueue
+    on the stream current at construction (or ``stream``)."""
+
+    def __init__(self, tables, series, npv, precision="mixed", stream=None):
+        if not isinstance(series, TimeSeries):
+            series = TimeSeries(series)
+        self.tables, self.series, self.npv = tables, series, int(npv)
+        self.prec = PRECISIONS[precision]
+        self.npar = tables.npar
+        dtype = torch.float64 if self.prec == RR_FP64 else torch.float32
+        self.out = torch.empty((self.npv, series.npt), dtype=dtype, device="cuda")
+        lc, npt, pb, nss, ex, nlc = series.lc_args()
+        s = torch.cuda.current_stream() if stream is None else stream
+        self._fn = _lib.lib().rr_evaluate
+        self._args = [tables.handle, series.times.data_ptr(), lc, npt, pb, nss, ex, nlc,
+                      None, self.npv, self.npar, self.prec, self.out.data_ptr(), s.cuda_stream]
+
+    def __call__(self, pv):
+        """Fluxes (npv, npt) for a contiguous float64 device tensor of rows."""
+        if (pv.dtype is not torch.float64 or not pv.is_cuda or not pv.is_contiguous()
+                or pv.numel() != self.npv * self.npar):
+            raise ValueError("pv must be a float64 device tensor of shape (npv, npar)")
+        a = self._args
+        a[8] = pv.data_ptr()
+        rc = self._fn(*a)
+        if rc:
+            check(rc, "rr_evaluate")
+        return self.out
+
+
 def loglik_grad(tables, series, pv, obs, sigma, precision="fp64", grad=True, profile=False,
                 wprof=None, stream=None):
     """Gaussian log-likelihood of ``obs`` under each parameter row and its

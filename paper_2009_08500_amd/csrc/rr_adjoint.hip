@@ -199,19 +199,49 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(
 
     // Pass 1: residuals of exposures that cannot overlap the star.
     uint32_t todo = 0;
-    for (int j = 0; j < kTimesPerThread; ++j) {
-        const int it = t_base + j * kBlock;
-        if (it >= npt) continue;
-        const int l = lcids ? lcids[it] : 0;
-        if (l < 0 || l >= lc.nlc) { ll = NAN; continue; }
-        if (in_phase_window((times[it] - p.t0) * p.invP, p, 0.5 * lc.exptime[l] * p.invP)) {
-            todo |= 1u << j;
-        } else {
-            const double r = double(obs[it]) - 1.0;
-            ll -= 0.5 * r * r * inv_sig2;
+    const int tfirst = tile * kTile;
+    if (!lcids && tfirst + kTile <= npt) {
+        // whole tile in range, one light curve (see forward_block)
+        double tv[kTimesPerThread], ov[kTimesPerThread];
+#pragma unroll
+        for (int j = 0; j < kTimesPerThread; ++j) {
+            tv[j] = times[tfirst + tid + j * kBlock];
+            ov[j] = double(obs[tfirst + tid + j * kBlock]);
+        }
+        const double hw = 0.5 * lc.exptime[0] * p.invP;
+        const double c0 = -p.t0 * p.invP - (p.flo - hw);
+        const double wn = p.wn + 2.0 * hw;
+#pragma unroll
+        for (int j = 0; j < kTimesPerThread; ++j) {
+            const double gph = fma(tv[j], p.invP, c0);
+            if (gph - floor(gph) < wn) {
+                todo |= 1u << j;
+            } else {
+                const double r = ov[j] - 1.0;
+                ll -= 0.5 * r * r * inv_sig2;
+            }
+        }
+    } else {
+        for (int j = 0; j < kTimesPerThread; ++j) {
+            const int it = t_base + j * kBlock;
+            if (it >= npt) continue;
+            const int l = lcids ? lcids[it] : 0;
+            if (l < 0 || l >= lc.nlc) { ll = NAN; continue; }
+            if (in_phase_window((times[it] - p.t0) * p.invP, p, 0.5 * lc.exptime[l] * p.invP)) {
+                todo |= 1u << j;
+            } else {
+                const double r = double(obs[it]) - 1.0;
+                ll -= 0.5 * r * r * inv_sig2;
+            }
         }
     }
-    const bool any = __syncthreads_or(todo != 0);
+    __shared__ int wave_any[kBlock / 64];
+    const int wany = __any(todo != 0);
+    if ((tid & 63) == 0) wave_any[tid >> 6] = wany;
+    __syncthreads();
+    bool any = false;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) any |= wave_any[w] != 0;
 
     if (any) {
         for (int idx = tid; idx < npb * ng; idx += kBlock) {

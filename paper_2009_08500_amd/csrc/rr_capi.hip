@@ -5,6 +5,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <string>
 #include <vector>
@@ -49,6 +50,25 @@ static int check_grid(const rr_grid* g) {
     return RR_OK;
 }
 
+hipError_t stream_workspace(rr_tables* t, hipStream_t stream, size_t bytes, void** out) {
+    std::lock_guard<std::mutex> lk(t->ws_mu);
+    auto& slot = t->ws[stream];
+    if (slot.second < bytes) {
+        if (slot.first) {
+            hipError_t e = hipFree(slot.first);     // synchronising; growth only
+            slot.first = nullptr;
+            slot.second = 0;
+            if (e != hipSuccess) return e;
+        }
+        const size_t nb = std::max(bytes, size_t(1) << 16);
+        hipError_t e = hipMalloc(&slot.first, nb);
+        if (e != hipSuccess) return e;
+        slot.second = nb;
+    }
+    *out = slot.first;
+    return hipSuccess;
+}
+
 static void free_tables(rr_tables* t) {
     if (!t) return;
     int cur = 0;
@@ -58,6 +78,8 @@ static void free_tables(rr_tables* t) {
                     t->W, t->T64, t->T32, t->inv_istar};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
+    for (auto& kv : t->ws)
+        if (kv.second.first) (void)hipFree(kv.second.first);
     (void)hipSetDevice(cur);
     delete t;
 }
@@ -234,16 +256,16 @@ RR_API int rr_evaluate(const rr_tables* t, const double* times_d,
     if (!out_d) return einval("out is NULL");
     rc = check_device(t);
     if (rc) return rc;
-    PvConst* pvc = nullptr;
-    hipError_t e = hipMallocAsync((void**)&pvc, sizeof(PvConst) * size_t(npv), stream);
-    if (e != hipSuccess) return e == hipErrorOutOfMemory ? RR_ENOMEM : hip_fail(e, "hipMallocAsync");
+    void* ws = nullptr;
+    hipError_t e = stream_workspace(const_cast<rr_tables*>(t), stream,
+                                    sizeof(PvConst) * size_t(npv), &ws);
+    if (e != hipSuccess) return e == hipErrorOutOfMemory ? RR_ENOMEM : hip_fail(e, "workspace");
+    PvConst* pvc = static_cast<PvConst*>(ws);
     e = launch_pv_setup(t, pv_d, npv, npar, pvc, stream);
     if (e == hipSuccess)
         e = launch_forward(t, times_d, lcids_d, npt, lc, pv_d, npv, npar, pvc,
                            precision, out_d, stream);
-    hipError_t ef = hipFreeAsync(pvc, stream);
     if (e != hipSuccess) return hip_fail(e, "forward kernels");
-    if (ef != hipSuccess) return hip_fail(ef, "hipFreeAsync");
     return RR_OK;
 }
 

@@ -182,9 +182,10 @@ __device__ inline PvConst make_pv_const(const double* row, int npb, double k0,
             const double m0 = mean_of_true(ftr);
             const double inv2pi = 0.5 / Num<double>::pi;
             // window in phase units (mean anomaly / 2 pi) around conjunction,
-            // widened by 1e-9 of a period on each side for rounding
-            const double lo = (mean_of_true(ftr - theta) - m0) * inv2pi - 1e-9;
-            const double hi = (mean_of_true(ftr + theta) - m0) * inv2pi + 1e-9;
+            // widened by 1e-8 of a period on each side, more than the
+            // rounding of a phase t/P - t0/P of up to 1e7 periods
+            const double lo = (mean_of_true(ftr - theta) - m0) * inv2pi - 1e-8;
+            const double hi = (mean_of_true(ftr + theta) - m0) * inv2pi + 1e-8;
             if (hi - lo < 1.0) {
                 c.flo = lo;
                 c.wn = hi - lo;

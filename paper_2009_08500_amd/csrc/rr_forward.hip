@@ -58,29 +58,58 @@ __device__ inline void forward_block(const FwdJob& job, const LcInfo& lc, int ip
         return;
     }
 
-    // Pass 1: exposures that cannot overlap the star get F = 1 now.  All
-    // loads first, so the wave has them in flight together.
-    double tv[kTimesPerThread];
-    int lv[kTimesPerThread];
-#pragma unroll
-    for (int j = 0; j < kTimesPerThread; ++j) {
-        const int it = t_base + j * kBlock;
-        tv[j] = it < npt ? times[it] : 0.0;
-        lv[j] = (lcids && it < npt) ? lcids[it] : 0;
-    }
-    const double hw0 = 0.5 * lc.exptime[0] * p.invP;
+    // Pass 1: exposures that cannot overlap the star get F = 1 now.
     uint32_t todo = 0;
+    const int tfirst = tile * kTile;
+    if (!lcids && tfirst + kTile <= npt) {
+        // Whole tile in range, one light curve: no bounds or light-curve
+        // checks; phase g = t/P + c0 with c0 = -t0/P - (window start) by one
+        // FMA; every output is written as 1 here and pass 2 overwrites the
+        // exposures that overlap the star.
+        const double* tp = times + tfirst + tid;
+        R* op = orow + tfirst + tid;
+        double tv[kTimesPerThread];
 #pragma unroll
-    for (int j = 0; j < kTimesPerThread; ++j) {
-        const int it = t_base + j * kBlock;
-        if (it >= npt) continue;
-        const int l = lv[j];
-        if (l < 0 || l >= lc.nlc) { orow[it] = R(NAN); continue; }
-        const double hw = lcids ? 0.5 * lc.exptime[l] * p.invP : hw0;
-        if (in_phase_window((tv[j] - p.t0) * p.invP, p, hw)) todo |= 1u << j;
-        else orow[it] = R(1);
+        for (int j = 0; j < kTimesPerThread; ++j) tv[j] = tp[j * kBlock];
+        const double hw = 0.5 * lc.exptime[0] * p.invP;
+        const double c0 = -p.t0 * p.invP - (p.flo - hw);
+        const double wn = p.wn + 2.0 * hw;
+#pragma unroll
+        for (int j = 0; j < kTimesPerThread; ++j) {
+            const double gph = fma(tv[j], p.invP, c0);
+            if (gph - floor(gph) < wn) todo |= 1u << j;
+            op[j * kBlock] = R(1);
+        }
+    } else {
+        double tv[kTimesPerThread];
+        int lv[kTimesPerThread];
+#pragma unroll
+        for (int j = 0; j < kTimesPerThread; ++j) {
+            const int it = t_base + j * kBlock;
+            tv[j] = it < npt ? times[it] : 0.0;
+            lv[j] = (lcids && it < npt) ? lcids[it] : 0;
+        }
+        const double hw0 = 0.5 * lc.exptime[0] * p.invP;
+#pragma unroll
+        for (int j = 0; j < kTimesPerThread; ++j) {
+            const int it = t_base + j * kBlock;
+            if (it >= npt) continue;
+            const int l = lv[j];
+            if (l < 0 || l >= lc.nlc) { orow[it] = R(NAN); continue; }
+            const double hw = lcids ? 0.5 * lc.exptime[l] * p.invP : hw0;
+            if (in_phase_window((tv[j] - p.t0) * p.invP, p, hw)) todo |= 1u << j;
+            else orow[it] = R(1);
+        }
     }
-    if (!__syncthreads_or(todo != 0)) return;
+    // Workgroup vote: does any exposure of the tile overlap the window?
+    __shared__ int wave_any[kBlock / 64];
+    const int wany = __any(todo != 0);
+    if ((tid & 63) == 0) wave_any[tid >> 6] = wany;
+    __syncthreads();
+    bool any = false;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) any |= wave_any[w] != 0;
+    if (!any) return;
 
     // k-interpolated LD-weighted vectors of this parameter vector, one per
     // passband (Sect. 3.1.2): ldw = (1 - ak) T[ik] + ak T[ik+1].
@@ -132,14 +161,14 @@ __device__ inline void forward_block(const FwdJob& job, const LcInfo& lc, int ip
     }
 }
 
-// One population (rr_evaluate): workgroup b -> row b / ntiles, tile b % ntiles.
+// One population (rr_evaluate): workgroup (x, y) -> row pv0 + y, tile x.
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_forward(FwdJob job, LcInfo lc, GridDev g,
                                                     const R* __restrict__ T,
                                                     const double* __restrict__ inv_istar) {
     extern __shared__ unsigned char smem_raw[];
-    const int ipv = blockIdx.x / job.ntiles;
-    const int tile = blockIdx.x - ipv * job.ntiles;
+    const int ipv = job.pv0 + blockIdx.y;
+    const int tile = blockIdx.x;
     forward_block<R>(job, lc, ipv, tile, g, T, inv_istar, reinterpret_cast<R*>(smem_raw));
 }
 
@@ -193,20 +222,24 @@ hipError_t launch_forward(const rr_tables* t, const double* times,
     job.times = times; job.lcids = lcids; job.lc = nullptr; job.pv = pv; job.pvc = pvc;
     job.out = out; job.npt = npt; job.npar = npar; job.pv0 = 0; job.npv = npv;
     job.ntiles = (npt + kTile - 1) / kTile; job.block0 = 0;
-    const dim3 grid(unsigned(int64_t(job.ntiles) * npv));
     const KernelEvents ev = kernel_events();
     if (ev.before) {
         hipError_t e = hipEventRecord(ev.before, s);
         if (e != hipSuccess) return e;
     }
-    if (precision == RR_FP64) {
-        const size_t lds = sizeof(double) * size_t(g.npb) * g.ng;
-        hipLaunchKernelGGL(k_forward<double>, grid, dim3(kBlock), lds, s, job, lc, g, t->T64,
-                           t->inv_istar);
-    } else {
-        const size_t lds = sizeof(float) * size_t(g.npb) * g.ng;
-        hipLaunchKernelGGL(k_forward<float>, grid, dim3(kBlock), lds, s, job, lc, g, t->T32,
-                           t->inv_istar);
+    // rows along grid y, at most 65535 per launch
+    for (int32_t r0 = 0; r0 < npv; r0 += 65535) {
+        job.pv0 = r0;
+        const dim3 grid(unsigned(job.ntiles), unsigned(npv - r0 < 65535 ? npv - r0 : 65535));
+        if (precision == RR_FP64) {
+            const size_t lds = sizeof(double) * size_t(g.npb) * g.ng;
+            hipLaunchKernelGGL(k_forward<double>, grid, dim3(kBlock), lds, s, job, lc, g,
+                               t->T64, t->inv_istar);
+        } else {
+            const size_t lds = sizeof(float) * size_t(g.npb) * g.ng;
+            hipLaunchKernelGGL(k_forward<float>, grid, dim3(kBlock), lds, s, job, lc, g,
+                               t->T32, t->inv_istar);
+        }
     }
     hipError_t e = hipGetLastError();
     if (e == hipSuccess && ev.after) e = hipEventRecord(ev.after, s);

@@ -7,14 +7,19 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
 #include <string>
+#include <unordered_map>
 
 #include "rr.h"
 
 namespace rr {
 
+#ifndef RR_TIMES_PER_THREAD
+#define RR_TIMES_PER_THREAD 8
+#endif
 constexpr int kBlock = 256;          // threads per workgroup (4 wave64)
-constexpr int kTimesPerThread = 8;   // times per thread in the forward kernel
+constexpr int kTimesPerThread = RR_TIMES_PER_THREAD;   // times per thread
 constexpr int kTile = kBlock * kTimesPerThread;
 constexpr int kMaxLdsBytes = 64 * 1024;   // LDS budget for the k-interpolated
                                           // LD vectors of one workgroup
@@ -118,6 +123,10 @@ struct rr_tables {
     double* T64 = nullptr;       // [npb][nk][ng]
     float* T32 = nullptr;        // [npb][nk][ng]
     double* inv_istar = nullptr; // [npb]
+    // Per-stream temporaries of rr_evaluate (grow-only; work on one stream is
+    // ordered, so a stream's buffer is reused without waiting).
+    std::mutex ws_mu;
+    std::unordered_map<hipStream_t, std::pair<void*, size_t>> ws;
 };
 
 namespace rr {
@@ -127,6 +136,8 @@ void set_error(const std::string& msg);
 struct KernelEvents { hipEvent_t before = nullptr, after = nullptr; };
 KernelEvents& kernel_events();
 int hip_fail(hipError_t err, const char* what);
+// Device workspace of at least `bytes` for `stream`, owned by the tables.
+hipError_t stream_workspace(rr_tables* t, hipStream_t stream, size_t bytes, void** out);
 rr::GridDev grid_dev(const rr_tables* t);
 
 // Kernel launchers (rr_prep.hip, rr_forward.hip).
