@@ -48,8 +48,9 @@ __device__ inline R lens_area_grad(R k, R z, R* Az, R* Ak) {
     R prod = (a + (b + s)) * (s - (a - b)) * (s + (a - b)) * (a + (b - s));
     prod = prod > R(0) ? prod : R(0);
     const R area2 = R(0.5) * N::sqrt_(prod);
-    const R h = area2 / z;
-    const R x1 = (z * z + (R(1) - k) * (R(1) + k)) / (R(2) * z);
+    const R invz = R(1) / z;
+    const R h = area2 * invz;
+    const R x1 = (z * z + (R(1) - k) * (R(1) + k)) * (R(0.5) * invz);
     const R x0 = z - x1;
     const R k1 = N::atan2_(h, x1);
     const R k0 = N::atan2_(h, x0);
@@ -103,21 +104,21 @@ __device__ inline R separation_grad(R dt, R x, const OrbitR<R>& o,
         d = dM / (R(1) - o.e * o.cE);
         d = d < lo ? lo : (d > hi ? hi : d);
         for (int it = 0; it < N::kepler_maxit; ++it) {
-            N::sincos_(R(0.5) * d, &s2, &c2);
+            sincos_small(R(0.5) * d, &s2, &c2);
             const R sd = R(2) * s2 * c2;
             const R cm1 = R(-2) * s2 * s2;
             const R h = d - o.e * (o.sE * cm1 + o.cE * sd) - dM;
             if (h < R(0)) lo = d; else hi = d;
             const R hp = R(1) - o.e * (o.cE * (R(1) + cm1) - o.sE * sd);
             const R hpp = o.e * (o.sE * (R(1) + cm1) + o.cE * sd);
-            R dn = d - h / (hp - R(0.5) * h * hpp / hp);
+            R dn = d - R(2) * h * hp / (R(2) * hp * hp - h * hpp);
             if (!(dn >= lo && dn <= hi)) dn = R(0.5) * (lo + hi);
             const R step = dn - d;
             d = dn;
             if (N::abs_(step) < N::kepler_stop) break;
         }
     }
-    N::sincos_(R(0.5) * d, &s2, &c2);
+    sincos_small(R(0.5) * d, &s2, &c2);
     const R sd = R(2) * s2 * c2;
     const R cm1 = R(-2) * s2 * s2;
     const R dc = o.cE * cm1 - o.sE * sd;

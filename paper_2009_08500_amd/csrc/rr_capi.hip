@@ -119,9 +119,6 @@ int check_eval_args(const rr_tables* t, const double* times_d,
         if (!times_d) return einval("times is NULL");
         if (!pv_d) return einval("pv is NULL");
     }
-    const size_t elt = precision == RR_FP64 ? sizeof(double) : sizeof(float);
-    if (elt * size_t(t->npb) * t->grid.ng > size_t(kMaxLdsBytes))
-        return elimit("npb * ng LD vectors exceed the 64 KiB LDS budget");
     const int64_t ntiles = (int64_t(npt) + kTile - 1) / kTile;
     if (ntiles * npv * kBlock >= (int64_t(1) << 32))
         return elimit("npv * npt too large for one launch");

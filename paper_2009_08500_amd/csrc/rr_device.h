@@ -30,6 +30,33 @@ template <> struct Num<float> {
     static constexpr int kepler_maxit = 20;
 };
 
+// sin and cos of a half-angle offset from conjunction, which is small
+// inside the transit window.  In float, for |x| <= 3/4 the Maclaurin series
+// through the x^9 and x^10 terms are summed by Horner's rule in x^2
+// (truncation below 2e-9 relative); larger float arguments and every double
+// argument go to the library sincos, which measured faster than a series of
+// double length.
+template <typename R>
+__device__ inline void sincos_small(R x, R* s, R* c) {
+    using N = Num<R>;
+    if (sizeof(R) == 8 || N::abs_(x) > R(0.75)) {
+        N::sincos_(x, s, c);
+        return;
+    }
+    const R x2 = x * x;
+    R ps = R(1.0 / 362880.0);                       // 1/9!
+    ps = ps * x2 - R(1.0 / 5040.0);
+    ps = ps * x2 + R(1.0 / 120.0);
+    ps = ps * x2 - R(1.0 / 6.0);
+    *s = x + x * x2 * ps;
+    R pc = R(-1.0 / 3628800.0);                     // -1/10!
+    pc = pc * x2 + R(1.0 / 40320.0);
+    pc = pc * x2 - R(1.0 / 720.0);
+    pc = pc * x2 + R(1.0 / 24.0);
+    pc = pc * x2 - R(0.5);
+    *c = R(1) + x2 * pc;
+}
+
 // Area of the intersection of a disk of radius Rd centred at the origin and a
 // disk of radius k centred at distance c (the lens a(c, k) of Eq. 5 when
 // Rd = 1).  In the partial-overlap case the three centres-and-chord-end
@@ -56,8 +83,9 @@ __device__ inline R lens_area(R Rd, R k, R c) {
     R prod = (a + (b + s)) * (s - (a - b)) * (s + (a - b)) * (a + (b - s));
     prod = prod > R(0) ? prod : R(0);
     const R area2 = R(0.5) * N::sqrt_(prod);        // 2 D
-    const R h = area2 / c;                          // half chord
-    const R x1 = (c * c + (Rd - k) * (Rd + k)) / (R(2) * c);
+    const R invc = R(1) / c;
+    const R h = area2 * invc;                       // half chord
+    const R x1 = (c * c + (Rd - k) * (Rd + k)) * (R(0.5) * invc);
     const R x0 = c - x1;
     const R k1 = N::atan2_(h, x1);
     const R k0 = N::atan2_(h, x0);
@@ -100,21 +128,22 @@ __device__ inline R separation(R dt, const OrbitR<R>& o, bool* front) {
         d = dM / (R(1) - o.e * o.cE);
         d = d < lo ? lo : (d > hi ? hi : d);
         for (int it = 0; it < N::kepler_maxit; ++it) {
-            N::sincos_(R(0.5) * d, &s2, &c2);
+            sincos_small(R(0.5) * d, &s2, &c2);
             const R sd = R(2) * s2 * c2;
             const R cm1 = R(-2) * s2 * s2;
             const R h = d - o.e * (o.sE * cm1 + o.cE * sd) - dM;
             if (h < R(0)) lo = d; else hi = d;
             const R hp = R(1) - o.e * (o.cE * (R(1) + cm1) - o.sE * sd);
             const R hpp = o.e * (o.sE * (R(1) + cm1) + o.cE * sd);
-            R dn = d - h / (hp - R(0.5) * h * hpp / hp);
+            // Halley: h / (h' - h h''/(2 h')) with a single division
+            R dn = d - R(2) * h * hp / (R(2) * hp * hp - h * hpp);
             if (!(dn >= lo && dn <= hi)) dn = R(0.5) * (lo + hi);
             const R step = dn - d;
             d = dn;
             if (N::abs_(step) < N::kepler_stop) break;
         }
     }
-    N::sincos_(R(0.5) * d, &s2, &c2);
+    sincos_small(R(0.5) * d, &s2, &c2);
     const R sd = R(2) * s2 * c2;
     const R cm1 = R(-2) * s2 * s2;
     const R dc = o.cE * cm1 - o.sE * sd;
@@ -161,31 +190,71 @@ __device__ inline PvConst make_pv_const(const double* row, int npb, double k0,
     c.flo = 0.0;
     c.wn = 2.0;                      // covers every phase unless narrowed below
     if (ok) {
-        // The planet can overlap the star only while r |cos(w + f)| < 1 + k
-        // and sin(w + f) > 0.  With r >= a (1 - e) that confines f to
-        // |f - f_tr| < theta = asin((1 + kmax) / (a (1 - e))).
-        const double s = (1.0 + kmax) / (a * (1.0 - e)) * (1.0 + 1e-6) + 1e-12;
-        if (s >= 1.0) {
-            flags |= kAlways;
+        // With psi = f - f_tr (transit at psi = 0) the sky separation obeys
+        // z^2 = r^2 (sin^2 psi sin^2 i + cos^2 i), and the planet is in front
+        // for |psi| < pi/2.  Over any set where r >= rmin, z < 1 + k needs
+        // sin^2 psi < ((1 + k)^2 / rmin^2 - cos^2 i) / sin^2 i.  Starting from
+        // rmin = a (1 - e), the window |psi| < theta is narrowed twice by
+        // taking rmin as the smallest r = a (1 - e^2)/(1 + e cos f) over the
+        // current window.  An empty window means the planet never overlaps
+        // the star.
+        //
+        // The window only has to contain the true one, so its transcendental
+        // steps run in float with every rounding pushed outward: the asin
+        // argument is rounded up and theta widened by 1e-6 rad, cos f is
+        // raised by 3e-7, and the phase limits are widened by 1e-6 (2 + the
+        // largest dM/df) of a period, several times the float error of the
+        // mean-anomaly differences.  This keeps the setup short: it is a
+        // serial chain per parameter vector.
+        const double ci2 = cosi * cosi, si2 = 1.0 - ci2;
+        const double opk2 = (1.0 + kmax) * (1.0 + kmax) * (1.0 + 2e-6);
+        const double twopi = 2.0 * Num<double>::pi;
+        double ftr = 0.5 * Num<double>::pi - w;
+        ftr -= twopi * rint(ftr / twopi);          // M(f + 2 pi) = M(f) + 2 pi
+        const float ftrf = float(ftr);
+        const float halfpi = 1.57079637f;          // pi/2 rounded up
+        double rmin = a * (1.0 - e);
+        float theta = halfpi;
+        bool never = false;
+        for (int it = 0; it < 3; ++it) {
+            const double num = opk2 / (rmin * rmin) - ci2;
+            if (num <= 0.0) { never = true; break; }
+            const double sn = si2 > 0.0 ? sqrt(num / si2) : 2.0;
+            theta = sn * (1.0 + 2e-7) >= 1.0 ? halfpi
+                                              : asinf(float(sn * (1.0 + 2e-7))) + 1e-6f;
+            if (e == 0.0) break;
+            // largest cos f over [f_tr - theta, f_tr + theta]: 1 if it holds
+            // a periapsis passage (|f_tr| <= theta after the reduction above),
+            // else at the nearer edge
+            const float cmax = fabsf(ftrf) <= theta + 1e-6f
+                                   ? 1.0f
+                                   : fminf(1.0f, fmaxf(cosf(ftrf - theta), cosf(ftrf + theta)) + 3e-7f);
+            const double rnew = a * (1.0 - e * e) / (1.0 + e * double(cmax));
+            if (rnew <= rmin) break;
+            rmin = rnew;
+        }
+        if (never) {
+            c.wn = 0.0;                  // no exposure is ever inside
         } else {
-            const double theta = asin(s);
-            const double ftr = 0.5 * Num<double>::pi - w;
-            const double beta = e / (1.0 + q);
+            const float ef = float(e);
+            const float beta = float(e / (1.0 + q));
             // mean anomaly as a continuous (unwrapped) function of the true
             // anomaly: E = f - 2 atan(beta sin f / (1 + beta cos f))
-            auto mean_of_true = [&](double f) {
-                double sf, cf;
-                sincos(f, &sf, &cf);
-                const double E = f - 2.0 * atan(beta * sf / (1.0 + beta * cf));
-                return E - e * sin(E);
+            auto mean_of_true = [&](float f) {
+                float sf, cf;
+                sincosf(f, &sf, &cf);
+                const float E = f - 2.0f * atanf(beta * sf / (1.0f + beta * cf));
+                return E - ef * sinf(E);
             };
-            const double m0 = mean_of_true(ftr);
+            const float m0 = mean_of_true(ftrf);
+            const float ml = mean_of_true(ftrf - theta);
+            const float mh = mean_of_true(ftrf + theta);
             const double inv2pi = 0.5 / Num<double>::pi;
-            // window in phase units (mean anomaly / 2 pi) around conjunction,
-            // widened by 1e-8 of a period on each side, more than the
-            // rounding of a phase t/P - t0/P of up to 1e7 periods
-            const double lo = (mean_of_true(ftr - theta) - m0) * inv2pi - 1e-8;
-            const double hi = (mean_of_true(ftr + theta) - m0) * inv2pi + 1e-8;
+            // dM/df peaks at (1 + e) sqrt((1 + e)/(1 - e)) (periapsis), which
+            // scales the float rounding of f into M
+            const double margin = 1e-6 * (2.0 + (1.0 + e) * sqrt((1.0 + e) / (1.0 - e)));
+            const double lo = double(ml - m0) * inv2pi - margin;
+            const double hi = double(mh - m0) * inv2pi + margin;
             if (hi - lo < 1.0) {
                 c.flo = lo;
                 c.wn = hi - lo;

@@ -11,14 +11,16 @@
 //               units, so the test is frac(phase - lo) < width);
 //   k_forward   one workgroup per (parameter vector, tile of 2048 times),
 //               lanes along time so loads of the shared time array and the
-//               stores of out[pv][t] are coalesced.  Pass 1 reduces each
-//               mid-exposure time to an offset from conjunction (FP64) and
-//               writes 1 for exposures entirely outside the window; if any
-//               exposure of the tile overlaps it, the workgroup builds the
-//               k-interpolated LD vectors of its parameter vector in LDS
-//               (Sect. 3.1.2) and pass 2 evaluates those exposures:
-//               per subsample, Kepler orbit -> z -> g-interpolation in LDS
-//               (Sect. 3.1.1) x lens area (Eq. 5) -> mean over subsamples.
+//               stores of out[pv][t] are coalesced; each wave64 owns 512
+//               consecutive times and runs alone.  Pass 1 reduces each
+//               mid-exposure time to an offset from conjunction (FP64),
+//               writes 1 for the exposures outside the window (on the
+//               aligned fast path for all of them, with 16-B stores) and
+//               flags the others; a wave with no flag ends there.
+//               Pass 2 evaluates the flagged exposures: per subsample,
+//               Kepler orbit -> z -> LD vector interpolated in k and g from
+//               the resident table (Sect. 3.1.1, Sect. 3.1.2) x lens area
+//               (Eq. 5) -> mean over subsamples.
 //
 // The kernels are templated on the bulk real type: double (RR_FP64) or float
 // (RR_MIXED: the time reduction stays FP64, the rest is FP32).
@@ -26,6 +28,9 @@
 
 namespace rr {
 namespace {
+
+static_assert(kTimesPerThread % 4 == 0 && kTimesPerThread <= 32,
+              "pass 1 packs 4 float or 2 double outputs per 16-B store");
 
 __global__ void k_pv_setup(const double* __restrict__ pv, int32_t npv,
                            int32_t npar, double k0, double k1,
@@ -35,112 +40,138 @@ __global__ void k_pv_setup(const double* __restrict__ pv, int32_t npv,
     out[ipv] = make_pv_const(pv + int64_t(ipv) * npar, npar - 6, k0, k1);
 }
 
-// The work of one workgroup: population row ipv, time tile `tile`.
+// The work of one workgroup: population row ipv, time tile `tile`.  Each
+// wave64 owns 64 kTimesPerThread consecutive exposures of the tile and works
+// on its own, with no workgroup barrier: a wave whose exposures all lie
+// outside the transit window stores ones and ends.
 template <typename R>
 __device__ inline void forward_block(const FwdJob& job, const LcInfo& lc, int ipv,
                                      int tile, const GridDev& g,
                                      const R* __restrict__ T,
-                                     const double* __restrict__ inv_istar, R* ldw) {
-    const int tid = threadIdx.x;
+                                     const double* __restrict__ inv_istar) {
+    constexpr int kSpan = 64 * kTimesPerThread;           // exposures per wave
+    const int lane = threadIdx.x & 63;
     const int npt = job.npt, npar = job.npar;
     const double* __restrict__ times = job.times;
     const int32_t* __restrict__ lcids = job.lcids;
     const double* __restrict__ pv = job.pv;
-    const int t_base = tile * kTile + tid;
+    // exposure r of this lane (pass 2 order, and pass 1 off the fast path)
+    const int w0 = tile * kTile + (threadIdx.x >> 6) * kSpan;
+    const int t_base = w0 + lane;
     R* __restrict__ orow = static_cast<R*>(job.out) + int64_t(ipv) * npt;
     const PvConst p = job.pvc[ipv];
 
     if (!(p.flags & kValid)) {
-        for (int j = 0; j < kTimesPerThread; ++j) {
-            const int it = t_base + j * kBlock;
+        for (int r = 0; r < kTimesPerThread; ++r) {
+            const int it = t_base + 64 * r;
             if (it < npt) orow[it] = R(NAN);
         }
         return;
     }
 
-    // Pass 1: exposures that cannot overlap the star get F = 1 now.
+    // Pass 1: exposures that cannot overlap the star get F = 1 now.  Bit r
+    // of `todo` marks exposure t_base + 64 r as one that may overlap it.
     uint32_t todo = 0;
-    const int tfirst = tile * kTile;
-    if (!lcids && tfirst + kTile <= npt) {
-        // Whole tile in range, one light curve: no bounds or light-curve
-        // checks; phase g = t/P + c0 with c0 = -t0/P - (window start) by one
-        // FMA; every output is written as 1 here and pass 2 overwrites the
-        // exposures that overlap the star.
-        const double* tp = times + tfirst + tid;
-        R* op = orow + tfirst + tid;
+    constexpr int kVec = 16 / int(sizeof(R));            // outputs per 16-B store
+    const bool vec = !lcids && w0 + kSpan <= npt &&
+                     ((reinterpret_cast<uintptr_t>(orow + w0) |
+                       reinterpret_cast<uintptr_t>(times)) & 15) == 0;
+    if (vec) {
+        // Whole span in range, one light curve, 16-B aligned: in group q the
+        // lane owns the kVec consecutive exposures w0 + 64 kVec q + kVec lane
+        // + v (16-B loads of times, one 16-B store of ones), with no bounds
+        // or light-curve checks.  Phase g = t/P + c0 with
+        // c0 = -t0/P - (window start) by one FMA.
+        typedef R RV __attribute__((ext_vector_type(kVec)));
+        constexpr int kGroups = kTimesPerThread / kVec;
         double tv[kTimesPerThread];
 #pragma unroll
-        for (int j = 0; j < kTimesPerThread; ++j) tv[j] = tp[j * kBlock];
+        for (int q = 0; q < kGroups; ++q) {
+            const double* tp = times + w0 + q * (64 * kVec) + lane * kVec;
+#pragma unroll
+            for (int v = 0; v < kVec; v += 2) {
+                const double2 d = *reinterpret_cast<const double2*>(tp + v);
+                tv[q * kVec + v] = d.x;
+                tv[q * kVec + v + 1] = d.y;
+            }
+        }
         const double hw = 0.5 * lc.exptime[0] * p.invP;
         const double c0 = -p.t0 * p.invP - (p.flo - hw);
         const double wn = p.wn + 2.0 * hw;
+        const RV ones = R(1);
+        uint32_t bits = 0;                                // bit q kVec + v
 #pragma unroll
-        for (int j = 0; j < kTimesPerThread; ++j) {
-            const double gph = fma(tv[j], p.invP, c0);
-            if (gph - floor(gph) < wn) todo |= 1u << j;
-            op[j * kBlock] = R(1);
+        for (int q = 0; q < kGroups; ++q) {
+#pragma unroll
+            for (int v = 0; v < kVec; ++v) {
+                const double gph = fma(tv[q * kVec + v], p.invP, c0);
+                if (gph - floor(gph) < wn) bits |= 1u << (q * kVec + v);
+            }
+            *reinterpret_cast<RV*>(orow + w0 + q * (64 * kVec) + lane * kVec) = ones;
+        }
+        if (!__any(bits != 0)) return;
+        // Regroup to pass 2's order: exposure w0 + 64 r + lane, r = q kVec + s,
+        // is bit q kVec + lane % kVec of lane (64 s + lane) / kVec.
+#pragma unroll
+        for (int sidx = 0; sidx < kVec; ++sidx) {
+            const uint32_t x = uint32_t(__shfl(int(bits), (64 * sidx + lane) / kVec));
+#pragma unroll
+            for (int q = 0; q < kGroups; ++q)
+                todo |= ((x >> (q * kVec + lane % kVec)) & 1u) << (q * kVec + sidx);
         }
     } else {
         double tv[kTimesPerThread];
         int lv[kTimesPerThread];
 #pragma unroll
-        for (int j = 0; j < kTimesPerThread; ++j) {
-            const int it = t_base + j * kBlock;
-            tv[j] = it < npt ? times[it] : 0.0;
-            lv[j] = (lcids && it < npt) ? lcids[it] : 0;
+        for (int r = 0; r < kTimesPerThread; ++r) {
+            const int it = t_base + 64 * r;
+            tv[r] = it < npt ? times[it] : 0.0;
+            lv[r] = (lcids && it < npt) ? lcids[it] : 0;
         }
         const double hw0 = 0.5 * lc.exptime[0] * p.invP;
 #pragma unroll
-        for (int j = 0; j < kTimesPerThread; ++j) {
-            const int it = t_base + j * kBlock;
+        for (int r = 0; r < kTimesPerThread; ++r) {
+            const int it = t_base + 64 * r;
             if (it >= npt) continue;
-            const int l = lv[j];
+            const int l = lv[r];
             if (l < 0 || l >= lc.nlc) { orow[it] = R(NAN); continue; }
             const double hw = lcids ? 0.5 * lc.exptime[l] * p.invP : hw0;
-            if (in_phase_window((tv[j] - p.t0) * p.invP, p, hw)) todo |= 1u << j;
+            if (in_phase_window((tv[r] - p.t0) * p.invP, p, hw)) todo |= 1u << r;
             else orow[it] = R(1);
         }
+        if (!__any(todo != 0)) return;
     }
-    // Workgroup vote: does any exposure of the tile overlap the window?
-    __shared__ int wave_any[kBlock / 64];
-    const int wany = __any(todo != 0);
-    if ((tid & 63) == 0) wave_any[tid >> 6] = wany;
-    __syncthreads();
-    bool any = false;
-#pragma unroll
-    for (int w = 0; w < kBlock / 64; ++w) any |= wave_any[w] != 0;
-    if (!any) return;
 
-    // k-interpolated LD-weighted vectors of this parameter vector, one per
-    // passband (Sect. 3.1.2): ldw = (1 - ak) T[ik] + ak T[ik+1].
-    for (int pb = 0; pb < g.npb; ++pb) {
-        const double u = (pv[int64_t(ipv) * npar + 6 + pb] - g.k0) / g.dk;
-        int ik = int(floor(u));
-        ik = ik < 0 ? 0 : (ik > g.nk - 2 ? g.nk - 2 : ik);
-        const R ak = R(u - ik);
-        const R* t0r = T + (int64_t(pb) * g.nk + ik) * g.ng;
-        for (int m = tid; m < g.ng; m += kBlock)
-            ldw[pb * g.ng + m] = (R(1) - ak) * t0r[m] + ak * t0r[g.ng + m];
-    }
-    __syncthreads();
-
-    // Pass 2: exposures that may overlap the star.
+    // Pass 2: exposures that may overlap the star.  The LD-weighted vector of
+    // the exposure's passband is interpolated in k on the fly (Sect. 3.1.2):
+    // ldw[m] = (1 - ak) T[pb][ik][m] + ak T[pb][ik+1][m], then in g.
     const OrbitR<R> orb(p);
     const R gscale = R(g.gscale);
+    int pb_cached = -1;
+    const R* t0r = T;
+    R ak = R(0), onepk = R(1), inv1pk = R(1), k = R(0), istar_inv = R(0);
     while (todo) {
-        const int j = __builtin_ctz(todo);
+        const int r = __builtin_ctz(todo);
         todo &= todo - 1;
-        const int it = t_base + j * kBlock;
+        const int it = t_base + 64 * r;
         const int l = lcids ? lcids[it] : 0;          // reloaded: keeps pass 1's
         const int pb = lc.pb[l];                      // registers free here
         const int nss = lc.nss[l];
         const double ex = lc.exptime[l];
         const double t = times[it];
-        const R k = R(pv[int64_t(ipv) * npar + 6 + pb]);
-        const R onepk = R(1) + k;
-        const R inv1pk = R(1) / onepk;
-        const R istar_inv = R(inv_istar[pb]);
-        const R* lw = ldw + pb * g.ng;
+        if (pb != pb_cached) {
+            pb_cached = pb;
+            const double kd = pv[int64_t(ipv) * npar + 6 + pb];
+            const double u = (kd - g.k0) / g.dk;
+            int ik = int(floor(u));
+            ik = ik < 0 ? 0 : (ik > g.nk - 2 ? g.nk - 2 : ik);
+            ak = R(u - ik);
+            t0r = T + (int64_t(pb) * g.nk + ik) * g.ng;
+            k = R(kd);
+            onepk = R(1) + k;
+            inv1pk = R(1) / onepk;
+            istar_inv = R(inv_istar[pb]);
+        }
         R acc = R(0);
         for (int s = 0; s < nss; ++s) {
             const double x = (t + ex * ((s + 0.5) / nss - 0.5)) - p.t0;
@@ -154,7 +185,9 @@ __device__ inline void forward_block(const FwdJob& job, const LcInfo& lc, int ip
             int m = int(v);
             m = m > g.ng - 2 ? g.ng - 2 : m;
             const R al = v - R(m);
-            const R ip = (R(1) - al) * lw[m] + al * lw[m + 1];
+            const R l0 = (R(1) - ak) * t0r[m] + ak * t0r[g.ng + m];
+            const R l1 = (R(1) - ak) * t0r[m + 1] + ak * t0r[g.ng + m + 1];
+            const R ip = (R(1) - al) * l0 + al * l1;
             acc += ip * lens_area<R>(R(1), k, z) * istar_inv;
         }
         orow[it] = R(1) - acc / R(nss);
@@ -166,10 +199,9 @@ template <typename R>
 __global__ __launch_bounds__(kBlock) void k_forward(FwdJob job, LcInfo lc, GridDev g,
                                                     const R* __restrict__ T,
                                                     const double* __restrict__ inv_istar) {
-    extern __shared__ unsigned char smem_raw[];
     const int ipv = job.pv0 + blockIdx.y;
     const int tile = blockIdx.x;
-    forward_block<R>(job, lc, ipv, tile, g, T, inv_istar, reinterpret_cast<R*>(smem_raw));
+    forward_block<R>(job, lc, ipv, tile, g, T, inv_istar);
 }
 
 // Grouped launch (serving): workgroup b belongs to the last job whose
@@ -178,7 +210,6 @@ template <typename R>
 __global__ __launch_bounds__(kBlock) void k_forward_jobs(JobTable jt, GridDev g,
                                                          const R* __restrict__ T,
                                                          const double* __restrict__ inv_istar) {
-    extern __shared__ unsigned char smem_raw[];
     const int b = blockIdx.x;
     int jj = 0;
     for (int q = 1; q < jt.njobs; ++q)
@@ -187,7 +218,7 @@ __global__ __launch_bounds__(kBlock) void k_forward_jobs(JobTable jt, GridDev g,
     const int local = b - job.block0;
     const int ipv = job.pv0 + local / job.ntiles;
     const int tile = local - (local / job.ntiles) * job.ntiles;
-    forward_block<R>(job, *job.lc, ipv, tile, g, T, inv_istar, reinterpret_cast<R*>(smem_raw));
+    forward_block<R>(job, *job.lc, ipv, tile, g, T, inv_istar);
 }
 
 __global__ void k_pv_setup_jobs(SetupTable st, double k0, double k1) {
@@ -231,15 +262,12 @@ hipError_t launch_forward(const rr_tables* t, const double* times,
     for (int32_t r0 = 0; r0 < npv; r0 += 65535) {
         job.pv0 = r0;
         const dim3 grid(unsigned(job.ntiles), unsigned(npv - r0 < 65535 ? npv - r0 : 65535));
-        if (precision == RR_FP64) {
-            const size_t lds = sizeof(double) * size_t(g.npb) * g.ng;
-            hipLaunchKernelGGL(k_forward<double>, grid, dim3(kBlock), lds, s, job, lc, g,
+        if (precision == RR_FP64)
+            hipLaunchKernelGGL(k_forward<double>, grid, dim3(kBlock), 0, s, job, lc, g,
                                t->T64, t->inv_istar);
-        } else {
-            const size_t lds = sizeof(float) * size_t(g.npb) * g.ng;
-            hipLaunchKernelGGL(k_forward<float>, grid, dim3(kBlock), lds, s, job, lc, g,
+        else
+            hipLaunchKernelGGL(k_forward<float>, grid, dim3(kBlock), 0, s, job, lc, g,
                                t->T32, t->inv_istar);
-        }
     }
     hipError_t e = hipGetLastError();
     if (e == hipSuccess && ev.after) e = hipEventRecord(ev.after, s);
@@ -250,15 +278,12 @@ hipError_t launch_forward_jobs(const rr_tables* t, const JobTable& jt, int32_t n
                                int32_t precision, hipStream_t s) {
     if (nblocks_total <= 0 || jt.njobs <= 0) return hipSuccess;
     const GridDev g = grid_dev(t);
-    if (precision == RR_FP64) {
-        const size_t lds = sizeof(double) * size_t(g.npb) * g.ng;
+    if (precision == RR_FP64)
         hipLaunchKernelGGL(k_forward_jobs<double>, dim3(unsigned(nblocks_total)), dim3(kBlock),
-                           lds, s, jt, g, t->T64, t->inv_istar);
-    } else {
-        const size_t lds = sizeof(float) * size_t(g.npb) * g.ng;
+                           0, s, jt, g, t->T64, t->inv_istar);
+    else
         hipLaunchKernelGGL(k_forward_jobs<float>, dim3(unsigned(nblocks_total)), dim3(kBlock),
-                           lds, s, jt, g, t->T32, t->inv_istar);
-    }
+                           0, s, jt, g, t->T32, t->inv_istar);
     return hipGetLastError();
 }
 

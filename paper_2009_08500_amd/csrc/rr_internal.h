@@ -21,8 +21,8 @@ namespace rr {
 constexpr int kBlock = 256;          // threads per workgroup (4 wave64)
 constexpr int kTimesPerThread = RR_TIMES_PER_THREAD;   // times per thread
 constexpr int kTile = kBlock * kTimesPerThread;
-constexpr int kMaxLdsBytes = 64 * 1024;   // LDS budget for the k-interpolated
-                                          // LD vectors of one workgroup
+constexpr int kMaxLdsBytes = 64 * 1024;   // LDS budget for the adjoint's
+                                          // per-workgroup tables
 
 // Per-parameter-vector orbit constants, computed once per call (FP64).
 struct PvConst {

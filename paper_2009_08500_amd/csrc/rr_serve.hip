@@ -322,10 +322,6 @@ RR_API int rr_server_create(const rr_tables* t, int64_t budget_bytes, int32_t ma
     if (!t) { set_error("tables handle is NULL"); return RR_EINVAL; }
     if (budget_bytes < (1 << 20)) { set_error("budget must be >= 1 MiB"); return RR_EINVAL; }
     if (max_tick_blocks < 1) { set_error("max_tick_blocks must be >= 1"); return RR_EINVAL; }
-    if (size_t(t->npb) * t->grid.ng * sizeof(double) > size_t(kMaxLdsBytes)) {
-        set_error("npb * ng LD vectors exceed the 64 KiB LDS budget");
-        return RR_ELIMIT;
-    }
     int cur = -1;
     hipError_t e = hipGetDevice(&cur);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
