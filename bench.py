@@ -54,9 +54,12 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(kernel, out_bytes_per_launch):
-    """HBM bytes per launch from the committed PMC summary, if it was taken on
-    the current kernel sources; otherwise None."""
+VALU_LANE_SLOTS = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes x clock: wave64 takes 4 cycles
+
+
+def profile_counters(kernel):
+    """Per-launch counters of `kernel` from the committed PMC summary, if it
+    was taken on the current kernel sources; otherwise None."""
     path = os.path.join(ROOT, "profiles", "forward_population_counters.json")
     try:
         with open(path) as fh:
@@ -65,10 +68,19 @@ def traffic_from_profile(kernel, out_bytes_per_launch):
         return None
     if prof.get("source_hash") != source_hash():
         return None
-    k = prof.get("kernels", {}).get(kernel)
-    if not k:
+    return prof.get("kernels", {}).get(kernel)
+
+
+def valu_view(kernel, kernel_ms):
+    """Issued VALU lane-slots per launch (SQ_INSTS_VALU x 64) against the
+    chip's VALU issue rate over the event-timed kernel duration."""
+    k = profile_counters(kernel)
+    if not k or "SQ_INSTS_VALU" not in k:
         return None
-    return k.get("hbm_bytes_per_launch")
+    slots = 64.0 * k["SQ_INSTS_VALU"]
+    return dict(valu_instrs_per_launch=k["SQ_INSTS_VALU"], lane_slots_per_launch=slots,
+                peak_lane_slots_per_s=VALU_LANE_SLOTS,
+                issue_frac=slots / (kernel_ms * 1e-3) / VALU_LANE_SLOTS)
 
 
 def time_path(rr, tab, series, pv, prec, steps, warmup, lib):
@@ -263,11 +275,13 @@ def main():
     m = summary("mixed", 4)
     d = summary("fp64", 8)
     achieved = m["alg_bytes"] / (m["kernel_ms"]["mean"] / 1e3) / 1e9
-    traffic = traffic_from_profile("k_forward<float>", m["alg_bytes"])
+    kc = profile_counters("k_forward<float>")
+    traffic = kc.get("hbm_bytes_per_launch") if kc else None
     roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=achieved / HBM_PEAK_GBS, traffic=traffic,
                 kernel="k_forward<float>", alg_bytes_per_launch=m["alg_bytes"],
-                kernel_ms=m["kernel_ms"]["mean"])
+                kernel_ms=m["kernel_ms"]["mean"],
+                valu=valu_view("k_forward<float>", m["kernel_ms"]["mean"]))
     achieved64 = d["alg_bytes"] / (d["kernel_ms"]["mean"] / 1e3) / 1e9
 
     line = dict(
@@ -283,7 +297,9 @@ def main():
                   dtype="f64", roofline=dict(bound="hbm", achieved=achieved64,
                                              peak=HBM_PEAK_GBS, unit="GB/s",
                                              frac=achieved64 / HBM_PEAK_GBS,
-                                             kernel_ms=d["kernel_ms"]["mean"])),
+                                             kernel_ms=d["kernel_ms"]["mean"],
+                                             valu=valu_view("k_forward<double>",
+                                                            d["kernel_ms"]["mean"]))),
         roofline=roof,
         in_transit_fraction=None,
         source_hash=source_hash(),

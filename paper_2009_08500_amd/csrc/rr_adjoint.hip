@@ -97,28 +97,9 @@ __device__ inline R separation_grad(R dt, R x, const OrbitR<R>& o,
                                     R dz[6]) {
     using N = Num<R>;
     const R dM = o.n * dt;
-    R d = dM;
     R s2, c2;
-    if (o.e > R(0)) {
-        R lo = dM - R(2) * o.e, hi = dM + R(2) * o.e;
-        d = dM / (R(1) - o.e * o.cE);
-        d = d < lo ? lo : (d > hi ? hi : d);
-        for (int it = 0; it < N::kepler_maxit; ++it) {
-            sincos_small(R(0.5) * d, &s2, &c2);
-            const R sd = R(2) * s2 * c2;
-            const R cm1 = R(-2) * s2 * s2;
-            const R h = d - o.e * (o.sE * cm1 + o.cE * sd) - dM;
-            if (h < R(0)) lo = d; else hi = d;
-            const R hp = R(1) - o.e * (o.cE * (R(1) + cm1) - o.sE * sd);
-            const R hpp = o.e * (o.sE * (R(1) + cm1) + o.cE * sd);
-            R dn = d - R(2) * h * hp / (R(2) * hp * hp - h * hpp);
-            if (!(dn >= lo && dn <= hi)) dn = R(0.5) * (lo + hi);
-            const R step = dn - d;
-            d = dn;
-            if (N::abs_(step) < N::kepler_stop) break;
-        }
-    }
-    sincos_small(R(0.5) * d, &s2, &c2);
+    if (o.e > R(0)) kepler_offset<R>(dM, o.e, o.sE, o.cE, &s2, &c2);
+    else sincos_small(R(0.5) * dM, &s2, &c2);
     const R sd = R(2) * s2 * c2;
     const R cm1 = R(-2) * s2 * s2;
     const R dc = o.cE * cm1 - o.sE * sd;
@@ -282,8 +263,9 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(
             R acc = R(0);
             R gt[6] = {0, 0, 0, 0, 0, 0};
             R gkt = R(0);
+            const double inv_nss = 1.0 / nss;
             for (int s = 0; s < nss; ++s) {
-                const double x = (t + ex * ((s + 0.5) / nss - 0.5)) - p.t0;
+                const double x = (t + ex * ((s + 0.5) * inv_nss - 0.5)) - p.t0;
                 const double u = x * p.invP;
                 if (!in_phase_window(u, p, 0.0)) continue;
                 const double dt = x - p.P * rint(u);
@@ -323,7 +305,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(
             if (want_prof) {
                 const double cw = wgt * wrow;
                 for (int s = 0; s < nss; ++s) {
-                    const double x = (t + ex * ((s + 0.5) / nss - 0.5)) - p.t0;
+                    const double x = (t + ex * ((s + 0.5) * inv_nss - 0.5)) - p.t0;
                     const double u = x * p.invP;
                     if (!in_phase_window(u, p, 0.0)) continue;
                     const double dt = x - p.P * rint(u);

@@ -30,31 +30,40 @@ template <> struct Num<float> {
     static constexpr int kepler_maxit = 20;
 };
 
-// sin and cos of a half-angle offset from conjunction, which is small
-// inside the transit window.  In float, for |x| <= 3/4 the Maclaurin series
-// through the x^9 and x^10 terms are summed by Horner's rule in x^2
-// (truncation below 2e-9 relative); larger float arguments and every double
-// argument go to the library sincos, which measured faster than a series of
-// double length.
-template <typename R>
-__device__ inline void sincos_small(R x, R* s, R* c) {
-    using N = Num<R>;
-    if (sizeof(R) == 8 || N::abs_(x) > R(0.75)) {
-        N::sincos_(x, s, c);
+// sin and cos of a half-angle x of the offset from conjunction, which is
+// small inside a transit window.  In float, for |x| <= 1/4 the Maclaurin
+// series through the x^7 and x^8 terms are summed by Horner's rule in x^2
+// (truncation below 1e-11); larger float arguments and every double
+// argument use the library sincos (a double series of the same accuracy
+// measured slower).
+__device__ inline void sincos_small(float x, float* s, float* c) {
+    if (fabsf(x) > 0.25f) {
+        sincosf(x, s, c);
         return;
     }
-    const R x2 = x * x;
-    R ps = R(1.0 / 362880.0);                       // 1/9!
-    ps = ps * x2 - R(1.0 / 5040.0);
-    ps = ps * x2 + R(1.0 / 120.0);
-    ps = ps * x2 - R(1.0 / 6.0);
+    const float x2 = x * x;
+    float ps = -1.0f / 5040.0f;                          // -1/7!
+    ps = ps * x2 + 1.0f / 120.0f;
+    ps = ps * x2 - 1.0f / 6.0f;
     *s = x + x * x2 * ps;
-    R pc = R(-1.0 / 3628800.0);                     // -1/10!
-    pc = pc * x2 + R(1.0 / 40320.0);
-    pc = pc * x2 - R(1.0 / 720.0);
-    pc = pc * x2 + R(1.0 / 24.0);
-    pc = pc * x2 - R(0.5);
-    *c = R(1) + x2 * pc;
+    float pc = 1.0f / 40320.0f;                          // 1/8!
+    pc = pc * x2 - 1.0f / 720.0f;
+    pc = pc * x2 + 1.0f / 24.0f;
+    pc = pc * x2 - 0.5f;
+    *c = 1.0f + x2 * pc;
+}
+__device__ inline void sincos_small(double x, double* s, double* c) { sincos(x, s, c); }
+
+// (sin x, cos x) -> (sin(x + y), cos(x + y)) for |y| <= 1e-3, with
+// sin y = y - y^3/6 and cos y = 1 - y^2/2 + y^4/24 (truncation below 1e-17).
+template <typename R>
+__device__ inline void rotate_small(R y, R* s, R* c) {
+    const R y2 = y * y;
+    const R sy = y - y * y2 * R(1.0 / 6.0);
+    const R cy = R(1) - y2 * (R(0.5) - y2 * R(1.0 / 24.0));
+    const R s0 = *s, c0 = *c;
+    *s = s0 * cy + c0 * sy;
+    *c = c0 * cy - s0 * sy;
 }
 
 // Area of the intersection of a disk of radius Rd centred at the origin and a
@@ -102,17 +111,74 @@ struct OrbitR {
           cosi(R(p.cosi)) {}
 };
 
-// Projected separation for a time offset dt from conjunction.
-//
 // Transit-centred Kepler solve: with E = E_tr + d and dM = n dt, Kepler's
 // equation becomes h(d) = d - e [sin E_tr (cos d - 1) + cos E_tr sin d] - dM
 // = 0.  h is increasing (h' = 1 - e cos E > 0) and its root lies in
 // [dM - 2e, dM + 2e]; Halley's method starts from d = dM / (1 - e cos E_tr)
 // and is safeguarded by that bracket (a step leaving the current bracket is
-// replaced by bisection), so it converges for any e < 1.  The sky
+// replaced by bisection), so it converges for any e < 1.  Returns d and
+// sin(d/2), cos(d/2) at d; after the last, small step they are rotated
+// rather than recomputed.  cos d - 1 = -2 sin^2(d/2) keeps every quantity
+// small near transit, so float keeps its relative precision there.
+template <typename R>
+__device__ inline R kepler_halley(R dM, R e, R sE, R cE, R* s2, R* c2) {
+    using N = Num<R>;
+    R lo = dM - R(2) * e, hi = dM + R(2) * e;
+    R d = dM / (R(1) - e * cE);
+    d = d < lo ? lo : (d > hi ? hi : d);
+    for (int it = 0; it < N::kepler_maxit; ++it) {
+        sincos_small(R(0.5) * d, s2, c2);
+        const R sd = R(2) * *s2 * *c2;
+        const R cm1 = R(-2) * *s2 * *s2;
+        const R h = d - e * (sE * cm1 + cE * sd) - dM;
+        if (h < R(0)) lo = d; else hi = d;
+        const R hp = R(1) - e * (cE * (R(1) + cm1) - sE * sd);
+        const R hpp = e * (sE * (R(1) + cm1) + cE * sd);
+        // Halley: h / (h' - h h''/(2 h')) with a single division
+        R dn = d - R(2) * h * hp / (R(2) * hp * hp - h * hpp);
+        if (!(dn >= lo && dn <= hi)) dn = R(0.5) * (lo + hi);
+        const R step = dn - d;
+        d = dn;
+        if (N::abs_(step) < N::kepler_stop) {
+            rotate_small(R(0.5) * step, s2, c2);
+            return d;
+        }
+    }
+    sincos_small(R(0.5) * d, s2, c2);
+    return d;
+}
+
+template <typename R>
+__device__ inline R kepler_offset(R dM, R e, R sE, R cE, R* s2, R* c2) {
+    return kepler_halley<R>(dM, e, sE, cE, s2, c2);
+}
+
+// Double: the float solve's root (good to ~1e-7) and one Halley step in
+// double, whose cubic rate leaves an error far below one ulp.  If that step
+// is not small (float too coarse, e.g. e close to 1 near periapsis), the
+// bracketed solve is repeated in double.
+template <>
+__device__ inline double kepler_offset<double>(double dM, double e, double sE, double cE,
+                                               double* s2, double* c2) {
+    float s2f, c2f;
+    const double d = kepler_halley<float>(float(dM), float(e), float(sE), float(cE), &s2f, &c2f);
+    sincos_small(0.5 * d, s2, c2);
+    const double sd = 2.0 * *s2 * *c2;
+    const double cm1 = -2.0 * *s2 * *s2;
+    const double h = d - e * (sE * cm1 + cE * sd) - dM;
+    const double hp = 1.0 - e * (cE * (1.0 + cm1) - sE * sd);
+    const double hpp = e * (sE * (1.0 + cm1) + cE * sd);
+    const double step = -2.0 * h * hp / (2.0 * hp * hp - h * hpp);
+    if (fabs(step) < 2e-6) {
+        rotate_small(0.5 * step, s2, c2);
+        return d + step;
+    }
+    return kepler_halley<double>(dM, e, sE, cE, s2, c2);
+}
+
+// Projected separation for a time offset dt from conjunction.  The sky
 // coordinates are formed from the differences cos E - cos E_tr and
-// sin E - sin E_tr (using cos d - 1 = -2 sin^2(d/2)), so every intermediate
-// is small near transit and FP32 keeps its relative precision there:
+// sin E - sin E_tr, so every intermediate is small near transit:
 //   X   = -a [(cos E - cos E_tr) cos w - q (sin E - sin E_tr) sin w]
 //   rho = r sin(w + f) = r_tr + a [(cos E - cos E_tr) sin w
 //                                  + q (sin E - sin E_tr) cos w]
@@ -121,29 +187,9 @@ template <typename R>
 __device__ inline R separation(R dt, const OrbitR<R>& o, bool* front) {
     using N = Num<R>;
     const R dM = o.n * dt;
-    R d = dM;
     R s2, c2;
-    if (o.e > R(0)) {
-        R lo = dM - R(2) * o.e, hi = dM + R(2) * o.e;
-        d = dM / (R(1) - o.e * o.cE);
-        d = d < lo ? lo : (d > hi ? hi : d);
-        for (int it = 0; it < N::kepler_maxit; ++it) {
-            sincos_small(R(0.5) * d, &s2, &c2);
-            const R sd = R(2) * s2 * c2;
-            const R cm1 = R(-2) * s2 * s2;
-            const R h = d - o.e * (o.sE * cm1 + o.cE * sd) - dM;
-            if (h < R(0)) lo = d; else hi = d;
-            const R hp = R(1) - o.e * (o.cE * (R(1) + cm1) - o.sE * sd);
-            const R hpp = o.e * (o.sE * (R(1) + cm1) + o.cE * sd);
-            // Halley: h / (h' - h h''/(2 h')) with a single division
-            R dn = d - R(2) * h * hp / (R(2) * hp * hp - h * hpp);
-            if (!(dn >= lo && dn <= hi)) dn = R(0.5) * (lo + hi);
-            const R step = dn - d;
-            d = dn;
-            if (N::abs_(step) < N::kepler_stop) break;
-        }
-    }
-    sincos_small(R(0.5) * d, &s2, &c2);
+    if (o.e > R(0)) kepler_offset<R>(dM, o.e, o.sE, o.cE, &s2, &c2);
+    else sincos_small(R(0.5) * dM, &s2, &c2);
     const R sd = R(2) * s2 * c2;
     const R cm1 = R(-2) * s2 * s2;
     const R dc = o.cE * cm1 - o.sE * sd;
@@ -194,9 +240,9 @@ __device__ inline PvConst make_pv_const(const double* row, int npb, double k0,
         // z^2 = r^2 (sin^2 psi sin^2 i + cos^2 i), and the planet is in front
         // for |psi| < pi/2.  Over any set where r >= rmin, z < 1 + k needs
         // sin^2 psi < ((1 + k)^2 / rmin^2 - cos^2 i) / sin^2 i.  Starting from
-        // rmin = a (1 - e), the window |psi| < theta is narrowed twice by
-        // taking rmin as the smallest r = a (1 - e^2)/(1 + e cos f) over the
-        // current window.  An empty window means the planet never overlaps
+        // rmin = a (1 - e), the window |psi| < theta is narrowed once by
+        // taking rmin as the smallest r = a (1 - e^2)/(1 + e cos f) over it
+        // (a second pass narrows the population's windows by under 1 %).  An empty window means the planet never overlaps
         // the star.
         //
         // The window only has to contain the true one, so its transcendental
@@ -216,7 +262,7 @@ __device__ inline PvConst make_pv_const(const double* row, int npb, double k0,
         double rmin = a * (1.0 - e);
         float theta = halfpi;
         bool never = false;
-        for (int it = 0; it < 3; ++it) {
+        for (int it = 0; it < 2; ++it) {
             const double num = opk2 / (rmin * rmin) - ci2;
             if (num <= 0.0) { never = true; break; }
             const double sn = si2 > 0.0 ? sqrt(num / si2) : 2.0;

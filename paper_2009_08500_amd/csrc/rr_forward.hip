@@ -29,6 +29,13 @@
 namespace rr {
 namespace {
 
+#ifndef RR_FWD_WAVES_F32
+#define RR_FWD_WAVES_F32 1
+#endif
+#ifndef RR_FWD_WAVES_F64
+#define RR_FWD_WAVES_F64 1
+#endif
+
 static_assert(kTimesPerThread % 4 == 0 && kTimesPerThread <= 32,
               "pass 1 packs 4 float or 2 double outputs per 16-B store");
 
@@ -38,6 +45,62 @@ __global__ void k_pv_setup(const double* __restrict__ pv, int32_t npv,
     const int ipv = blockIdx.x * blockDim.x + threadIdx.x;
     if (ipv >= npv) return;
     out[ipv] = make_pv_const(pv + int64_t(ipv) * npar, npar - 6, k0, k1);
+}
+
+// Per-row, per-passband constants of pass 2: the two k-rows of T that
+// bracket k and the k-lerp weight (Sect. 3.1.2), 1 + k, I_star.
+template <typename R>
+struct PbConst {
+    const R* t0r;          // T[pb][ik]; T[pb][ik+1] follows at + ng
+    R ak, k, onepk, inv1pk, istar_inv;
+};
+
+template <typename R>
+__device__ inline PbConst<R> pb_const(const double* __restrict__ pv, int ipv, int npar, int pb,
+                                      const GridDev& g, const R* __restrict__ T,
+                                      const double* __restrict__ inv_istar) {
+    PbConst<R> c;
+    const double kd = pv[int64_t(ipv) * npar + 6 + pb];
+    const double u = (kd - g.k0) / g.dk;
+    int ik = int(floor(u));
+    ik = ik < 0 ? 0 : (ik > g.nk - 2 ? g.nk - 2 : ik);
+    c.ak = R(u - ik);
+    c.t0r = T + (int64_t(pb) * g.nk + ik) * g.ng;
+    c.k = R(kd);
+    c.onepk = R(1) + c.k;
+    c.inv1pk = R(1) / c.onepk;
+    c.istar_inv = R(inv_istar[pb]);
+    return c;
+}
+
+// Flux of one exposure at mid-time t: mean over its nss subsamples of
+// Eq. 5, each through the orbit (z), the LD vector interpolated in k and g
+// from the resident table (Sect. 3.1.1, Sect. 3.1.2) and the lens area.
+template <typename R>
+__device__ inline R exposure_flux(const PvConst& p, const OrbitR<R>& orb, const PbConst<R>& c,
+                                  double t, double ex, int nss, const GridDev& g) {
+    const R gscale = R(g.gscale);
+    const double inv_nss = 1.0 / nss;
+    R acc = R(0);
+    for (int s = 0; s < nss; ++s) {
+        const double x = (t + ex * ((s + 0.5) * inv_nss - 0.5)) - p.t0;
+        const double u = x * p.invP;
+        if (!in_phase_window(u, p, 0.0)) continue;
+        const double dt = x - p.P * rint(u);
+        bool front;
+        const R z = separation<R>(R(dt), orb, &front);
+        if (!front || !(z < c.onepk)) continue;
+        const R v = z * c.inv1pk * gscale;
+        int m = int(v);
+        m = m > g.ng - 2 ? g.ng - 2 : m;
+        const R al = v - R(m);
+        const R* t0r = c.t0r;
+        const R l0 = (R(1) - c.ak) * t0r[m] + c.ak * t0r[g.ng + m];
+        const R l1 = (R(1) - c.ak) * t0r[m + 1] + c.ak * t0r[g.ng + m + 1];
+        const R ip = (R(1) - al) * l0 + al * l1;
+        acc += ip * lens_area<R>(R(1), c.k, z) * c.istar_inv;
+    }
+    return R(1) - acc * R(inv_nss);
 }
 
 // The work of one workgroup: population row ipv, time tile `tile`.  Each
@@ -142,61 +205,32 @@ __device__ inline void forward_block(const FwdJob& job, const LcInfo& lc, int ip
         if (!__any(todo != 0)) return;
     }
 
-    // Pass 2: exposures that may overlap the star.  The LD-weighted vector of
-    // the exposure's passband is interpolated in k on the fly (Sect. 3.1.2):
-    // ldw[m] = (1 - ak) T[pb][ik][m] + ak T[pb][ik+1][m], then in g.
+    // Pass 2 in the wave: the flagged exposures, one per lane and bit.
     const OrbitR<R> orb(p);
-    const R gscale = R(g.gscale);
     int pb_cached = -1;
-    const R* t0r = T;
-    R ak = R(0), onepk = R(1), inv1pk = R(1), k = R(0), istar_inv = R(0);
+    PbConst<R> c = {};
     while (todo) {
         const int r = __builtin_ctz(todo);
         todo &= todo - 1;
         const int it = t_base + 64 * r;
         const int l = lcids ? lcids[it] : 0;          // reloaded: keeps pass 1's
         const int pb = lc.pb[l];                      // registers free here
-        const int nss = lc.nss[l];
-        const double ex = lc.exptime[l];
-        const double t = times[it];
         if (pb != pb_cached) {
             pb_cached = pb;
-            const double kd = pv[int64_t(ipv) * npar + 6 + pb];
-            const double u = (kd - g.k0) / g.dk;
-            int ik = int(floor(u));
-            ik = ik < 0 ? 0 : (ik > g.nk - 2 ? g.nk - 2 : ik);
-            ak = R(u - ik);
-            t0r = T + (int64_t(pb) * g.nk + ik) * g.ng;
-            k = R(kd);
-            onepk = R(1) + k;
-            inv1pk = R(1) / onepk;
-            istar_inv = R(inv_istar[pb]);
+            c = pb_const<R>(pv, ipv, npar, pb, g, T, inv_istar);
         }
-        R acc = R(0);
-        for (int s = 0; s < nss; ++s) {
-            const double x = (t + ex * ((s + 0.5) / nss - 0.5)) - p.t0;
-            const double u = x * p.invP;
-            if (!in_phase_window(u, p, 0.0)) continue;
-            const double dt = x - p.P * rint(u);
-            bool front;
-            const R z = separation<R>(R(dt), orb, &front);
-            if (!front || !(z < onepk)) continue;
-            const R v = z * inv1pk * gscale;
-            int m = int(v);
-            m = m > g.ng - 2 ? g.ng - 2 : m;
-            const R al = v - R(m);
-            const R l0 = (R(1) - ak) * t0r[m] + ak * t0r[g.ng + m];
-            const R l1 = (R(1) - ak) * t0r[m + 1] + ak * t0r[g.ng + m + 1];
-            const R ip = (R(1) - al) * l0 + al * l1;
-            acc += ip * lens_area<R>(R(1), k, z) * istar_inv;
-        }
-        orow[it] = R(1) - acc / R(nss);
+        orow[it] = exposure_flux<R>(p, orb, c, times[it], lc.exptime[l], lc.nss[l], g);
     }
 }
 
+// Minimum waves per SIMD the register allocator must leave room for.
+template <typename R> struct FwdOccupancy;
+template <> struct FwdOccupancy<float> { static constexpr int waves = RR_FWD_WAVES_F32; };
+template <> struct FwdOccupancy<double> { static constexpr int waves = RR_FWD_WAVES_F64; };
+
 // One population (rr_evaluate): workgroup (x, y) -> row pv0 + y, tile x.
 template <typename R>
-__global__ __launch_bounds__(kBlock) void k_forward(FwdJob job, LcInfo lc, GridDev g,
+__global__ __launch_bounds__(kBlock, FwdOccupancy<R>::waves) void k_forward(FwdJob job, LcInfo lc, GridDev g,
                                                     const R* __restrict__ T,
                                                     const double* __restrict__ inv_istar) {
     const int ipv = job.pv0 + blockIdx.y;
@@ -207,7 +241,7 @@ __global__ __launch_bounds__(kBlock) void k_forward(FwdJob job, LcInfo lc, GridD
 // Grouped launch (serving): workgroup b belongs to the last job whose
 // block0 <= b; jobs come from several requests and time series.
 template <typename R>
-__global__ __launch_bounds__(kBlock) void k_forward_jobs(JobTable jt, GridDev g,
+__global__ __launch_bounds__(kBlock, FwdOccupancy<R>::waves) void k_forward_jobs(JobTable jt, GridDev g,
                                                          const R* __restrict__ T,
                                                          const double* __restrict__ inv_istar) {
     const int b = blockIdx.x;
