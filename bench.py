@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=240)
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the heterogeneous-series and log-likelihood legs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy --steps times "
                          "(the reference kernel for scaling HBM byte counters)")
@@ -154,6 +156,112 @@ def cpu_baseline(w, grid, budget_s, gpu_out64, gpu_out32):
     return dict(value=pts / t_used, unit="points/s", cores=1, kind="oracle", sample=sample), \
         dict(rows_checked=min(done_rows, npv), max_abs_err_fp64=err64,
              max_abs_err_mixed_ppm=err32 * 1e6)
+
+
+def heterogeneous_leg(rr, wl, steps, warmup, lib):
+    """Four passbands with their own profiles and chromatic k, two 30-min
+    light curves with nss = 10 and two 2-min ones with nss = 1 over 27 d,
+    256 rows: subsamples/s for both precisions, and the error of every
+    output against the oracle (same grid)."""
+    import numpy as np
+    import torch
+    from oracle import roadrunner as orr
+    w = wl.heterogeneous(npv=256)
+    grid = wl.DEFAULT_GRID
+    tab = rr.Tables(w["mu_s"], w["I_s"], grid)
+    ser = rr.TimeSeries(w["times"], w["lcids"], w["pbids"], w["nss"], w["exptimes"])
+    pv = torch.as_tensor(w["pv"], device="cuda")
+    npv = pv.shape[0]
+    subs = npv * int(np.sum(w["nss"][w["lcids"]]))
+    res = dict(workload="heterogeneous: 256 rows, 4 passbands, 2 x 30-min LCs (nss 10) + "
+                        "2 x 2-min LCs (nss 1) over 27 d", npv=npv, npt=int(w["times"].size),
+               subsamples_per_call=subs)
+    outs = {}
+    for prec in ("mixed", "fp64"):
+        wall, step_ms, kern_ms, out = time_path(rr, tab, ser, pv, prec, steps, warmup, lib)
+        ms = 1e3 * wall / steps
+        res[prec] = dict(subsamples_per_s=subs / (ms / 1e3), ms_per_step=ms,
+                         kernel_ms=float(np.mean(kern_ms)),
+                         latency_ms=dict(p50=pct(step_ms, 50), p99=pct(step_ms, 99)))
+        outs[prec] = out.cpu().numpy().astype(np.float64)
+    otab = orr.Tables(w["mu_s"], w["I_s"], **grid)
+    ref = orr.evaluate(otab, w["times"], w["pv"], lcids=w["lcids"], pbids=w["pbids"],
+                       nss=w["nss"], exptimes=w["exptimes"])
+    res["accuracy_vs_oracle"] = dict(rows_checked=npv,
+                                     max_abs_err_fp64=float(np.abs(outs["fp64"] - ref).max()),
+                                     max_abs_err_mixed_ppm=float(np.abs(outs["mixed"] - ref).max()) * 1e6)
+    return res
+
+
+def loglik_leg(rr, wl, steps, warmup):
+    """Gaussian log-likelihood and its adjoint for 1024 walkers around a truth
+    vector, 50 000 times at 2-min cadence with nss = 5 (data = the oracle's
+    light curve at the truth + seeded 200 ppm noise): subsamples/s of
+    rr_loglik_grad (logL and the parameter gradients) for both precisions,
+    the time of a full autograd step through the power-2 LD coefficients,
+    and the errors of 16 walkers against the oracle's analytic gradient."""
+    import numpy as np
+    import torch
+    from oracle import gradient as ogr
+    from oracle import roadrunner as orr
+    w = wl.loglik_walkers()
+    grid = wl.DEFAULT_GRID
+    otab = orr.Tables(w["mu_s"], w["I_s"], **grid)
+    obs = orr.evaluate(otab, w["times"], w["truth"][None, :], nss=w["nss"],
+                       exptimes=w["exptimes"])[0] + w["noise"]
+    tab = rr.Tables(w["mu_s"], w["I_s"], grid)
+    ser = rr.TimeSeries(w["times"], nss=w["nss"], exptimes=w["exptimes"])
+    pv = torch.as_tensor(w["pv"], device="cuda")
+    npv = pv.shape[0]
+    subs = npv * int(w["times"].size) * int(w["nss"][0])
+    res = dict(workload="log-likelihood + gradient: 1024 walkers, 50 000 times at 2 min, nss 5",
+               npv=npv, npt=int(w["times"].size), nss=int(w["nss"][0]),
+               subsamples_per_call=subs)
+    nchk = 16
+    for prec in ("mixed", "fp64"):
+        obs_d = torch.as_tensor(obs, device="cuda",
+                                dtype=torch.float64 if prec == "fp64" else torch.float32)
+        for _ in range(warmup):
+            rr.loglik_grad(tab, ser, pv, obs_d, w["sigma"], prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ll, g, _ = rr.loglik_grad(tab, ser, pv, obs_d, w["sigma"], prec)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / steps
+        ll, g = ll.cpu().numpy(), g.cpu().numpy()
+        obs_in = obs if prec == "fp64" else obs.astype(np.float32).astype(np.float64)
+        oll, og, _ = ogr.loglik_grad(otab, w["times"], w["pv"][:nchk], obs_in, w["sigma"],
+                                     nss=w["nss"], exptimes=w["exptimes"], want_profile=False)
+        scale = np.abs(og).max(axis=1, keepdims=True)
+        res[prec] = dict(subsamples_per_s=subs / (ms / 1e3), ms_per_step=ms,
+                         walkers_checked=nchk,
+                         max_rel_err_logl=float(np.max(np.abs(ll[:nchk] - oll) / np.abs(oll))),
+                         max_rel_err_grad=float(np.max(np.abs(g[:nchk] - og) / scale)))
+    # one autograd step: profile from (c, alpha) in torch -> logL -> backward
+    mu = torch.as_tensor(w["mu_s"], device="cuda")
+    pos = mu > 0
+    logmu = torch.log(torch.where(pos, mu, torch.ones_like(mu)))
+    c = torch.tensor(w["ld_c"], device="cuda", dtype=torch.float64, requires_grad=True)
+    al = torch.tensor(w["ld_alpha"], device="cuda", dtype=torch.float64, requires_grad=True)
+    pvg = pv.clone().requires_grad_(True)
+    obs_d = torch.as_tensor(obs, device="cuda", dtype=torch.float32)
+
+    def step():
+        mu_al = torch.where(pos, torch.exp(al * logmu), torch.zeros_like(mu))
+        prof = (1.0 - c * (1.0 - mu_al))[None, :]
+        ll = rr.RRLogLik.apply(pvg, prof, tab, ser, obs_d, w["sigma"], "mixed")
+        ll.sum().backward()
+
+    for _ in range(2):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(max(2, steps // 2)):
+        step()
+    torch.cuda.synchronize()
+    res["autograd_step_ms_mixed"] = 1e3 * (time.perf_counter() - t0) / max(2, steps // 2)
+    return res
 
 
 def serving_leg(rr, wl, nreq):
@@ -309,6 +417,9 @@ def main():
     line["in_transit_fraction"] = float(np.mean(o64 < 1.0))
     if not args.no_serving:
         line["serving"] = serving_leg(rr, wl, args.serving_requests)
+    if not args.no_extra:
+        line["heterogeneous"] = heterogeneous_leg(rr, wl, min(args.steps, 50), 5, lib)
+        line["loglik_grad"] = loglik_leg(rr, wl, 10, 2)
     if not args.no_cpu_baseline:
         cb, acc = cpu_baseline(w, grid, args.cpu_seconds, o64, o32)
         line["cpu_baseline"] = cb

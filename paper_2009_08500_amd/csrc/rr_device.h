@@ -201,22 +201,25 @@ __device__ inline R separation(R dt, const OrbitR<R>& o, bool* front) {
     return N::sqrt_(X * X + Y * Y);
 }
 
+// x is neither infinite nor NaN (x - x is 0 exactly for every finite x).
+__host__ __device__ inline bool is_finite(double x) { return (x - x) == 0.0; }
+
 // Orbit constants and transit window of one parameter row
 // [t0, P, a, b, e, w, k_0 .. k_{npb-1}] (FP64).  The row is invalid (NaN
 // output) if any value is non-finite, P <= 0, a <= 0, b < 0, e outside
 // [0, 1), a k outside [k0, k1] or |cos i| > 1.
-__device__ inline PvConst make_pv_const(const double* row, int npb, double k0,
-                                        double k1) {
+__host__ __device__ inline PvConst make_pv_const(const double* row, int npb, double k0,
+                                                 double k1) {
     PvConst c = {};
     const double t0 = row[0], P = row[1], a = row[2], b = row[3], e = row[4],
                  w = row[5];
-    bool ok = isfinite(t0) && isfinite(P) && isfinite(a) && isfinite(b) &&
-              isfinite(e) && isfinite(w) && P > 0.0 && a > 0.0 && b >= 0.0 &&
+    bool ok = is_finite(t0) && is_finite(P) && is_finite(a) && is_finite(b) &&
+              is_finite(e) && is_finite(w) && P > 0.0 && a > 0.0 && b >= 0.0 &&
               e >= 0.0 && e < 1.0;
     double kmax = 0.0;
     for (int pb = 0; pb < npb; ++pb) {
         const double k = row[6 + pb];
-        ok = ok && isfinite(k) && k >= k0 && k <= k1;
+        ok = ok && is_finite(k) && k >= k0 && k <= k1;
         kmax = k > kmax ? k : kmax;
     }
     double sw = 0.0, cw = 1.0;

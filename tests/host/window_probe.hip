@@ -1,0 +1,17 @@
+// Host build of the library's per-row setup (make_pv_const), so CPU tests
+// can check the transit window it computes against the oracle's orbit.
+#include "rr_device.h"
+
+extern "C" {
+int probe_pvconst_size() { return int(sizeof(rr::PvConst)); }
+// rows[n][npar] -> flags, window start and width (phase units) per row
+void probe_windows(const double* rows, int n, int npar, double k0, double k1,
+                   int* flags, double* flo, double* wn) {
+    for (int i = 0; i < n; ++i) {
+        const rr::PvConst c = rr::make_pv_const(rows + size_t(i) * npar, npar - 6, k0, k1);
+        flags[i] = c.flags;
+        flo[i] = c.flo;
+        wn[i] = c.wn;
+    }
+}
+}
