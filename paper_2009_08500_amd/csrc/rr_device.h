@@ -241,70 +241,59 @@ __host__ __device__ inline PvConst make_pv_const(const double* row, int npb, dou
     if (ok) {
         // With psi = f - f_tr (transit at psi = 0) the sky separation obeys
         // z^2 = r^2 (sin^2 psi sin^2 i + cos^2 i), and the planet is in front
-        // for |psi| < pi/2.  Over any set where r >= rmin, z < 1 + k needs
+        // for |psi| < pi/2.  Over any arc where r >= rmin, z < 1 + k needs
         // sin^2 psi < ((1 + k)^2 / rmin^2 - cos^2 i) / sin^2 i.  Starting from
-        // rmin = a (1 - e), the window |psi| < theta is narrowed once by
-        // taking rmin as the smallest r = a (1 - e^2)/(1 + e cos f) over it
-        // (a second pass narrows the population's windows by under 1 %).  An empty window means the planet never overlaps
-        // the star.
+        // rmin = a (1 - e), the arc |psi| < theta is narrowed once by taking
+        // rmin as the smallest r = a (1 - e^2)/(1 + e cos f) over it (a
+        // second pass narrows the population's windows by under 1 %).  An
+        // empty arc means the planet never overlaps the star.
         //
-        // The window only has to contain the true one, so its transcendental
-        // steps run in float with every rounding pushed outward: the asin
-        // argument is rounded up and theta widened by 1e-6 rad, cos f is
-        // raised by 3e-7, and the phase limits are widened by 1e-6 (2 + the
-        // largest dM/df) of a period, several times the float error of the
-        // mean-anomaly differences.  This keeps the setup short: it is a
-        // serial chain per parameter vector.
+        // Only sin and cos of theta are needed: the arc's ends f = f_tr +- theta
+        // have cos f = sin w cos theta -+ cos w sin theta and
+        // sin f = cos w cos theta +- sin w sin theta, their eccentric
+        // anomalies follow from cos E = (e + cos f)/(1 + e cos f) and
+        // sin E = q sin f/(1 + e cos f), and the mean-anomaly offsets from
+        // conjunction are dM = dE - e (sin E - sin E_tr) with dE the angle from
+        // E_tr to E (one atan2 each).  The arc contains periapsis iff
+        // cos f_tr = sin w >= cos theta.
         const double ci2 = cosi * cosi, si2 = 1.0 - ci2;
         const double opk2 = (1.0 + kmax) * (1.0 + kmax) * (1.0 + 2e-6);
-        const double twopi = 2.0 * Num<double>::pi;
-        double ftr = 0.5 * Num<double>::pi - w;
-        ftr -= twopi * rint(ftr / twopi);          // M(f + 2 pi) = M(f) + 2 pi
-        const float ftrf = float(ftr);
-        const float halfpi = 1.57079637f;          // pi/2 rounded up
         double rmin = a * (1.0 - e);
-        float theta = halfpi;
+        double sth = 1.0, cth = 0.0;                 // theta = pi/2: the front half
         bool never = false;
         for (int it = 0; it < 2; ++it) {
             const double num = opk2 / (rmin * rmin) - ci2;
             if (num <= 0.0) { never = true; break; }
-            const double sn = si2 > 0.0 ? sqrt(num / si2) : 2.0;
-            theta = sn * (1.0 + 2e-7) >= 1.0 ? halfpi
-                                              : asinf(float(sn * (1.0 + 2e-7))) + 1e-6f;
+            const double s2 = si2 > 0.0 ? num / si2 : 2.0;
+            if (s2 < 1.0) { sth = sqrt(s2); cth = sqrt(1.0 - s2); }
+            else { sth = 1.0; cth = 0.0; }
             if (e == 0.0) break;
-            // largest cos f over [f_tr - theta, f_tr + theta]: 1 if it holds
-            // a periapsis passage (|f_tr| <= theta after the reduction above),
-            // else at the nearer edge
-            const float cmax = fabsf(ftrf) <= theta + 1e-6f
-                                   ? 1.0f
-                                   : fminf(1.0f, fmaxf(cosf(ftrf - theta), cosf(ftrf + theta)) + 3e-7f);
-            const double rnew = a * (1.0 - e * e) / (1.0 + e * double(cmax));
+            const double cmax = sw >= cth ? 1.0 : fmax(sw * cth - cw * sth, sw * cth + cw * sth);
+            const double rnew = a * (1.0 - e * e) / (1.0 + e * cmax);
             if (rnew <= rmin) break;
             rmin = rnew;
         }
         if (never) {
             c.wn = 0.0;                  // no exposure is ever inside
         } else {
-            const float ef = float(e);
-            const float beta = float(e / (1.0 + q));
-            // mean anomaly as a continuous (unwrapped) function of the true
-            // anomaly: E = f - 2 atan(beta sin f / (1 + beta cos f))
-            auto mean_of_true = [&](float f) {
-                float sf, cf;
-                sincosf(f, &sf, &cf);
-                const float E = f - 2.0f * atanf(beta * sf / (1.0f + beta * cf));
-                return E - ef * sinf(E);
+            // dE in float: its error (a few 1e-7 rad) is far inside the
+            // margin of 2e-6 of a period added on each side
+            auto dmean = [&](double sign) {
+                const double cf = sw * cth - sign * cw * sth;
+                const double sf = cw * cth + sign * sw * sth;
+                const double inv = 1.0 / (1.0 + e * cf);
+                const double cEx = (e + cf) * inv, sEx = q * sf * inv;
+                const float dE = atan2f(float(sEx * c.cE - cEx * c.sE),
+                                        float(cEx * c.cE + sEx * c.sE));
+                return double(dE) - e * (sEx - c.sE);
             };
-            const float m0 = mean_of_true(ftrf);
-            const float ml = mean_of_true(ftrf - theta);
-            const float mh = mean_of_true(ftrf + theta);
             const double inv2pi = 0.5 / Num<double>::pi;
-            // dM/df peaks at (1 + e) sqrt((1 + e)/(1 - e)) (periapsis), which
-            // scales the float rounding of f into M
-            const double margin = 1e-6 * (2.0 + (1.0 + e) * sqrt((1.0 + e) / (1.0 - e)));
-            const double lo = double(ml - m0) * inv2pi - margin;
-            const double hi = double(mh - m0) * inv2pi + margin;
-            if (hi - lo < 1.0) {
+            const double dlo = dmean(-1.0), dhi = dmean(1.0);
+            const double lo = dlo * inv2pi - 2e-6;
+            const double hi = dhi * inv2pi + 2e-6;
+            // |dE| < pi on both sides unless e is close to 1 and the arc is the
+            // whole front half; a wrapped atan2 shows as a sign change
+            if (dlo < 0.0 && dhi > 0.0 && hi - lo < 1.0) {
                 c.flo = lo;
                 c.wn = hi - lo;
             } else {
