@@ -29,13 +29,6 @@
 namespace rr {
 namespace {
 
-#ifndef RR_FWD_WAVES_F32
-#define RR_FWD_WAVES_F32 1
-#endif
-#ifndef RR_FWD_WAVES_F64
-#define RR_FWD_WAVES_F64 1
-#endif
-
 static_assert(kTimesPerThread % 4 == 0 && kTimesPerThread <= 32,
               "pass 1 packs 4 float or 2 double outputs per 16-B store");
 
@@ -73,33 +66,40 @@ __device__ inline PbConst<R> pb_const(const double* __restrict__ pv, int ipv, in
     return c;
 }
 
-// Flux of one exposure at mid-time t: mean over its nss subsamples of
-// Eq. 5, each through the orbit (z), the LD vector interpolated in k and g
-// from the resident table (Sect. 3.1.1, Sect. 3.1.2) and the lens area.
+// Occulted fraction of subsample s of an exposure at mid-time t (the term
+// of Eq. 5 after the leading 1): the orbit (z), the LD vector interpolated
+// in k and g from the resident table (Sect. 3.1.1, Sect. 3.1.2) and the lens
+// area; 0 when the planet does not overlap the star.
+template <typename R>
+__device__ inline R subsample_delta(const PvConst& p, const OrbitR<R>& orb,
+                                    const PbConst<R>& c, double t, double ex,
+                                    double inv_nss, int s, const GridDev& g) {
+    const double x = (t + ex * ((s + 0.5) * inv_nss - 0.5)) - p.t0;
+    const double u = x * p.invP;
+    if (!in_phase_window(u, p, 0.0)) return R(0);
+    const double dt = x - p.P * rint(u);
+    bool front;
+    const R z = separation<R>(R(dt), orb, &front);
+    if (!front || !(z < c.onepk)) return R(0);
+    const R v = z * c.inv1pk * R(g.gscale);
+    int m = int(v);
+    m = m > g.ng - 2 ? g.ng - 2 : m;
+    const R al = v - R(m);
+    const R* t0r = c.t0r;
+    const R l0 = (R(1) - c.ak) * t0r[m] + c.ak * t0r[g.ng + m];
+    const R l1 = (R(1) - c.ak) * t0r[m + 1] + c.ak * t0r[g.ng + m + 1];
+    const R ip = (R(1) - al) * l0 + al * l1;
+    return ip * lens_area<R>(R(1), c.k, z) * c.istar_inv;
+}
+
+// Flux of one exposure: 1 - mean over its nss subsamples (Sect. 4.1),
+// summed in subsample order.
 template <typename R>
 __device__ inline R exposure_flux(const PvConst& p, const OrbitR<R>& orb, const PbConst<R>& c,
                                   double t, double ex, int nss, const GridDev& g) {
-    const R gscale = R(g.gscale);
     const double inv_nss = 1.0 / nss;
     R acc = R(0);
-    for (int s = 0; s < nss; ++s) {
-        const double x = (t + ex * ((s + 0.5) * inv_nss - 0.5)) - p.t0;
-        const double u = x * p.invP;
-        if (!in_phase_window(u, p, 0.0)) continue;
-        const double dt = x - p.P * rint(u);
-        bool front;
-        const R z = separation<R>(R(dt), orb, &front);
-        if (!front || !(z < c.onepk)) continue;
-        const R v = z * c.inv1pk * gscale;
-        int m = int(v);
-        m = m > g.ng - 2 ? g.ng - 2 : m;
-        const R al = v - R(m);
-        const R* t0r = c.t0r;
-        const R l0 = (R(1) - c.ak) * t0r[m] + c.ak * t0r[g.ng + m];
-        const R l1 = (R(1) - c.ak) * t0r[m + 1] + c.ak * t0r[g.ng + m + 1];
-        const R ip = (R(1) - al) * l0 + al * l1;
-        acc += ip * lens_area<R>(R(1), c.k, z) * c.istar_inv;
-    }
+    for (int s = 0; s < nss; ++s) acc += subsample_delta<R>(p, orb, c, t, ex, inv_nss, s, g);
     return R(1) - acc * R(inv_nss);
 }
 
@@ -107,7 +107,7 @@ __device__ inline R exposure_flux(const PvConst& p, const OrbitR<R>& orb, const 
 // wave64 owns 64 kTimesPerThread consecutive exposures of the tile and works
 // on its own, with no workgroup barrier: a wave whose exposures all lie
 // outside the transit window stores ones and ends.
-template <typename R>
+template <typename R, bool kSubPar>
 __device__ inline void forward_block(const FwdJob& job, const LcInfo& lc, int ipv,
                                      int tile, const GridDev& g,
                                      const R* __restrict__ T,
@@ -205,10 +205,74 @@ __device__ inline void forward_block(const FwdJob& job, const LcInfo& lc, int ip
         if (!__any(todo != 0)) return;
     }
 
-    // Pass 2 in the wave: the flagged exposures, one per lane and bit.
     const OrbitR<R> orb(p);
     int pb_cached = -1;
     PbConst<R> c = {};
+
+    if constexpr (kSubPar) {
+        // Supersampled exposures: if every flagged exposure of the wave has
+        // the same nss in [2, 32], spread the subsamples over the lanes --
+        // G = 64 / nss exposures per round, lane L on subsample L % nss of
+        // exposure L / nss -- and let the first lane of each group sum the
+        // group's terms in subsample order (so the result is the same as
+        // one lane's serial loop).  The flagged exposures are packed in
+        // exposure order into this wave's own LDS region first.
+        int nmin = 1 << 30, nmax = 0;
+        for (uint32_t b = todo; b; b &= b - 1) {
+            const int it = t_base + 64 * __builtin_ctz(b);
+            const int n = lc.nss[lcids ? lcids[it] : 0];
+            nmin = n < nmin ? n : nmin;
+            nmax = n > nmax ? n : nmax;
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const int a = __shfl_xor(nmin, off), b = __shfl_xor(nmax, off);
+            nmin = a < nmin ? a : nmin;
+            nmax = b > nmax ? b : nmax;
+        }
+        const int N = nmax;
+        if (nmin == nmax && N >= 2 && N <= 32) {
+            __shared__ uint16_t packed[kBlock / 64][kSpan];
+            uint16_t* pk = packed[threadIdx.x >> 6];
+            const uint64_t below = __lanemask_lt();
+            int total = 0;
+#pragma unroll
+            for (int r = 0; r < kTimesPerThread; ++r) {
+                const uint64_t m = __ballot((todo >> r) & 1u);
+                if ((todo >> r) & 1u) pk[total + __popcll(m & below)] = uint16_t(64 * r + lane);
+                total += __popcll(m);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const int G = 64 / N;
+            const int gi = lane / N, sub = lane - gi * N;
+            const double inv_nss = 1.0 / N;
+            for (int j0 = 0; j0 < total; j0 += G) {
+                const int j = j0 + gi;
+                const bool have = gi < G && j < total;
+                int it = 0;
+                R val = R(0);
+                if (have) {
+                    it = w0 + pk[j];
+                    const int l = lcids ? lcids[it] : 0;
+                    const int pb = lc.pb[l];
+                    if (pb != pb_cached) {
+                        pb_cached = pb;
+                        c = pb_const<R>(pv, ipv, npar, pb, g, T, inv_istar);
+                    }
+                    val = subsample_delta<R>(p, orb, c, times[it], lc.exptime[l], inv_nss, sub, g);
+                }
+                R acc = R(0);
+                const int src0 = gi < G ? gi * N : 0;         // idle lanes read lane 0..N-1
+                for (int q = 0; q < N; ++q) acc += __shfl(val, src0 + q);
+                if (have && sub == 0) orow[it] = R(1) - acc * R(inv_nss);
+            }
+            return;
+        }
+    }
+
+    // Pass 2 in the wave: the flagged exposures, one per lane and bit.
     while (todo) {
         const int r = __builtin_ctz(todo);
         todo &= todo - 1;
@@ -223,25 +287,21 @@ __device__ inline void forward_block(const FwdJob& job, const LcInfo& lc, int ip
     }
 }
 
-// Minimum waves per SIMD the register allocator must leave room for.
-template <typename R> struct FwdOccupancy;
-template <> struct FwdOccupancy<float> { static constexpr int waves = RR_FWD_WAVES_F32; };
-template <> struct FwdOccupancy<double> { static constexpr int waves = RR_FWD_WAVES_F64; };
-
 // One population (rr_evaluate): workgroup (x, y) -> row pv0 + y, tile x.
-template <typename R>
-__global__ __launch_bounds__(kBlock, FwdOccupancy<R>::waves) void k_forward(FwdJob job, LcInfo lc, GridDev g,
+// kSubPar: some light curve has nss > 1.
+template <typename R, bool kSubPar>
+__global__ __launch_bounds__(kBlock) void k_forward(FwdJob job, LcInfo lc, GridDev g,
                                                     const R* __restrict__ T,
                                                     const double* __restrict__ inv_istar) {
     const int ipv = job.pv0 + blockIdx.y;
     const int tile = blockIdx.x;
-    forward_block<R>(job, lc, ipv, tile, g, T, inv_istar);
+    forward_block<R, kSubPar>(job, lc, ipv, tile, g, T, inv_istar);
 }
 
 // Grouped launch (serving): workgroup b belongs to the last job whose
 // block0 <= b; jobs come from several requests and time series.
-template <typename R>
-__global__ __launch_bounds__(kBlock, FwdOccupancy<R>::waves) void k_forward_jobs(JobTable jt, GridDev g,
+template <typename R, bool kSubPar>
+__global__ __launch_bounds__(kBlock) void k_forward_jobs(JobTable jt, GridDev g,
                                                          const R* __restrict__ T,
                                                          const double* __restrict__ inv_istar) {
     const int b = blockIdx.x;
@@ -252,7 +312,7 @@ __global__ __launch_bounds__(kBlock, FwdOccupancy<R>::waves) void k_forward_jobs
     const int local = b - job.block0;
     const int ipv = job.pv0 + local / job.ntiles;
     const int tile = local - (local / job.ntiles) * job.ntiles;
-    forward_block<R>(job, *job.lc, ipv, tile, g, T, inv_istar);
+    forward_block<R, kSubPar>(job, *job.lc, ipv, tile, g, T, inv_istar);
 }
 
 __global__ void k_pv_setup_jobs(SetupTable st, double k0, double k1) {
@@ -286,22 +346,33 @@ hipError_t launch_forward(const rr_tables* t, const double* times,
     FwdJob job;
     job.times = times; job.lcids = lcids; job.lc = nullptr; job.pv = pv; job.pvc = pvc;
     job.out = out; job.npt = npt; job.npar = npar; job.pv0 = 0; job.npv = npv;
-    job.ntiles = (npt + kTile - 1) / kTile; job.block0 = 0;
+    job.ntiles = (npt + kTile - 1) / kTile; job.block0 = 0; job.max_nss = 1;
+    for (int l = 0; l < lc.nlc; ++l) job.max_nss = lc.nss[l] > job.max_nss ? lc.nss[l] : job.max_nss;
     const KernelEvents ev = kernel_events();
     if (ev.before) {
         hipError_t e = hipEventRecord(ev.before, s);
         if (e != hipSuccess) return e;
     }
+    const bool sub = job.max_nss > 1;
     // rows along grid y, at most 65535 per launch
     for (int32_t r0 = 0; r0 < npv; r0 += 65535) {
         job.pv0 = r0;
         const dim3 grid(unsigned(job.ntiles), unsigned(npv - r0 < 65535 ? npv - r0 : 65535));
-        if (precision == RR_FP64)
-            hipLaunchKernelGGL(k_forward<double>, grid, dim3(kBlock), 0, s, job, lc, g,
-                               t->T64, t->inv_istar);
-        else
-            hipLaunchKernelGGL(k_forward<float>, grid, dim3(kBlock), 0, s, job, lc, g,
-                               t->T32, t->inv_istar);
+        if (precision == RR_FP64) {
+            if (sub)
+                hipLaunchKernelGGL((k_forward<double, true>), grid, dim3(kBlock), 0, s, job, lc,
+                                   g, t->T64, t->inv_istar);
+            else
+                hipLaunchKernelGGL((k_forward<double, false>), grid, dim3(kBlock), 0, s, job, lc,
+                                   g, t->T64, t->inv_istar);
+        } else {
+            if (sub)
+                hipLaunchKernelGGL((k_forward<float, true>), grid, dim3(kBlock), 0, s, job, lc,
+                                   g, t->T32, t->inv_istar);
+            else
+                hipLaunchKernelGGL((k_forward<float, false>), grid, dim3(kBlock), 0, s, job, lc,
+                                   g, t->T32, t->inv_istar);
+        }
     }
     hipError_t e = hipGetLastError();
     if (e == hipSuccess && ev.after) e = hipEventRecord(ev.after, s);
@@ -312,12 +383,24 @@ hipError_t launch_forward_jobs(const rr_tables* t, const JobTable& jt, int32_t n
                                int32_t precision, hipStream_t s) {
     if (nblocks_total <= 0 || jt.njobs <= 0) return hipSuccess;
     const GridDev g = grid_dev(t);
-    if (precision == RR_FP64)
-        hipLaunchKernelGGL(k_forward_jobs<double>, dim3(unsigned(nblocks_total)), dim3(kBlock),
-                           0, s, jt, g, t->T64, t->inv_istar);
-    else
-        hipLaunchKernelGGL(k_forward_jobs<float>, dim3(unsigned(nblocks_total)), dim3(kBlock),
-                           0, s, jt, g, t->T32, t->inv_istar);
+    bool sub = false;
+    for (int q = 0; q < jt.njobs; ++q) sub = sub || jt.j[q].max_nss > 1;
+    const dim3 grid{unsigned(nblocks_total), 1u, 1u};
+    if (precision == RR_FP64) {
+        if (sub)
+            hipLaunchKernelGGL((k_forward_jobs<double, true>), grid, dim3(kBlock), 0, s, jt, g,
+                               t->T64, t->inv_istar);
+        else
+            hipLaunchKernelGGL((k_forward_jobs<double, false>), grid, dim3(kBlock), 0, s, jt, g,
+                               t->T64, t->inv_istar);
+    } else {
+        if (sub)
+            hipLaunchKernelGGL((k_forward_jobs<float, true>), grid, dim3(kBlock), 0, s, jt, g,
+                               t->T32, t->inv_istar);
+        else
+            hipLaunchKernelGGL((k_forward_jobs<float, false>), grid, dim3(kBlock), 0, s, jt, g,
+                               t->T32, t->inv_istar);
+    }
     return hipGetLastError();
 }
 

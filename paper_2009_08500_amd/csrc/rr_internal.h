@@ -58,6 +58,7 @@ struct FwdJob {
     const PvConst* pvc;
     void* out;
     int32_t npt, npar, pv0, npv, ntiles, block0;
+    int32_t max_nss;           // largest nss of the job's light curves
 };
 constexpr int kMaxJobs = 24;   // jobs per grouped launch (kernel arguments)
 struct JobTable {

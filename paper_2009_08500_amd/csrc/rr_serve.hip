@@ -47,6 +47,7 @@ struct Series {
     LcInfo* lc = nullptr;
     int32_t npt = 0, ntiles = 0;
     int64_t nsub = 0;          // subsamples per parameter row
+    int32_t max_nss = 1;       // largest nss of its light curves
 };
 
 enum ReqState { kQueued = 0, kRunning = 1, kDone = 2 };
@@ -269,6 +270,7 @@ bool rr_server::step() {
                 j.times = se.times; j.lcids = se.lcids; j.lc = se.lc; j.pv = r->pv_dev;
                 j.pvc = r->pvc_dev; j.out = r->out_dev; j.npt = se.npt; j.npar = r->npar;
                 j.pv0 = r->next_row; j.npv = rows; j.ntiles = se.ntiles; j.block0 = nb[p];
+                j.max_nss = se.max_nss;
                 nb[p] += rows * se.ntiles;
                 left -= rows * se.ntiles;
                 r->next_row += rows;
@@ -383,6 +385,7 @@ RR_API int rr_server_add_series(rr_server* s, const double* times, const int32_t
         se.nsub += (l >= 0 && l < nlc) ? lc.nss[l] : 0;
     }
     se.ntiles = (npt + kTile - 1) / kTile;
+    for (int32_t i = 0; i < nlc; ++i) se.max_nss = std::max(se.max_nss, lc.nss[i]);
     hipError_t e = hipMalloc((void**)&se.times, sizeof(double) * npt);
     if (e == hipSuccess && lcids) e = hipMalloc((void**)&se.lcids, sizeof(int32_t) * npt);
     if (e == hipSuccess) e = hipMalloc((void**)&se.lc, sizeof(LcInfo));
