@@ -378,81 +378,156 @@ __global__ void k_adjoint_reduce(const double* __restrict__ partials, int32_t np
     }
 }
 
-// dlogL/dT[pb][i][m] = sum_pv [(ik == i)(1 - ak) + (ik + 1 == i) ak] dlogL/dldw_pv[pb][m]
-__global__ void k_table_grad(const double* __restrict__ gldw_pv,
-                             const double* __restrict__ pv, int32_t npv, int32_t npar,
-                             const PvConst* __restrict__ pvc, GridDev g,
-                             double* __restrict__ GT) {
-    const int64_t per = int64_t(g.nk) * g.ng;
+// k-row index and lerp weight of every (row, passband) for the table
+// gradient: kidx = ik (kNoRow for an invalid row, so that neither ik nor
+// ik + 1 matches any k-row), kfrac = ak.
+constexpr int kNoRow = -2;
+__global__ void k_row_kidx(const double* __restrict__ pv, int32_t npv, int32_t npar,
+                           const PvConst* __restrict__ pvc, GridDev g,
+                           int32_t* __restrict__ kidx, double* __restrict__ kfrac) {
     const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (idx >= per * g.npb) return;
-    const int pb = int(idx / per);
-    const int64_t r = idx - pb * per;
-    const int i = int(r / g.ng), m = int(r - int64_t(i) * g.ng);
-    double s = 0.0;
-    for (int ipv = 0; ipv < npv; ++ipv) {
-        if (!(pvc[ipv].flags & kValid)) continue;
-        const double u = (pv[int64_t(ipv) * npar + 6 + pb] - g.k0) / g.dk;
-        int ik = int(floor(u));
-        ik = ik < 0 ? 0 : (ik > g.nk - 2 ? g.nk - 2 : ik);
-        if (i != ik && i != ik + 1) continue;
-        const double ak = u - ik;
-        const double w = (i == ik) ? 1.0 - ak : ak;
-        s += w * gldw_pv[(int64_t(ipv) * g.npb + pb) * g.ng + m];
+    if (idx >= int64_t(npv) * g.npb) return;
+    const int ipv = int(idx / g.npb), pb = int(idx - int64_t(ipv) * g.npb);
+    if (!(pvc[ipv].flags & kValid)) {
+        kidx[idx] = kNoRow;
+        kfrac[idx] = 0.0;
+        return;
     }
-    GT[idx] = s;
+    const double u = (pv[int64_t(ipv) * npar + 6 + pb] - g.k0) / g.dk;
+    int ik = int(floor(u));
+    ik = ik < 0 ? 0 : (ik > g.nk - 2 ? g.nk - 2 : ik);
+    kidx[idx] = ik;
+    kfrac[idx] = u - ik;
 }
 
-// dlogL/dldp[pb][j] = sum_{i,m} W[i][j][m] dlogL/dT[pb][i][m]; one
-// workgroup per (pb, j), fixed-shape tree.
+// dlogL/dT[pb][i][m] = sum over rows, in row order, of
+// [(ik == i)(1 - ak) + (ik + 1 == i) ak] dlogL/dldw_row[pb][m].  Workgroup
+// (x, i, pb), x = a block of m.  Each wave reads the k-rows of 64
+// rows at a time and visits only those that touch k-row i (a ballot), so
+// the loop over rows costs ~npv/64 loads.  Grid (m blocks, nk, npb).
+__global__ void k_table_grad(const double* __restrict__ gldw_pv,
+                             const int32_t* __restrict__ kidx, const double* __restrict__ kfrac,
+                             int32_t npv, GridDev g, double* __restrict__ GT) {
+    const int pb = int(blockIdx.z), i = int(blockIdx.y);
+    const int m = int(blockIdx.x) * kBlock + int(threadIdx.x);
+    const int lane = threadIdx.x & 63;
+    double s = 0.0;
+    for (int base = 0; base < npv; base += 64) {
+        const int r = base + lane;
+        const int ik = r < npv ? kidx[int64_t(r) * g.npb + pb] : kNoRow;
+        const double ak = r < npv ? kfrac[int64_t(r) * g.npb + pb] : 0.0;
+        uint64_t hit = __ballot(ik == i || ik + 1 == i);
+        while (hit) {
+            const int q = __builtin_ctzll(hit);
+            hit &= hit - 1;
+            const int ikq = __shfl(ik, q);
+            const double akq = __shfl(ak, q);
+            const double w = (ikq == i) ? 1.0 - akq : akq;
+            if (m < g.ng) s += w * gldw_pv[(int64_t(base + q) * g.npb + pb) * g.ng + m];
+        }
+    }
+    if (m < g.ng) GT[(int64_t(pb) * g.nk + i) * g.ng + m] = s;
+}
+
+// dlogL/dldp[pb][j] = sum_{i,m} W[i][j][m] dlogL/dT[pb][i][m], in two fixed-
+// order stages: workgroup (c, j, pb) sums the k-rows of chunk c with a
+// fixed-shape tree, then k_ldp_sum adds the chunks in order.
+constexpr int kLdpChunks = 16;
 __global__ void k_ldp_grad(const double* __restrict__ W, const double* __restrict__ GT,
-                           GridDev g, double* __restrict__ gldp) {
+                           GridDev g, double* __restrict__ part_out) {
     __shared__ double part[kBlock];
-    const int pb = blockIdx.x / g.nz, j = blockIdx.x - pb * g.nz;
+    const int c = blockIdx.x;
+    const int j = int(blockIdx.y), pb = int(blockIdx.z);
+    const int per_chunk = (g.nk + kLdpChunks - 1) / kLdpChunks;
+    const int i0 = c * per_chunk, i1 = min(g.nk, i0 + per_chunk);
     const int64_t per = int64_t(g.nk) * g.ng;
     double s = 0.0;
-    for (int64_t r = threadIdx.x; r < per; r += kBlock) {
-        const int i = int(r / g.ng), m = int(r - int64_t(i) * g.ng);
-        s += W[(int64_t(i) * g.nz + j) * g.ng + m] * GT[pb * per + r];
-    }
+    for (int i = i0; i < i1; ++i)
+        for (int m = threadIdx.x; m < g.ng; m += kBlock)
+            s += W[(int64_t(i) * g.nz + j) * g.ng + m] * GT[pb * per + int64_t(i) * g.ng + m];
     part[threadIdx.x] = s;
     __syncthreads();
     for (int w = kBlock / 2; w > 0; w >>= 1) {
         if (threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) gldp[blockIdx.x] = part[0];
+    if (threadIdx.x == 0) part_out[(int64_t(pb) * g.nz + j) * kLdpChunks + c] = part[0];
 }
 
-// dlogL/dI_s[pb][s]: back through ldp = interp(mu_m; mu_s, I_s) and
-// I_star = 2 pi sum of exact segment integrals (both linear in I_s).
-__global__ void k_prof_grad(const double* __restrict__ gldp, const double* __restrict__ gist_pv,
-                            int32_t npv, const PvConst* __restrict__ pvc,
+__global__ void k_ldp_sum(const double* __restrict__ part, int32_t n, double* __restrict__ gldp) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n) return;
+    double s = 0.0;
+    for (int c = 0; c < kLdpChunks; ++c) s += part[int64_t(idx) * kLdpChunks + c];
+    gldp[idx] = s;
+}
+
+// Sum over valid rows of dlogL/dI_star[pb], one workgroup per passband,
+// fixed-shape tree.
+__global__ void k_gist_sum(const double* __restrict__ gist_pv, int32_t npv,
+                           const PvConst* __restrict__ pvc, int32_t npb,
+                           double* __restrict__ gist) {
+    __shared__ double part[kBlock];
+    const int pb = blockIdx.x;
+    double s = 0.0;
+    for (int ipv = threadIdx.x; ipv < npv; ipv += kBlock)
+        if (pvc[ipv].flags & kValid) s += gist_pv[int64_t(ipv) * npb + pb];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) gist[pb] = part[0];
+}
+
+// Profile gradient: chain dlogL/dldp (profile at the bin means, linear in
+// the samples with the weights of the piecewise-linear interpolant) and
+// dlogL/dI_star (I_star linear in the samples, Eq. 2 / Eq. 4) back to the
+// samples prof[pb][s].  Each workgroup first tabulates, for every bin j, the
+// interpolation segment of mu_j in LDS; then one thread per sample gathers
+// over j in order.
+constexpr int kMaxNzLds = 4096;
+__global__ void k_prof_grad(const double* __restrict__ gldp, const double* __restrict__ gist,
                             const double* __restrict__ mu_s, int32_t nmu,
                             const double* __restrict__ zm, int32_t nz, int32_t npb,
                             double* __restrict__ out) {
+    __shared__ int seg_lo[kMaxNzLds];
+    __shared__ double seg_tau[kMaxNzLds];
+    for (int j = threadIdx.x; j < nz; j += kBlock) {
+        const double z = zm[j];
+        const double mu = sqrt(1.0 - z * z);
+        int lo;
+        double tau;
+        if (mu <= mu_s[0]) {
+            lo = -1; tau = 0.0;                     // weight 1 on sample 0
+        } else if (mu >= mu_s[nmu - 1]) {
+            lo = nmu - 1; tau = 1.0;                // weight 1 on sample nmu - 1
+        } else {
+            int a = 0, b = nmu - 1;
+            while (b - a > 1) {
+                const int mid = (a + b) >> 1;
+                if (mu_s[mid] <= mu) a = mid; else b = mid;
+            }
+            lo = a;
+            tau = (mu - mu_s[a]) / (mu_s[a + 1] - mu_s[a]);
+        }
+        seg_lo[j] = lo;
+        seg_tau[j] = tau;
+    }
+    __syncthreads();
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= npb * nmu) return;
     const int pb = idx / nmu, s = idx - pb * nmu;
     double acc = 0.0;
     for (int j = 0; j < nz; ++j) {
-        const double z = zm[j];
-        const double mu = sqrt(1.0 - z * z);
+        const int lo = seg_lo[j];
+        const double tau = seg_tau[j];
         double w = 0.0;
-        if (mu <= mu_s[0]) {
-            w = (s == 0) ? 1.0 : 0.0;
-        } else if (mu >= mu_s[nmu - 1]) {
-            w = (s == nmu - 1) ? 1.0 : 0.0;
-        } else {
-            int lo = 0, hi = nmu - 1;
-            while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                if (mu_s[mid] <= mu) lo = mid; else hi = mid;
-            }
-            const double tau = (mu - mu_s[lo]) / (mu_s[lo + 1] - mu_s[lo]);
-            if (s == lo) w = 1.0 - tau;
-            else if (s == lo + 1) w = tau;
-        }
+        if (lo < 0) w = (s == 0) ? 1.0 : 0.0;
+        else if (lo == nmu - 1) w = (s == nmu - 1) ? 1.0 : 0.0;
+        else if (s == lo) w = 1.0 - tau;
+        else if (s == lo + 1) w = tau;
         if (w != 0.0) acc += w * gldp[pb * nz + j];
     }
     // I_star weight of sample s
@@ -468,10 +543,7 @@ __global__ void k_prof_grad(const double* __restrict__ gldp, const double* __res
     if (s == 0) qs += 0.5 * mu_s[0] * mu_s[0];
     if (s == nmu - 1) qs += 0.5 * (1.0 - mu_s[nmu - 1] * mu_s[nmu - 1]);
     qs *= 2.0 * Num<double>::pi;
-    double gist = 0.0;
-    for (int ipv = 0; ipv < npv; ++ipv)
-        if (pvc[ipv].flags & kValid) gist += gist_pv[int64_t(ipv) * npb + pb];
-    out[idx] = acc + qs * gist;
+    out[idx] = acc + qs * gist[pb];
 }
 
 inline unsigned nblocks(int64_t n) { return unsigned((n + kBlock - 1) / kBlock); }
@@ -533,20 +605,27 @@ hipError_t launch_adjoint(const AdjointArgs& A, int32_t precision, hipStream_t s
     return hipGetLastError();
 }
 
-hipError_t launch_profile_grad(const rr_tables* t, const AdjointArgs& A, double* GT,
-                               double* gldp, double* out, hipStream_t s) {
+hipError_t launch_profile_grad(const rr_tables* t, const AdjointArgs& A,
+                               const ProfGradScratch& w, double* out, hipStream_t s) {
     const GridDev g = A.g;
-    const int64_t nt = int64_t(g.npb) * g.nk * g.ng;
-    hipLaunchKernelGGL(k_table_grad, dim3(nblocks(nt)), dim3(kBlock), 0, s, A.gldw_pv, A.pv,
-                       A.npv, A.npar, A.pvc, g, GT);
+    const int64_t nrk = int64_t(A.npv) * g.npb;
+    hipLaunchKernelGGL(k_row_kidx, dim3(nblocks(nrk)), dim3(kBlock), 0, s, A.pv, A.npv, A.npar,
+                       A.pvc, g, w.kidx, w.kfrac);
+    hipLaunchKernelGGL(k_table_grad,
+                       dim3(unsigned((g.ng + kBlock - 1) / kBlock), unsigned(g.nk), unsigned(g.npb)),
+                       dim3(kBlock), 0, s, A.gldw_pv, w.kidx, w.kfrac, A.npv, g, w.GT);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_ldp_grad, dim3(unsigned(g.npb * g.nz)), dim3(kBlock), 0, s, t->W, GT, g,
-                       gldp);
+    hipLaunchKernelGGL(k_ldp_grad, dim3(unsigned(kLdpChunks), unsigned(g.nz), unsigned(g.npb)),
+                       dim3(kBlock), 0, s, t->W, w.GT, g, w.ldp_part);
+    hipLaunchKernelGGL(k_ldp_sum, dim3(nblocks(int64_t(g.npb) * g.nz)), dim3(kBlock), 0, s,
+                       w.ldp_part, g.npb * g.nz, w.gldp);
+    hipLaunchKernelGGL(k_gist_sum, dim3(unsigned(g.npb)), dim3(kBlock), 0, s, A.gist_pv, A.npv,
+                       A.pvc, g.npb, w.gist);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_prof_grad, dim3(nblocks(int64_t(g.npb) * t->nmu)), dim3(kBlock), 0, s,
-                       gldp, A.gist_pv, A.npv, A.pvc, t->mu_s, t->nmu, t->zm, t->nz, g.npb, out);
+                       w.gldp, w.gist, t->mu_s, t->nmu, t->zm, t->nz, g.npb, out);
     return hipGetLastError();
 }
 

@@ -306,6 +306,10 @@ RR_API int rr_loglik_grad(const rr_tables* t, const double* times_d,
     const size_t o_gist = prof ? take(sizeof(double) * size_t(npv) * t->npb) : 0;
     const size_t o_gt = prof ? take(sizeof(double) * size_t(t->npb) * g.nk * g.ng) : 0;
     const size_t o_gldp = prof ? take(sizeof(double) * size_t(t->npb) * t->nz) : 0;
+    const size_t o_ldpp = prof ? take(sizeof(double) * size_t(t->npb) * t->nz * 16) : 0;
+    const size_t o_kidx = prof ? take(sizeof(int32_t) * size_t(npv) * t->npb) : 0;
+    const size_t o_kfrac = prof ? take(sizeof(double) * size_t(npv) * t->npb) : 0;
+    const size_t o_gist_sum = prof ? take(sizeof(double) * size_t(t->npb)) : 0;
     char* base = nullptr;
     e = hipMallocAsync((void**)&base, off, stream);
     if (e != hipSuccess) return e == hipErrorOutOfMemory ? RR_ENOMEM : hip_fail(e, "hipMallocAsync");
@@ -321,9 +325,16 @@ RR_API int rr_loglik_grad(const rr_tables* t, const double* times_d,
     A.logl = logl_d; A.grad = grad_d;
     e = launch_pv_setup(t, pv_d, npv, npar, const_cast<PvConst*>(A.pvc), stream);
     if (e == hipSuccess) e = launch_adjoint(A, precision, stream);
-    if (e == hipSuccess && prof)
-        e = launch_profile_grad(t, A, reinterpret_cast<double*>(base + o_gt),
-                                reinterpret_cast<double*>(base + o_gldp), grad_prof_d, stream);
+    if (e == hipSuccess && prof) {
+        ProfGradScratch w;
+        w.kidx = reinterpret_cast<int32_t*>(base + o_kidx);
+        w.kfrac = reinterpret_cast<double*>(base + o_kfrac);
+        w.GT = reinterpret_cast<double*>(base + o_gt);
+        w.ldp_part = reinterpret_cast<double*>(base + o_ldpp);
+        w.gldp = reinterpret_cast<double*>(base + o_gldp);
+        w.gist = reinterpret_cast<double*>(base + o_gist_sum);
+        e = launch_profile_grad(t, A, w, grad_prof_d, stream);
+    }
     hipError_t ef = hipFreeAsync(base, stream);
     if (e != hipSuccess) return hip_fail(e, "log-likelihood kernels");
     if (ef != hipSuccess) return hip_fail(ef, "hipFreeAsync");

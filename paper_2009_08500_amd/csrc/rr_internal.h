@@ -148,8 +148,17 @@ hipError_t launch_pv_setup(const rr_tables* t, const double* pv, int32_t npv,
                            int32_t npar, PvConst* pvc, hipStream_t s);
 size_t adjoint_lds_bytes(int32_t precision, int32_t npb, int32_t ng);
 hipError_t launch_adjoint(const AdjointArgs& a, int32_t precision, hipStream_t s);
-hipError_t launch_profile_grad(const rr_tables* t, const AdjointArgs& a, double* GT,
-                               double* gldp, double* out, hipStream_t s);
+// Temporaries of the profile gradient.
+struct ProfGradScratch {
+    int32_t* kidx;        // [npv][npb]
+    double* kfrac;        // [npv][npb]
+    double* GT;           // [npb][nk][ng]
+    double* ldp_part;     // [npb][nz][16]
+    double* gldp;         // [npb][nz]
+    double* gist;         // [npb]
+};
+hipError_t launch_profile_grad(const rr_tables* t, const AdjointArgs& a,
+                               const ProfGradScratch& w, double* out, hipStream_t s);
 hipError_t launch_fill(double* p, int64_t n, hipStream_t s);
 hipError_t launch_forward_jobs(const rr_tables* t, const JobTable& jt,
                                int32_t nblocks_total, int32_t precision, hipStream_t s);
