@@ -418,12 +418,29 @@ __global__ void k_table_grad(const double* __restrict__ gldw_pv,
         const double ak = r < npv ? kfrac[int64_t(r) * g.npb + pb] : 0.0;
         uint64_t hit = __ballot(ik == i || ik + 1 == i);
         while (hit) {
-            const int q = __builtin_ctzll(hit);
-            hit &= hit - 1;
-            const int ikq = __shfl(ik, q);
-            const double akq = __shfl(ak, q);
-            const double w = (ikq == i) ? 1.0 - akq : akq;
-            if (m < g.ng) s += w * gldw_pv[(int64_t(base + q) * g.npb + pb) * g.ng + m];
+            // up to 8 hits at a time: their loads are issued together, the
+            // sum still runs in row order
+            constexpr int kB = 8;
+            int qs[kB];
+            int n = 0;
+#pragma unroll
+            for (int b = 0; b < kB; ++b) {
+                qs[b] = hit ? __builtin_ctzll(hit) : 0;
+                n += hit ? 1 : 0;
+                hit &= hit - 1;
+            }
+            double wv[kB], gv[kB];
+#pragma unroll
+            for (int b = 0; b < kB; ++b) {
+                const int ikq = __shfl(ik, qs[b]);
+                const double akq = __shfl(ak, qs[b]);
+                wv[b] = (ikq == i) ? 1.0 - akq : akq;
+                gv[b] = (b < n && m < g.ng)
+                            ? gldw_pv[(int64_t(base + qs[b]) * g.npb + pb) * g.ng + m] : 0.0;
+            }
+#pragma unroll
+            for (int b = 0; b < kB; ++b)
+                if (b < n) s += wv[b] * gv[b];
         }
     }
     if (m < g.ng) GT[(int64_t(pb) * g.nk + i) * g.ng + m] = s;
