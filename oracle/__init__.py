@@ -21,6 +21,9 @@ orbit       Keplerian orbit -> projected separation, plus an independent
             bisection Kepler solver used as a pin.
 gradient    Analytic gradient of the Gaussian log-likelihood of Oracle-A's
             light curve, and a central finite-difference driver.
+analytic    The analytic quadratic limb-darkening transit model of Mandel &
+            Agol (2002), which the paper uses to measure its accuracy; a pin
+            for both oracles.
 """
 
-from . import orbit, roadrunner, exact  # noqa: F401
+from . import orbit, roadrunner, exact, analytic  # noqa: F401
