@@ -383,13 +383,13 @@ def main():
     m = summary("mixed", 4)
     d = summary("fp64", 8)
     achieved = m["alg_bytes"] / (m["kernel_ms"]["mean"] / 1e3) / 1e9
-    kc = profile_counters("k_forward<float>")
+    kc = profile_counters("k_forward<float, false>")
     traffic = kc.get("hbm_bytes_per_launch") if kc else None
     roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=achieved / HBM_PEAK_GBS, traffic=traffic,
-                kernel="k_forward<float>", alg_bytes_per_launch=m["alg_bytes"],
+                kernel="k_forward<float, false>", alg_bytes_per_launch=m["alg_bytes"],
                 kernel_ms=m["kernel_ms"]["mean"],
-                valu=valu_view("k_forward<float>", m["kernel_ms"]["mean"]))
+                valu=valu_view("k_forward<float, false>", m["kernel_ms"]["mean"]))
     achieved64 = d["alg_bytes"] / (d["kernel_ms"]["mean"] / 1e3) / 1e9
 
     line = dict(
@@ -406,7 +406,7 @@ def main():
                                              peak=HBM_PEAK_GBS, unit="GB/s",
                                              frac=achieved64 / HBM_PEAK_GBS,
                                              kernel_ms=d["kernel_ms"]["mean"],
-                                             valu=valu_view("k_forward<double>",
+                                             valu=valu_view("k_forward<double, false>",
                                                             d["kernel_ms"]["mean"]))),
         roofline=roof,
         in_transit_fraction=None,
