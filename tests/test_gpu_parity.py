@@ -240,6 +240,28 @@ def test_supersampling_long_exposures(rr):
         check_parity(ref, f64, f32)
 
 
+def test_supersample_lane_groups(rr):
+    """Light curves whose nss select the lane-group path (2, 7: groups that
+    leave idle lanes, 32: two groups) or the per-lane loop (33), interleaved
+    so that some waves see mixed nss; every row transits inside the span."""
+    grid = wl.TEST_GRID
+    w = wl.population(npv=12, npt=6000)
+    pv = w["pv"].copy()
+    pv[:, 0] = np.linspace(0.0, 4.0, pv.shape[0])
+    times = w["times"]
+    lcids = (np.arange(times.size) // 700) % 4                 # blocks of 700 times
+    nss = np.array([2, 7, 32, 33], np.int32)
+    ex = np.array([0.004, 0.01, 0.02, 0.03])
+    pbids = np.zeros(4, np.int32)
+    tab = rr.Tables(w["mu_s"], w["I_s"], grid)
+    otab = orr.Tables(w["mu_s"], w["I_s"], **grid)
+    ref = orr.evaluate(otab, times, pv, lcids=lcids, pbids=pbids, nss=nss, exptimes=ex)
+    ser = rr.TimeSeries(times, lcids.astype(np.int32), pbids, nss, ex)
+    f64, f32 = both(rr, tab, ser, pv)
+    assert (ref < 1.0).sum() > 1000
+    check_parity(ref, f64, f32)
+
+
 def test_invalid_light_curve_ids_give_nan(rr):
     grid = wl.TEST_GRID
     w = wl.population(npv=4, npt=100)
