@@ -48,7 +48,7 @@ __device__ inline R lens_area_grad(R k, R z, R* Az, R* Ak) {
     R prod = (a + (b + s)) * (s - (a - b)) * (s + (a - b)) * (a + (b - s));
     prod = prod > R(0) ? prod : R(0);
     const R area2 = R(0.5) * N::sqrt_(prod);
-    const R invz = R(1) / z;
+    const R invz = N::rcp_(z);
     const R h = area2 * invz;
     const R x1 = (z * z + (R(1) - k) * (R(1) + k)) * (R(0.5) * invz);
     const R x0 = z - x1;
@@ -111,13 +111,13 @@ __device__ inline R separation_grad(R dt, R x, const OrbitR<R>& o,
     const R z = N::sqrt_(X * X + Y * Y);
     // derivatives (absolute cos E, sin E are fine here)
     const R cE = o.cE + dc, sE = o.sE + ds;
-    const R iE = R(1) / (R(1) - o.e * cE);
+    const R iE = N::rcp_(R(1) - o.e * cE);
     const R XE = o.a * (sE * o.cosw + o.q * cE * o.sinw);
     const R rE = o.a * (o.q * cE * o.cosw - sE * o.sinw);
     const R Xe = o.a * (o.cosw + dv.dq_de * sE * o.sinw);
     const R re = o.a * (dv.dq_de * sE * o.cosw - o.sinw);
-    const R inva = R(1) / o.a;
-    const R iz = z > R(0) ? R(1) / z : R(0);
+    const R inva = N::rcp_(o.a);
+    const R iz = z > R(0) ? N::rcp_(z) : R(0);
     // dE/dtheta for t0, P, e, w
     const R dE_t0 = -o.n * iE;
     const R dE_P = -o.n * (x * invP) * iE;
