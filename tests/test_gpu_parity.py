@@ -153,6 +153,31 @@ def test_population_full_size(rr):
           f" in-transit fraction {np.mean(ref < 1):.4f}")
 
 
+def test_more_rows_than_one_grid_dimension(rr):
+    """70 000 rows (the kernels put rows on the grid's y dimension, at most
+    65 535 per launch, so this takes two launches) x 300 times: 100 distinct
+    rows tiled 700 times must give bitwise-identical outputs wherever a row
+    repeats, and the distinct rows match the oracle."""
+    grid = wl.TEST_GRID
+    w = wl.population(npv=100, npt=300)
+    pv = w["pv"].copy()
+    pv[:, 0] = np.linspace(0.0, 0.4, pv.shape[0])      # transits inside the 0.42-d span
+    big = np.tile(pv, (700, 1))
+    tab = rr.Tables(w["mu_s"], w["I_s"], grid)
+    ser = rr.TimeSeries(w["times"])
+    for prec in ("fp64", "mixed"):
+        out = rr.evaluate(tab, ser, big, prec).cpu().numpy()
+        assert out.shape == (70000, 300)
+        rows = out.reshape(700, 100, 300)
+        assert np.array_equal(rows, np.broadcast_to(rows[0], rows.shape))
+    ref = orr.evaluate(orr.Tables(w["mu_s"], w["I_s"], **grid), w["times"], pv)
+    assert (ref < 1.0).sum() > 500
+    f64, f32 = both(rr, tab, ser, pv)
+    check_parity(ref, f64, f32)
+    last64 = rr.evaluate(tab, ser, big, "fp64").cpu().numpy()[-100:]
+    assert np.array_equal(last64, f64)
+
+
 def test_population_bjd_offset(rr):
     """Times near BJD 2.459e6: the FP64 time reduction keeps the mixed path
     within 1 ppm."""
