@@ -276,7 +276,7 @@ def serving_leg(rr, wl, nreq):
     het = wl.heterogeneous(npv=1)
     tab = rr.Tables(het["mu_s"], het["I_s"], wl.DEFAULT_GRID)
     series, reqs = wl.serving_mix(nreq)
-    srv = rr.Server(tab, budget_bytes=16 << 30, max_tick_blocks=8192)
+    srv = rr.Server(tab, budget_bytes=16 << 30, max_tick_blocks=32768)
     sids = [srv.add_series(se["times"], se["lcids"], se["pbids"], se["nss"], se["exptimes"])
             for se in series]
     nsub = [int(np.sum(se["nss"][se["lcids"]])) for se in series]

@@ -166,7 +166,7 @@ RR_API int rr_evaluate(const rr_tables* t, const double* times_d,
  * through FP64 atomics, reproducible to rounding.  The adjoint keeps
  * npb * ng * (2 sizeof(real) + 8) bytes of tables in LDS, at most 64 KiB
  * (RR_ELIMIT beyond).  Temporary device memory, ~(160 + 8 (7 + npb) npt /
- * 2048 + 8 npb ng) bytes per parameter vector, comes from the
+ * 1024 + 8 npb ng) bytes per parameter vector, comes from the
  * stream-ordered allocator. */
 RR_API int rr_loglik_grad(const rr_tables* t, const double* times_d,
                           const int32_t* lcids_d, int32_t npt,

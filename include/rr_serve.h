@@ -31,7 +31,8 @@ typedef struct rr_server rr_server;   /* opaque, owned by the library */
  * it).  budget_bytes (>= 1 MiB) of device memory are allocated once as the
  * request arena; a request needs about npv (8 npar + 160 + npt * 4 or 8)
  * bytes of it while in flight.  max_tick_blocks (>= 1) bounds the
- * workgroups (2048 times each) of one grouped launch; smaller values favour
+ * workgroups (one wave64 over 512 times each) of one grouped launch;
+ * smaller values favour
  * latency of small requests, larger ones throughput.  Starts a worker
  * thread. */
 RR_API int rr_server_create(const rr_tables* t, int64_t budget_bytes,

@@ -6,8 +6,8 @@
 //   dlogL/dtheta = sum_t psi_t dF_t/dtheta,       F_t = 1 - mean_s delta_s
 //   delta = ip(g, k) a(z, k) / I_star                               (Eq. 5)
 //
-// k_adjoint     one workgroup per (parameter vector, tile of 2048 times),
-//               the forward kernel's layout.  Out-of-window exposures only
+// k_adjoint     one workgroup (two wave64) per (parameter vector, tile of
+//               1024 times), lanes along time.  Out-of-window exposures only
 //               add their residual to logL.  For the others the subsample
 //               loop evaluates delta together with d delta/dz and
 //               d delta/dk, and z's derivatives through the transit-centred
@@ -143,7 +143,7 @@ __device__ inline T wave_sum(T v) {
 }
 
 template <typename R, int NPBT>
-__global__ __launch_bounds__(kBlock) void k_adjoint(
+__global__ __launch_bounds__(kAdjBlock) void k_adjoint(
     const double* __restrict__ times, const int32_t* __restrict__ lcids,
     int32_t npt, LcInfo lc, const double* __restrict__ pv, int32_t npar,
     const PvConst* __restrict__ pvc, GridDev g, const R* __restrict__ T,
@@ -158,12 +158,12 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(
     double* gw = reinterpret_cast<double*>(                     // [npb][ng]
         smem_raw + ((2 * sizeof(R) * npb * ng + 7) / 8) * 8);
     double* gi = gw + npb * ng;                                 // [npb]
-    __shared__ double red[kBlock / 64][kNq + NPBT];
+    __shared__ double red[kAdjBlock / 64][kNq + NPBT];
 
     const int ipv = blockIdx.x / ntiles;
     const int tile = blockIdx.x - ipv * ntiles;
     const int tid = threadIdx.x;
-    const int t_base = tile * kTile + tid;
+    const int t_base = tile * kAdjTile + tid;
     const int nq = kNq + npb;
     double* part = partials + int64_t(blockIdx.x) * nq;
     const PvConst p = pvc[ipv];
@@ -181,14 +181,14 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(
 
     // Pass 1: residuals of exposures that cannot overlap the star.
     uint32_t todo = 0;
-    const int tfirst = tile * kTile;
-    if (!lcids && tfirst + kTile <= npt) {
+    const int tfirst = tile * kAdjTile;
+    if (!lcids && tfirst + kAdjTile <= npt) {
         // whole tile in range, one light curve (see forward_block)
         double tv[kTimesPerThread], ov[kTimesPerThread];
 #pragma unroll
         for (int j = 0; j < kTimesPerThread; ++j) {
-            tv[j] = times[tfirst + tid + j * kBlock];
-            ov[j] = double(obs[tfirst + tid + j * kBlock]);
+            tv[j] = times[tfirst + tid + j * kAdjBlock];
+            ov[j] = double(obs[tfirst + tid + j * kAdjBlock]);
         }
         const double hw = 0.5 * lc.exptime[0] * p.invP;
         const double c0 = -p.t0 * p.invP - (p.flo - hw);
@@ -205,7 +205,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(
         }
     } else {
         for (int j = 0; j < kTimesPerThread; ++j) {
-            const int it = t_base + j * kBlock;
+            const int it = t_base + j * kAdjBlock;
             if (it >= npt) continue;
             const int l = lcids ? lcids[it] : 0;
             if (l < 0 || l >= lc.nlc) { ll = NAN; continue; }
@@ -217,16 +217,16 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(
             }
         }
     }
-    __shared__ int wave_any[kBlock / 64];
+    __shared__ int wave_any[kAdjBlock / 64];
     const int wany = __any(todo != 0);
     if ((tid & 63) == 0) wave_any[tid >> 6] = wany;
     __syncthreads();
     bool any = false;
 #pragma unroll
-    for (int w = 0; w < kBlock / 64; ++w) any |= wave_any[w] != 0;
+    for (int w = 0; w < kAdjBlock / 64; ++w) any |= wave_any[w] != 0;
 
     if (any) {
-        for (int idx = tid; idx < npb * ng; idx += kBlock) {
+        for (int idx = tid; idx < npb * ng; idx += kAdjBlock) {
             const int pb = idx / ng, m = idx - pb * ng;
             const double u = (pv[int64_t(ipv) * npar + 6 + pb] - g.k0) / g.dk;
             int ik = int(floor(u));
@@ -248,7 +248,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(
         while (todo) {
             const int j = __builtin_ctz(todo);
             todo &= todo - 1;
-            const int it = t_base + j * kBlock;
+            const int it = t_base + j * kAdjBlock;
             const int l = lcids ? lcids[it] : 0;
             const int pb = lc.pb[l];
             const int nss = lc.nss[l];
@@ -327,7 +327,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(
         }
         if (want_prof) {
             __syncthreads();
-            for (int idx = tid; idx < npb * ng; idx += kBlock) {
+            for (int idx = tid; idx < npb * ng; idx += kAdjBlock) {
                 const double v = gw[idx];
                 if (v != 0.0) atomicAdd(&gldw_pv[int64_t(ipv) * npb * ng + idx], v);
             }
@@ -352,7 +352,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(
     __syncthreads();
     if (tid < nq) {
         double s = 0.0;
-        for (int w = 0; w < kBlock / 64; ++w) s += red[w][tid];
+        for (int w = 0; w < kAdjBlock / 64; ++w) s += red[w][tid];
         part[tid] = s;
     }
 }
@@ -568,7 +568,7 @@ inline unsigned nblocks(int64_t n) { return unsigned((n + kBlock - 1) / kBlock);
 template <typename R, int NPBT>
 void launch_adjoint_t(const AdjointArgs& A, size_t lds, hipStream_t s) {
     hipLaunchKernelGGL((k_adjoint<R, NPBT>), dim3(unsigned(int64_t(A.ntiles) * A.npv)),
-                       dim3(kBlock), lds, s, A.times, A.lcids, A.npt, *A.lc, A.pv, A.npar,
+                       dim3(kAdjBlock), lds, s, A.times, A.lcids, A.npt, *A.lc, A.pv, A.npar,
                        A.pvc, A.g, static_cast<const R*>(A.T), A.inv_istar,
                        static_cast<const R*>(A.obs), A.inv_sig2, A.ntiles, A.want_grad,
                        A.want_prof, A.wprof, A.partials, A.gldw_pv, A.gist_pv);

@@ -119,8 +119,9 @@ int check_eval_args(const rr_tables* t, const double* times_d,
         if (!times_d) return einval("times is NULL");
         if (!pv_d) return einval("pv is NULL");
     }
-    const int64_t ntiles = (int64_t(npt) + kTile - 1) / kTile;
-    if (ntiles * npv * kBlock >= (int64_t(1) << 32))
+    const int64_t ntiles = (int64_t(npt) + kAdjTile - 1) / kAdjTile;   // the larger tiles
+    if (ntiles * npv * kAdjBlock >= (int64_t(1) << 32) ||
+        ((int64_t(npt) + kFwdTile - 1) / kFwdTile) * npv * kFwdBlock >= (int64_t(1) << 32))
         return elimit("npv * npt too large for one launch");
     return RR_OK;
 }
@@ -293,7 +294,7 @@ RR_API int rr_loglik_grad(const rr_tables* t, const double* times_d,
         }
         return RR_OK;
     }
-    const int32_t ntiles = npt > 0 ? (npt + kTile - 1) / kTile : 1;
+    const int32_t ntiles = npt > 0 ? (npt + kAdjTile - 1) / kAdjTile : 1;
     const int32_t nq = 7 + t->npb;
     const bool prof = grad_prof_d != nullptr;
     const GridDev g = grid_dev(t);

@@ -9,10 +9,10 @@
 //               the planet is either behind the star or farther than 1 + k
 //               from its centre, so the flux is exactly 1 (kept in phase
 //               units, so the test is frac(phase - lo) < width);
-//   k_forward   one workgroup per (parameter vector, tile of 2048 times),
-//               lanes along time so loads of the shared time array and the
-//               stores of out[pv][t] are coalesced; each wave64 owns 512
-//               consecutive times and runs alone.  Pass 1 reduces each
+//   k_forward   one wave64 workgroup per (parameter vector, tile of 512
+//               consecutive times), lanes along time so loads of the shared
+//               time array and the stores of out[pv][t] are coalesced; each
+//               wave runs alone (no LDS, no barrier).  Pass 1 reduces each
 //               mid-exposure time to an offset from conjunction (FP64),
 //               writes 1 for the exposures outside the window (on the
 //               aligned fast path for all of them, with 16-B stores) and
@@ -119,7 +119,7 @@ __device__ inline void forward_block(const FwdJob& job, const LcInfo& lc, int ip
     const int32_t* __restrict__ lcids = job.lcids;
     const double* __restrict__ pv = job.pv;
     // exposure r of this lane (pass 2 order, and pass 1 off the fast path)
-    const int w0 = tile * kTile + (threadIdx.x >> 6) * kSpan;
+    const int w0 = tile * kFwdTile + (threadIdx.x >> 6) * kSpan;
     const int t_base = w0 + lane;
     R* __restrict__ orow = static_cast<R*>(job.out) + int64_t(ipv) * npt;
     const PvConst p = job.pvc[ipv];
@@ -232,7 +232,7 @@ __device__ inline void forward_block(const FwdJob& job, const LcInfo& lc, int ip
         }
         const int N = nmax;
         if (nmin == nmax && N >= 2 && N <= 32) {
-            __shared__ uint16_t packed[kBlock / 64][kSpan];
+            __shared__ uint16_t packed[kFwdBlock / 64][kSpan];
             uint16_t* pk = packed[threadIdx.x >> 6];
             const uint64_t below = __lanemask_lt();
             int total = 0;
@@ -290,7 +290,7 @@ __device__ inline void forward_block(const FwdJob& job, const LcInfo& lc, int ip
 // One population (rr_evaluate): workgroup (x, y) -> row pv0 + y, tile x.
 // kSubPar: some light curve has nss > 1.
 template <typename R, bool kSubPar>
-__global__ __launch_bounds__(kBlock) void k_forward(FwdJob job, LcInfo lc, GridDev g,
+__global__ __launch_bounds__(kFwdBlock) void k_forward(FwdJob job, LcInfo lc, GridDev g,
                                                     const R* __restrict__ T,
                                                     const double* __restrict__ inv_istar) {
     const int ipv = job.pv0 + blockIdx.y;
@@ -301,7 +301,7 @@ __global__ __launch_bounds__(kBlock) void k_forward(FwdJob job, LcInfo lc, GridD
 // Grouped launch (serving): workgroup b belongs to the last job whose
 // block0 <= b; jobs come from several requests and time series.
 template <typename R, bool kSubPar>
-__global__ __launch_bounds__(kBlock) void k_forward_jobs(JobTable jt, GridDev g,
+__global__ __launch_bounds__(kFwdBlock) void k_forward_jobs(JobTable jt, GridDev g,
                                                          const R* __restrict__ T,
                                                          const double* __restrict__ inv_istar) {
     const int b = blockIdx.x;
@@ -346,7 +346,7 @@ hipError_t launch_forward(const rr_tables* t, const double* times,
     FwdJob job;
     job.times = times; job.lcids = lcids; job.lc = nullptr; job.pv = pv; job.pvc = pvc;
     job.out = out; job.npt = npt; job.npar = npar; job.pv0 = 0; job.npv = npv;
-    job.ntiles = (npt + kTile - 1) / kTile; job.block0 = 0; job.max_nss = 1;
+    job.ntiles = (npt + kFwdTile - 1) / kFwdTile; job.block0 = 0; job.max_nss = 1;
     for (int l = 0; l < lc.nlc; ++l) job.max_nss = lc.nss[l] > job.max_nss ? lc.nss[l] : job.max_nss;
     const KernelEvents ev = kernel_events();
     if (ev.before) {
@@ -360,17 +360,17 @@ hipError_t launch_forward(const rr_tables* t, const double* times,
         const dim3 grid(unsigned(job.ntiles), unsigned(npv - r0 < 65535 ? npv - r0 : 65535));
         if (precision == RR_FP64) {
             if (sub)
-                hipLaunchKernelGGL((k_forward<double, true>), grid, dim3(kBlock), 0, s, job, lc,
+                hipLaunchKernelGGL((k_forward<double, true>), grid, dim3(kFwdBlock), 0, s, job, lc,
                                    g, t->T64, t->inv_istar);
             else
-                hipLaunchKernelGGL((k_forward<double, false>), grid, dim3(kBlock), 0, s, job, lc,
+                hipLaunchKernelGGL((k_forward<double, false>), grid, dim3(kFwdBlock), 0, s, job, lc,
                                    g, t->T64, t->inv_istar);
         } else {
             if (sub)
-                hipLaunchKernelGGL((k_forward<float, true>), grid, dim3(kBlock), 0, s, job, lc,
+                hipLaunchKernelGGL((k_forward<float, true>), grid, dim3(kFwdBlock), 0, s, job, lc,
                                    g, t->T32, t->inv_istar);
             else
-                hipLaunchKernelGGL((k_forward<float, false>), grid, dim3(kBlock), 0, s, job, lc,
+                hipLaunchKernelGGL((k_forward<float, false>), grid, dim3(kFwdBlock), 0, s, job, lc,
                                    g, t->T32, t->inv_istar);
         }
     }
@@ -388,17 +388,17 @@ hipError_t launch_forward_jobs(const rr_tables* t, const JobTable& jt, int32_t n
     const dim3 grid{unsigned(nblocks_total), 1u, 1u};
     if (precision == RR_FP64) {
         if (sub)
-            hipLaunchKernelGGL((k_forward_jobs<double, true>), grid, dim3(kBlock), 0, s, jt, g,
+            hipLaunchKernelGGL((k_forward_jobs<double, true>), grid, dim3(kFwdBlock), 0, s, jt, g,
                                t->T64, t->inv_istar);
         else
-            hipLaunchKernelGGL((k_forward_jobs<double, false>), grid, dim3(kBlock), 0, s, jt, g,
+            hipLaunchKernelGGL((k_forward_jobs<double, false>), grid, dim3(kFwdBlock), 0, s, jt, g,
                                t->T64, t->inv_istar);
     } else {
         if (sub)
-            hipLaunchKernelGGL((k_forward_jobs<float, true>), grid, dim3(kBlock), 0, s, jt, g,
+            hipLaunchKernelGGL((k_forward_jobs<float, true>), grid, dim3(kFwdBlock), 0, s, jt, g,
                                t->T32, t->inv_istar);
         else
-            hipLaunchKernelGGL((k_forward_jobs<float, false>), grid, dim3(kBlock), 0, s, jt, g,
+            hipLaunchKernelGGL((k_forward_jobs<float, false>), grid, dim3(kFwdBlock), 0, s, jt, g,
                                t->T32, t->inv_istar);
     }
     return hipGetLastError();

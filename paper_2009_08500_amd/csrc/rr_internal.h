@@ -18,9 +18,16 @@ namespace rr {
 #ifndef RR_TIMES_PER_THREAD
 #define RR_TIMES_PER_THREAD 8
 #endif
-constexpr int kBlock = 256;          // threads per workgroup (4 wave64)
+constexpr int kBlock = 256;          // threads per workgroup of the table,
+                                     // setup and reduction kernels (4 wave64)
 constexpr int kTimesPerThread = RR_TIMES_PER_THREAD;   // times per thread
-constexpr int kTile = kBlock * kTimesPerThread;
+// Forward kernels: one wave64 per workgroup (measured faster than 2 or 4:
+// a finished wave frees its slot at once), each owning kFwdTile times.
+constexpr int kFwdBlock = 64;
+constexpr int kFwdTile = kFwdBlock * kTimesPerThread;
+// Log-likelihood kernel: two wave64 per workgroup share the LDS tables.
+constexpr int kAdjBlock = 128;
+constexpr int kAdjTile = kAdjBlock * kTimesPerThread;
 constexpr int kMaxLdsBytes = 64 * 1024;   // LDS budget for the adjoint's
                                           // per-workgroup tables
 

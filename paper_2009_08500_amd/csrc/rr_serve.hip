@@ -384,7 +384,7 @@ RR_API int rr_server_add_series(rr_server* s, const double* times, const int32_t
         const int32_t l = lcids ? lcids[i] : 0;
         se.nsub += (l >= 0 && l < nlc) ? lc.nss[l] : 0;
     }
-    se.ntiles = (npt + kTile - 1) / kTile;
+    se.ntiles = (npt + kFwdTile - 1) / kFwdTile;
     for (int32_t i = 0; i < nlc; ++i) se.max_nss = std::max(se.max_nss, lc.nss[i]);
     hipError_t e = hipMalloc((void**)&se.times, sizeof(double) * npt);
     if (e == hipSuccess && lcids) e = hipMalloc((void**)&se.lcids, sizeof(int32_t) * npt);

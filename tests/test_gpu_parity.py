@@ -127,9 +127,10 @@ def test_single_light_curve_against_analytic_model(rr):
     assert np.abs(f32[0].astype(np.float64) - fm).max() <= 1e-6
 
 
-@pytest.mark.parametrize("npt", [1, 7, 2047, 2048, 2049, 5000])
+@pytest.mark.parametrize("npt", [1, 7, 511, 512, 513, 1023, 1024, 1025, 2047, 2048, 2049, 5000])
 def test_population_ragged_sizes(rr, npt):
-    """Tiles of 2048 times per workgroup: sizes around the tile edge."""
+    """Tiles of 512 (forward) and 1024 (log-likelihood) times per workgroup,
+    and the vector fast path's whole-span condition: sizes around the edges."""
     w = wl.population(npv=24, npt=npt)
     grid = wl.TEST_GRID
     pv = w["pv"].copy()
