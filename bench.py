@@ -88,8 +88,9 @@ def valu_view(kernel, kernel_ms):
 def time_path(rr, tab, series, pv, prec, steps, warmup, lib):
     """Throughput: `steps` back-to-back calls between two synchronisations
     (no per-step instrumentation).  Then the same number of calls again with
-    HIP events around each call and, through rr_set_kernel_events, around its
-    forward kernel alone, for latency percentiles and the kernel time."""
+    HIP events around each call, for latency percentiles, and, through
+    rr_set_kernel_events, as the forward kernel launch's own start and stop
+    events, for the kernel time."""
     import torch
     ev_fn = rr.Evaluator(tab, series, pv.shape[0], prec)
     for _ in range(warmup):

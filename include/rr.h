@@ -178,12 +178,13 @@ RR_API int rr_loglik_grad(const rr_tables* t, const double* times_d,
                           double* grad_prof_d, hipStream_t stream);
 
 /* Instrumentation: the next rr_evaluate / rr_loglik_grad calls made by the
- * calling thread record `before` on their stream immediately before
- * launching their main kernel and `after` immediately after it, so the event
- * pair brackets that one kernel (the per-parameter-vector setup kernel that
- * precedes it is outside the pair).  Both events must be created by the
- * caller on the device of the tables; NULL, NULL turns this off.  Returns
- * RR_EINVAL if exactly one of them is NULL. */
+ * calling thread launch their main kernel with `before` and `after` as the
+ * launch's own start and stop events (hipExtLaunchKernel), so the pair times
+ * that kernel's execution alone (the per-parameter-vector setup kernel that
+ * precedes it is outside the pair; with more than 65 535 parameter vectors
+ * the pair spans the consecutive launches of the main kernel).  Both events
+ * must be created by the caller on the device of the tables; NULL, NULL
+ * turns this off.  Returns RR_EINVAL if exactly one of them is NULL. */
 RR_API int rr_set_kernel_events(hipEvent_t before, hipEvent_t after);
 
 /* Release a handle (device and host memory).  The caller must make sure no

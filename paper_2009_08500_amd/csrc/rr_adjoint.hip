@@ -566,19 +566,19 @@ __global__ void k_prof_grad(const double* __restrict__ gldp, const double* __res
 inline unsigned nblocks(int64_t n) { return unsigned((n + kBlock - 1) / kBlock); }
 
 template <typename R, int NPBT>
-void launch_adjoint_t(const AdjointArgs& A, size_t lds, hipStream_t s) {
-    hipLaunchKernelGGL((k_adjoint<R, NPBT>), dim3(unsigned(int64_t(A.ntiles) * A.npv)),
-                       dim3(kAdjBlock), lds, s, A.times, A.lcids, A.npt, *A.lc, A.pv, A.npar,
-                       A.pvc, A.g, static_cast<const R*>(A.T), A.inv_istar,
-                       static_cast<const R*>(A.obs), A.inv_sig2, A.ntiles, A.want_grad,
-                       A.want_prof, A.wprof, A.partials, A.gldw_pv, A.gist_pv);
+void launch_adjoint_t(const AdjointArgs& A, size_t lds, hipStream_t s, const KernelEvents& ev) {
+    launch_timed(k_adjoint<R, NPBT>, dim3(unsigned(int64_t(A.ntiles) * A.npv)), dim3(kAdjBlock),
+                 lds, s, ev.before, ev.after, A.times, A.lcids, A.npt, *A.lc, A.pv, A.npar,
+                 A.pvc, A.g, static_cast<const R*>(A.T), A.inv_istar,
+                 static_cast<const R*>(A.obs), A.inv_sig2, A.ntiles, A.want_grad,
+                 A.want_prof, A.wprof, A.partials, A.gldw_pv, A.gist_pv);
 }
 
 template <typename R>
-void launch_adjoint_r(const AdjointArgs& A, size_t lds, hipStream_t s) {
-    if (A.g.npb <= 1) launch_adjoint_t<R, 1>(A, lds, s);
-    else if (A.g.npb <= 4) launch_adjoint_t<R, 4>(A, lds, s);
-    else launch_adjoint_t<R, 16>(A, lds, s);
+void launch_adjoint_r(const AdjointArgs& A, size_t lds, hipStream_t s, const KernelEvents& ev) {
+    if (A.g.npb <= 1) launch_adjoint_t<R, 1>(A, lds, s, ev);
+    else if (A.g.npb <= 4) launch_adjoint_t<R, 4>(A, lds, s, ev);
+    else launch_adjoint_t<R, 16>(A, lds, s, ev);
 }
 
 }  // namespace
@@ -604,18 +604,10 @@ hipError_t launch_adjoint(const AdjointArgs& A, int32_t precision, hipStream_t s
         if (e != hipSuccess) return e;
     }
     const KernelEvents ev = kernel_events();
-    if (ev.before) {
-        hipError_t e = hipEventRecord(ev.before, s);
-        if (e != hipSuccess) return e;
-    }
-    if (precision == RR_FP64) launch_adjoint_r<double>(A, lds, s);
-    else launch_adjoint_r<float>(A, lds, s);
+    if (precision == RR_FP64) launch_adjoint_r<double>(A, lds, s, ev);
+    else launch_adjoint_r<float>(A, lds, s, ev);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (ev.after) {
-        e = hipEventRecord(ev.after, s);
-        if (e != hipSuccess) return e;
-    }
     hipLaunchKernelGGL(k_adjoint_reduce, dim3(nblocks(int64_t(A.npv) * (kNq + A.g.npb))),
                        dim3(kBlock), 0, s, A.partials, A.npv, A.ntiles, A.g.npb, A.logl,
                        A.grad);

@@ -349,34 +349,31 @@ hipError_t launch_forward(const rr_tables* t, const double* times,
     job.ntiles = (npt + kFwdTile - 1) / kFwdTile; job.block0 = 0; job.max_nss = 1;
     for (int l = 0; l < lc.nlc; ++l) job.max_nss = lc.nss[l] > job.max_nss ? lc.nss[l] : job.max_nss;
     const KernelEvents ev = kernel_events();
-    if (ev.before) {
-        hipError_t e = hipEventRecord(ev.before, s);
-        if (e != hipSuccess) return e;
-    }
     const bool sub = job.max_nss > 1;
     // rows along grid y, at most 65535 per launch
     for (int32_t r0 = 0; r0 < npv; r0 += 65535) {
         job.pv0 = r0;
         const dim3 grid(unsigned(job.ntiles), unsigned(npv - r0 < 65535 ? npv - r0 : 65535));
+        const dim3 block(kFwdBlock);
+        hipEvent_t st = r0 == 0 ? ev.before : nullptr;
+        hipEvent_t sp = npv - r0 <= 65535 ? ev.after : nullptr;
         if (precision == RR_FP64) {
             if (sub)
-                hipLaunchKernelGGL((k_forward<double, true>), grid, dim3(kFwdBlock), 0, s, job, lc,
-                                   g, t->T64, t->inv_istar);
+                launch_timed(k_forward<double, true>, grid, block, 0, s, st, sp, job, lc, g,
+                             t->T64, t->inv_istar);
             else
-                hipLaunchKernelGGL((k_forward<double, false>), grid, dim3(kFwdBlock), 0, s, job, lc,
-                                   g, t->T64, t->inv_istar);
+                launch_timed(k_forward<double, false>, grid, block, 0, s, st, sp, job, lc, g,
+                             t->T64, t->inv_istar);
         } else {
             if (sub)
-                hipLaunchKernelGGL((k_forward<float, true>), grid, dim3(kFwdBlock), 0, s, job, lc,
-                                   g, t->T32, t->inv_istar);
+                launch_timed(k_forward<float, true>, grid, block, 0, s, st, sp, job, lc, g,
+                             t->T32, t->inv_istar);
             else
-                hipLaunchKernelGGL((k_forward<float, false>), grid, dim3(kFwdBlock), 0, s, job, lc,
-                                   g, t->T32, t->inv_istar);
+                launch_timed(k_forward<float, false>, grid, block, 0, s, st, sp, job, lc, g,
+                             t->T32, t->inv_istar);
         }
     }
-    hipError_t e = hipGetLastError();
-    if (e == hipSuccess && ev.after) e = hipEventRecord(ev.after, s);
-    return e;
+    return hipGetLastError();
 }
 
 hipError_t launch_forward_jobs(const rr_tables* t, const JobTable& jt, int32_t nblocks_total,

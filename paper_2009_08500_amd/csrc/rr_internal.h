@@ -4,6 +4,7 @@
 // FP64/int32 so that host code can fill and launch them.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -143,6 +144,18 @@ void set_error(const std::string& msg);
 // Events bracketing the next main-kernel launch of this thread (or null).
 struct KernelEvents { hipEvent_t before = nullptr, after = nullptr; };
 KernelEvents& kernel_events();
+
+// Launches `kernel`; if st or sp is set they become the launch's own start
+// and stop events (recorded at the kernel's execution, not around the
+// launch call).
+template <typename K, typename... Args>
+inline void launch_timed(K kernel, dim3 grid, dim3 block, size_t lds, hipStream_t s,
+                         hipEvent_t st, hipEvent_t sp, Args... args) {
+    if (st || sp)
+        hipExtLaunchKernelGGL(kernel, grid, block, uint32_t(lds), s, st, sp, 0u, args...);
+    else
+        hipLaunchKernelGGL(kernel, grid, block, lds, s, args...);
+}
 int hip_fail(hipError_t err, const char* what);
 // Device workspace of at least `bytes` for `stream`, owned by the tables.
 hipError_t stream_workspace(rr_tables* t, hipStream_t stream, size_t bytes, void** out);
