@@ -136,17 +136,37 @@ __device__ inline void forward_block(const FwdJob& job, const LcInfo& lc, int ip
     // of `todo` marks exposure t_base + 64 r as one that may overlap it.
     uint32_t todo = 0;
     constexpr int kVec = 16 / int(sizeof(R));            // outputs per 16-B store
-    const bool vec = !lcids && w0 + kSpan <= npt &&
-                     ((reinterpret_cast<uintptr_t>(orow + w0) |
-                       reinterpret_cast<uintptr_t>(times)) & 15) == 0;
+    constexpr int kGroups = kTimesPerThread / kVec;
+    bool vec = w0 + kSpan <= npt &&
+               ((reinterpret_cast<uintptr_t>(orow + w0) | reinterpret_cast<uintptr_t>(times) |
+                 reinterpret_cast<uintptr_t>(lcids)) & 15) == 0;
+    int lvec = 0;                                       // the span's light curve
+    if (vec && lcids) {
+        // The fast path also serves a span that lies in one light curve:
+        // the lane reads its light-curve ids in the same grouping as its
+        // times (kVec consecutive ids per group).
+        typedef int IV __attribute__((ext_vector_type(kVec)));
+        bool same = true;
+        int first = 0;
+#pragma unroll
+        for (int q = 0; q < kGroups; ++q) {
+            const IV ids = *reinterpret_cast<const IV*>(lcids + w0 + q * (64 * kVec) + lane * kVec);
+#pragma unroll
+            for (int v = 0; v < kVec; ++v) {
+                if (q == 0 && v == 0) first = ids[0];
+                same = same && ids[v] == first;
+            }
+        }
+        lvec = __shfl(first, 0);
+        vec = __all(same && first == lvec) && lvec >= 0 && lvec < lc.nlc;
+    }
     if (vec) {
-        // Whole span in range, one light curve, 16-B aligned: in group q the
-        // lane owns the kVec consecutive exposures w0 + 64 kVec q + kVec lane
-        // + v (16-B loads of times, one 16-B store of ones), with no bounds
-        // or light-curve checks.  Phase g = t/P + c0 with
+        // Whole span in range, in one light curve, 16-B aligned: in group q
+        // the lane owns the kVec consecutive exposures w0 + 64 kVec q +
+        // kVec lane + v (16-B loads of times, one 16-B store of ones), with
+        // no bounds or light-curve checks.  Phase g = t/P + c0 with
         // c0 = -t0/P - (window start) by one FMA.
         typedef R RV __attribute__((ext_vector_type(kVec)));
-        constexpr int kGroups = kTimesPerThread / kVec;
         double tv[kTimesPerThread];
 #pragma unroll
         for (int q = 0; q < kGroups; ++q) {
@@ -158,7 +178,7 @@ __device__ inline void forward_block(const FwdJob& job, const LcInfo& lc, int ip
                 tv[q * kVec + v + 1] = d.y;
             }
         }
-        const double hw = 0.5 * lc.exptime[0] * p.invP;
+        const double hw = 0.5 * lc.exptime[lvec] * p.invP;
         const double c0 = -p.t0 * p.invP - (p.flo - hw);
         const double wn = p.wn + 2.0 * hw;
         const RV ones = R(1);
