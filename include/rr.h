@@ -162,12 +162,14 @@ RR_API int rr_evaluate(const rr_tables* t, const double* times_d,
  * wprof_d   device double[npv] weights for grad_prof_d, or NULL for ones.
  * At least one output must be requested.  Invalid rows give NaN in logl
  * and grad and contribute nothing to grad_prof.  logl and grad are summed
- * in FP64 in a fixed order (bitwise reproducible); grad_prof accumulates
- * through FP64 atomics, reproducible to rounding.  The adjoint keeps
- * npb * ng * (2 sizeof(real) + 8) bytes of tables in LDS, at most 64 KiB
- * (RR_ELIMIT beyond).  Temporary device memory, ~(160 + 8 (7 + npb) npt /
- * 1024 + 8 npb ng) bytes per parameter vector, comes from the
- * stream-ordered allocator. */
+ * in FP64 in a fixed order (bitwise reproducible); grad_prof sums each
+ * workgroup's share through LDS FP64 atomics and adds the shares in a fixed
+ * order, reproducible to rounding.  The adjoint keeps npb * ng * (2
+ * sizeof(real) + 8) bytes of tables in LDS, at most 64 KiB (RR_ELIMIT
+ * beyond).  Temporary device memory comes from the stream-ordered
+ * allocator: ~(160 + 8 (7 + npb) npt / 1024) bytes per parameter vector,
+ * and with grad_prof a further 8 npb ng bytes per vector plus at most
+ * 512 MiB of partial sums. */
 RR_API int rr_loglik_grad(const rr_tables* t, const double* times_d,
                           const int32_t* lcids_d, int32_t npt,
                           const int32_t* pbids, const int32_t* nss,

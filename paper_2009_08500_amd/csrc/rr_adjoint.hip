@@ -6,8 +6,9 @@
 //   dlogL/dtheta = sum_t psi_t dF_t/dtheta,       F_t = 1 - mean_s delta_s
 //   delta = ip(g, k) a(z, k) / I_star                               (Eq. 5)
 //
-// k_adjoint     one workgroup (two wave64) per (parameter vector, tile of
-//               1024 times), lanes along time.  Out-of-window exposures only
+// k_adjoint     workgroups of two wave64 over tiles of 1024 times of one
+//               parameter vector (one tile each without the profile
+//               gradient), lanes along time.  Out-of-window exposures only
 //               add their residual to logL.  For the others the subsample
 //               loop evaluates delta together with d delta/dz and
 //               d delta/dk, and z's derivatives through the transit-centred
@@ -16,17 +17,23 @@
 //               da/dz = -chord and da/dk = 2 k kappa_0.  Per-lane sums are
 //               FP64 and reduced in a fixed order (butterfly within the wave,
 //               then waves in order) to one partial per workgroup.  With the
-//               profile gradient requested, a second subsample loop scatters
+//               profile gradient requested each workgroup runs several
+//               consecutive tiles, and a second subsample loop scatters
 //               psi-weighted lerp weights into the workgroup's LDS copy of
-//               d logL / d ldw and d logL / d I_star, which are added to per
-//               parameter vector buffers.
-//   k_adjoint_reduce   per parameter vector, the workgroup partials in tile
-//               order -> logL and the gradient row.
+//               d logL / d ldw and d logL / d I_star, stored once per
+//               workgroup; k_prof_seg_sum adds a vector's workgroups in order
+//               (no accumulation across workgroups).
+//   k_adjoint_reduce   per parameter vector, the workgroup partials in a
+//               fixed order (lanes over tiles, then a butterfly) -> logL and
+//               the gradient row.
 //   k_table_grad d logL / d T[pb][i][m] from the per-vector d logL / d ldw
-//               through the k-interpolation weights, vectors in order.
+//               through the k-interpolation weights: chunks of vectors in
+//               parallel, each in order, then the chunks in order.
 //   k_ldp_grad   d logL / d ldp = sum_{i,m} W[i][j][m] dT[i][m] (fixed tree).
 //   k_prof_grad  back through the profile interpolation and I_star (both
 //               linear in the samples) to d logL / d I_s.
+#include <algorithm>
+
 #include "rr_device.h"
 
 namespace rr {
@@ -142,15 +149,26 @@ __device__ inline T wave_sum(T v) {
     return v;
 }
 
-template <typename R, int NPBT>
+// Workgroup (ipv, c) = blockIdx.x = ipv nparts + c handles the time tiles
+// [c tpp, (c + 1) tpp) of vector ipv (tpp = tiles per part, 1 without the
+// profile gradient).  Per tile, pass 1 adds the residuals of exposures that
+// cannot overlap the star; pass 2 runs the subsample loop of the others.
+// The LDS tables (ldw and its k-derivative) are built at the first tile with
+// in-window work.  Per-lane sums go to one partial per workgroup; with the
+// profile gradient the workgroup's LDS sums of d logL / d ldw and
+// d logL / d I_star are stored once at the end, to slot (ipv, c) of
+// seg_gw / seg_gi with flag 1 (flag 0 and nothing else if no exposure was in
+// the window), or, with seg_flag NULL (one part per vector), as the final
+// per-vector sums.
+template <typename R, int NPBT, bool kProf>
 __global__ __launch_bounds__(kAdjBlock) void k_adjoint(
     const double* __restrict__ times, const int32_t* __restrict__ lcids,
     int32_t npt, LcInfo lc, const double* __restrict__ pv, int32_t npar,
     const PvConst* __restrict__ pvc, GridDev g, const R* __restrict__ T,
     const double* __restrict__ inv_istar, const R* __restrict__ obs,
-    double inv_sig2, int32_t ntiles, int32_t want_grad, int32_t want_prof,
+    double inv_sig2, int32_t ntiles, int32_t nparts, int32_t tpp, int32_t want_grad,
     const double* __restrict__ wprof, double* __restrict__ partials,
-    double* __restrict__ gldw_pv, double* __restrict__ gist_pv) {
+    double* __restrict__ seg_gw, double* __restrict__ seg_gi, int32_t* __restrict__ seg_flag) {
     extern __shared__ unsigned char smem_raw[];
     const int npb = g.npb, ng = g.ng;
     R* ldw = reinterpret_cast<R*>(smem_raw);                    // [npb][ng]
@@ -159,17 +177,27 @@ __global__ __launch_bounds__(kAdjBlock) void k_adjoint(
         smem_raw + ((2 * sizeof(R) * npb * ng + 7) / 8) * 8);
     double* gi = gw + npb * ng;                                 // [npb]
     __shared__ double red[kAdjBlock / 64][kNq + NPBT];
+    __shared__ int wave_any[2][kAdjBlock / 64];                 // by tile parity
 
-    const int ipv = blockIdx.x / ntiles;
-    const int tile = blockIdx.x - ipv * ntiles;
-    const int tid = threadIdx.x;
-    const int t_base = tile * kAdjTile + tid;
+    const int64_t slot = blockIdx.x;
+    const int ipv = int(slot / nparts);
+    const int c = int(slot - int64_t(ipv) * nparts);
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int nq = kNq + npb;
-    double* part = partials + int64_t(blockIdx.x) * nq;
+    double* part = partials + slot * nq;
     const PvConst p = pvc[ipv];
 
     if (!(p.flags & kValid)) {
         if (tid < nq) part[tid] = NAN;
+        if (kProf) {
+            if (seg_flag) {
+                if (tid == 0) seg_flag[slot] = 0;
+            } else {
+                for (int idx = tid; idx < npb * ng; idx += kAdjBlock)
+                    seg_gw[slot * npb * ng + idx] = 0.0;
+                if (tid < npb) seg_gi[slot * npb + tid] = 0.0;
+            }
+        }
         return;
     }
 
@@ -178,73 +206,85 @@ __global__ __launch_bounds__(kAdjBlock) void k_adjoint(
     double gk[NPBT];
 #pragma unroll
     for (int q = 0; q < NPBT; ++q) gk[q] = 0.0;
+    bool ready = false;                  // LDS tables built (uniform)
 
-    // Pass 1: residuals of exposures that cannot overlap the star.
-    uint32_t todo = 0;
-    const int tfirst = tile * kAdjTile;
-    if (!lcids && tfirst + kAdjTile <= npt) {
-        // whole tile in range, one light curve (see forward_block)
-        double tv[kTimesPerThread], ov[kTimesPerThread];
+    // without the profile gradient: exactly one tile, tile c
+    const int tile0 = kProf ? c * tpp : c;
+    const int tile_end = kProf ? min(ntiles, (c + 1) * tpp) : c + 1;
+    for (int tile = tile0; tile < tile_end; ++tile) {
+        const int t_base = tile * kAdjTile + tid;
+        // Pass 1: residuals of exposures that cannot overlap the star.
+        uint32_t todo = 0;
+        const int tfirst = tile * kAdjTile;
+        if (!lcids && tfirst + kAdjTile <= npt) {
+            // whole tile in range, one light curve (see forward_block)
+            double tv[kTimesPerThread], ov[kTimesPerThread];
 #pragma unroll
-        for (int j = 0; j < kTimesPerThread; ++j) {
-            tv[j] = times[tfirst + tid + j * kAdjBlock];
-            ov[j] = double(obs[tfirst + tid + j * kAdjBlock]);
-        }
-        const double hw = 0.5 * lc.exptime[0] * p.invP;
-        const double c0 = -p.t0 * p.invP - (p.flo - hw);
-        const double wn = p.wn + 2.0 * hw;
+            for (int j = 0; j < kTimesPerThread; ++j) {
+                tv[j] = times[tfirst + tid + j * kAdjBlock];
+                ov[j] = double(obs[tfirst + tid + j * kAdjBlock]);
+            }
+            const double hw = 0.5 * lc.exptime[0] * p.invP;
+            const double c0 = -p.t0 * p.invP - (p.flo - hw);
+            const double wn = p.wn + 2.0 * hw;
 #pragma unroll
-        for (int j = 0; j < kTimesPerThread; ++j) {
-            const double gph = fma(tv[j], p.invP, c0);
-            if (gph - floor(gph) < wn) {
-                todo |= 1u << j;
-            } else {
-                const double r = ov[j] - 1.0;
-                ll -= 0.5 * r * r * inv_sig2;
+            for (int j = 0; j < kTimesPerThread; ++j) {
+                const double gph = fma(tv[j], p.invP, c0);
+                if (gph - floor(gph) < wn) {
+                    todo |= 1u << j;
+                } else {
+                    const double r = ov[j] - 1.0;
+                    ll -= 0.5 * r * r * inv_sig2;
+                }
+            }
+        } else {
+            for (int j = 0; j < kTimesPerThread; ++j) {
+                const int it = t_base + j * kAdjBlock;
+                if (it >= npt) continue;
+                const int l = lcids ? lcids[it] : 0;
+                if (l < 0 || l >= lc.nlc) { ll = NAN; continue; }
+                if (in_phase_window((times[it] - p.t0) * p.invP, p, 0.5 * lc.exptime[l] * p.invP)) {
+                    todo |= 1u << j;
+                } else {
+                    const double r = double(obs[it]) - 1.0;
+                    ll -= 0.5 * r * r * inv_sig2;
+                }
             }
         }
-    } else {
-        for (int j = 0; j < kTimesPerThread; ++j) {
-            const int it = t_base + j * kAdjBlock;
-            if (it >= npt) continue;
-            const int l = lcids ? lcids[it] : 0;
-            if (l < 0 || l >= lc.nlc) { ll = NAN; continue; }
-            if (in_phase_window((times[it] - p.t0) * p.invP, p, 0.5 * lc.exptime[l] * p.invP)) {
-                todo |= 1u << j;
-            } else {
-                const double r = double(obs[it]) - 1.0;
-                ll -= 0.5 * r * r * inv_sig2;
-            }
-        }
-    }
-    __shared__ int wave_any[kAdjBlock / 64];
-    const int wany = __any(todo != 0);
-    if ((tid & 63) == 0) wave_any[tid >> 6] = wany;
-    __syncthreads();
-    bool any = false;
-#pragma unroll
-    for (int w = 0; w < kAdjBlock / 64; ++w) any |= wave_any[w] != 0;
-
-    if (any) {
-        for (int idx = tid; idx < npb * ng; idx += kAdjBlock) {
-            const int pb = idx / ng, m = idx - pb * ng;
-            const double u = (pv[int64_t(ipv) * npar + 6 + pb] - g.k0) / g.dk;
-            int ik = int(floor(u));
-            ik = ik < 0 ? 0 : (ik > g.nk - 2 ? g.nk - 2 : ik);
-            const R ak = R(u - ik);
-            const R* t0r = T + (int64_t(pb) * g.nk + ik) * ng;
-            ldw[idx] = (R(1) - ak) * t0r[m] + ak * t0r[ng + m];
-            dTk[idx] = (t0r[ng + m] - t0r[m]) * R(g.inv_dk);
-            gw[idx] = 0.0;
-        }
-        if (tid < npb) gi[tid] = 0.0;
+        // wave_any is double-buffered by tile parity: a wave that runs ahead
+        // to the next tile writes the other half while slower waves read
+        const int par = tile & 1;
+        const int wany = __any(todo != 0);
+        if (lane == 0) wave_any[par][wave] = wany;
         __syncthreads();
+        bool any = false;
+#pragma unroll
+        for (int w = 0; w < kAdjBlock / 64; ++w) any |= wave_any[par][w] != 0;
+        if (!any) continue;
+
+        if (!ready) {
+            for (int idx = tid; idx < npb * ng; idx += kAdjBlock) {
+                const int pb = idx / ng, m = idx - pb * ng;
+                const double u = (pv[int64_t(ipv) * npar + 6 + pb] - g.k0) / g.dk;
+                int ik = int(floor(u));
+                ik = ik < 0 ? 0 : (ik > g.nk - 2 ? g.nk - 2 : ik);
+                const R ak = R(u - ik);
+                const R* t0r = T + (int64_t(pb) * g.nk + ik) * ng;
+                ldw[idx] = (R(1) - ak) * t0r[m] + ak * t0r[ng + m];
+                dTk[idx] = (t0r[ng + m] - t0r[m]) * R(g.inv_dk);
+                if (kProf) gw[idx] = 0.0;
+            }
+            if (kProf && tid < npb) gi[tid] = 0.0;
+            __syncthreads();
+            ready = true;
+        }
 
         const OrbitR<R> orb(p);
         const DerivR<R> dv(make_pv_deriv(p, pv[int64_t(ipv) * npar + 3]));
         const R gscale = R(g.gscale);
         const R invP = R(p.invP);
-        const double wrow = wprof ? wprof[ipv] : 1.0;
+
+        // Pass 2: the exposures that may overlap the star.
         while (todo) {
             const int j = __builtin_ctz(todo);
             todo &= todo - 1;
@@ -302,8 +342,9 @@ __global__ __launch_bounds__(kAdjBlock) void k_adjoint(
 #pragma unroll
                 for (int q = 0; q < NPBT; ++q) gk[q] += (q == pb) ? wgt * double(gkt) : 0.0;
             }
-            if (want_prof) {
-                const double cw = wgt * wrow;
+            if (kProf) {
+                // psi-weighted lerp weights of each overlapping subsample
+                const double cw = wgt * (wprof ? wprof[ipv] : 1.0);
                 for (int s = 0; s < nss; ++s) {
                     const double x = (t + ex * ((s + 0.5) * inv_nss - 0.5)) - p.t0;
                     const double u = x * p.invP;
@@ -317,27 +358,32 @@ __global__ __launch_bounds__(kAdjBlock) void k_adjoint(
                     m = m > ng - 2 ? ng - 2 : m;
                     const double al = double(v - R(m));
                     const double A = double(lens_area<R>(R(1), k, z)) * double(istar_inv);
-                    const double c = cw * A;
-                    atomicAdd(&gw[pb * ng + m], (1.0 - al) * c);
-                    atomicAdd(&gw[pb * ng + m + 1], al * c);
+                    const double cc = cw * A;
+                    atomicAdd(&gw[pb * ng + m], (1.0 - al) * cc);
+                    atomicAdd(&gw[pb * ng + m + 1], al * cc);
                     const double ip = (1.0 - al) * double(lw[m]) + al * double(lw[m + 1]);
                     atomicAdd(&gi[pb], -cw * ip * A * double(istar_inv));
                 }
             }
         }
-        if (want_prof) {
-            __syncthreads();
-            for (int idx = tid; idx < npb * ng; idx += kAdjBlock) {
-                const double v = gw[idx];
-                if (v != 0.0) atomicAdd(&gldw_pv[int64_t(ipv) * npb * ng + idx], v);
+    }
+
+    if (kProf) {
+        __syncthreads();                 // every wave's LDS additions done
+        double* out = seg_gw + slot * npb * ng;
+        if (seg_flag) {
+            if (tid == 0) seg_flag[slot] = ready ? 1 : 0;
+            if (ready) {
+                for (int idx = tid; idx < npb * ng; idx += kAdjBlock) out[idx] = gw[idx];
+                if (tid < npb) seg_gi[slot * npb + tid] = gi[tid];
             }
-            if (tid < npb && gi[tid] != 0.0)
-                atomicAdd(&gist_pv[int64_t(ipv) * npb + tid], gi[tid]);
+        } else {
+            for (int idx = tid; idx < npb * ng; idx += kAdjBlock) out[idx] = ready ? gw[idx] : 0.0;
+            if (tid < npb) seg_gi[slot * npb + tid] = ready ? gi[tid] : 0.0;
         }
     }
 
     // fixed-order reduction of the per-lane sums
-    const int wave = tid >> 6, lane = tid & 63;
     double vals[kNq + NPBT];
     vals[0] = ll;
 #pragma unroll
@@ -351,9 +397,34 @@ __global__ __launch_bounds__(kAdjBlock) void k_adjoint(
     }
     __syncthreads();
     if (tid < nq) {
+        double sum = 0.0;
+        for (int w = 0; w < kAdjBlock / 64; ++w) sum += red[w][tid];
+        part[tid] = sum;
+    }
+}
+
+// d logL / d ldw_row and d logL / d I_star per vector: the flagged parts of
+// k_adjoint added in part order.  Thread idx < npv npb ng sums
+// one ldw entry, the next npv npb threads one I_star entry each.
+__global__ void k_prof_seg_sum(const double* __restrict__ seg_gw,
+                               const double* __restrict__ seg_gi,
+                               const int32_t* __restrict__ seg_flag, int32_t npv, int32_t nseg,
+                               int32_t nw, int32_t npb, double* __restrict__ gldw_pv,
+                               double* __restrict__ gist_pv) {
+    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t n1 = int64_t(npv) * nw;
+    if (idx < n1) {
+        const int64_t ipv = idx / nw, e = idx - ipv * nw;
         double s = 0.0;
-        for (int w = 0; w < kAdjBlock / 64; ++w) s += red[w][tid];
-        part[tid] = s;
+        for (int sg = 0; sg < nseg; ++sg)
+            if (seg_flag[ipv * nseg + sg]) s += seg_gw[(ipv * nseg + sg) * nw + e];
+        gldw_pv[idx] = s;
+    } else if (idx < n1 + int64_t(npv) * npb) {
+        const int64_t j = idx - n1, ipv = j / npb, pb = j - ipv * npb;
+        double s = 0.0;
+        for (int sg = 0; sg < nseg; ++sg)
+            if (seg_flag[ipv * nseg + sg]) s += seg_gi[(ipv * nseg + sg) * npb + pb];
+        gist_pv[j] = s;
     }
 }
 
@@ -362,15 +433,20 @@ __global__ void k_fill(double* __restrict__ p, int64_t n) {
     if (i < n) p[i] = 0.0;
 }
 
+// One wave per (row, quantity): lane l sums the partials of tiles l, l + 64,
+// ... in order, then a fixed butterfly across the lanes.
 __global__ void k_adjoint_reduce(const double* __restrict__ partials, int32_t npv,
                                  int32_t ntiles, int32_t npb, double* __restrict__ logl,
                                  double* __restrict__ grad) {
     const int nq = kNq + npb;
-    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (idx >= int64_t(npv) * nq) return;
-    const int ipv = int(idx / nq), q = int(idx - int64_t(ipv) * nq);
+    const int64_t wv = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (wv >= int64_t(npv) * nq) return;                 // whole waves leave together
+    const int ipv = int(wv / nq), q = int(wv - int64_t(ipv) * nq);
     double s = 0.0;
-    for (int tl = 0; tl < ntiles; ++tl) s += partials[(int64_t(ipv) * ntiles + tl) * nq + q];
+    for (int tl = lane; tl < ntiles; tl += 64) s += partials[(int64_t(ipv) * ntiles + tl) * nq + q];
+    s = wave_sum(s);
+    if (lane != 0) return;
     if (q == 0) {
         if (logl) logl[ipv] = s;
     } else if (grad) {
@@ -400,23 +476,29 @@ __global__ void k_row_kidx(const double* __restrict__ pv, int32_t npv, int32_t n
     kfrac[idx] = u - ik;
 }
 
-// dlogL/dT[pb][i][m] = sum over rows, in row order, of
-// [(ik == i)(1 - ak) + (ik + 1 == i) ak] dlogL/dldw_row[pb][m].  Workgroup
-// (x, i, pb), x = a block of m.  Each wave reads the k-rows of 64
-// rows at a time and visits only those that touch k-row i (a ballot), so
-// the loop over rows costs ~npv/64 loads.  Grid (m blocks, nk, npb).
+// dlogL/dT[pb][i][m] = sum over rows of [(ik == i)(1 - ak) + (ik + 1 == i) ak]
+// dlogL/dldw_row[pb][m], in two fixed-order stages.  Workgroup (x, i, c npb +
+// pb), x a block of m, sums the rows of chunk c in row order; each wave reads
+// the k-rows of 64 rows at a time and visits only those touching k-row i (a
+// ballot), with eight loads in flight.  A chunk with no such row writes only
+// its flag.  k_table_grad_sum then adds the flagged chunks in order.
 __global__ void k_table_grad(const double* __restrict__ gldw_pv,
                              const int32_t* __restrict__ kidx, const double* __restrict__ kfrac,
-                             int32_t npv, GridDev g, double* __restrict__ GT) {
-    const int pb = int(blockIdx.z), i = int(blockIdx.y);
+                             int32_t npv, int32_t rows_per_chunk, GridDev g,
+                             double* __restrict__ part, int32_t* __restrict__ flags) {
+    const int c = int(blockIdx.z) / g.npb, pb = int(blockIdx.z) - c * g.npb, i = int(blockIdx.y);
     const int m = int(blockIdx.x) * kBlock + int(threadIdx.x);
     const int lane = threadIdx.x & 63;
+    const int r0 = c * rows_per_chunk;
+    const int r1 = min(npv, r0 + rows_per_chunk);
     double s = 0.0;
-    for (int base = 0; base < npv; base += 64) {
+    bool touched = false;
+    for (int base = r0; base < r1; base += 64) {
         const int r = base + lane;
-        const int ik = r < npv ? kidx[int64_t(r) * g.npb + pb] : kNoRow;
-        const double ak = r < npv ? kfrac[int64_t(r) * g.npb + pb] : 0.0;
+        const int ik = r < r1 ? kidx[int64_t(r) * g.npb + pb] : kNoRow;
+        const double ak = r < r1 ? kfrac[int64_t(r) * g.npb + pb] : 0.0;
         uint64_t hit = __ballot(ik == i || ik + 1 == i);
+        touched = touched || hit != 0;
         while (hit) {
             // up to 8 hits at a time: their loads are issued together, the
             // sum still runs in row order
@@ -443,7 +525,22 @@ __global__ void k_table_grad(const double* __restrict__ gldw_pv,
                 if (b < n) s += wv[b] * gv[b];
         }
     }
-    if (m < g.ng) GT[(int64_t(pb) * g.nk + i) * g.ng + m] = s;
+    const int64_t slot = (int64_t(c) * g.npb + pb) * g.nk + i;
+    if (blockIdx.x == 0 && threadIdx.x == 0) flags[slot] = touched ? 1 : 0;
+    if (touched && m < g.ng) part[slot * g.ng + m] = s;
+}
+
+__global__ void k_table_grad_sum(const double* __restrict__ part,
+                                 const int32_t* __restrict__ flags, int32_t nchunks, GridDev g,
+                                 double* __restrict__ GT) {
+    const int64_t per = int64_t(g.npb) * g.nk * g.ng;
+    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= per) return;
+    const int64_t row = idx / g.ng;                       // pb nk + i
+    double s = 0.0;
+    for (int c = 0; c < nchunks; ++c)
+        if (flags[int64_t(c) * g.npb * g.nk + row]) s += part[int64_t(c) * per + idx];
+    GT[idx] = s;
 }
 
 // dlogL/dldp[pb][j] = sum_{i,m} W[i][j][m] dlogL/dT[pb][i][m], in two fixed-
@@ -565,20 +662,29 @@ __global__ void k_prof_grad(const double* __restrict__ gldp, const double* __res
 
 inline unsigned nblocks(int64_t n) { return unsigned((n + kBlock - 1) / kBlock); }
 
-template <typename R, int NPBT>
+template <typename R, int NPBT, bool kProf>
 void launch_adjoint_t(const AdjointArgs& A, size_t lds, hipStream_t s, const KernelEvents& ev) {
-    launch_timed(k_adjoint<R, NPBT>, dim3(unsigned(int64_t(A.ntiles) * A.npv)), dim3(kAdjBlock),
-                 lds, s, ev.before, ev.after, A.times, A.lcids, A.npt, *A.lc, A.pv, A.npar,
-                 A.pvc, A.g, static_cast<const R*>(A.T), A.inv_istar,
-                 static_cast<const R*>(A.obs), A.inv_sig2, A.ntiles, A.want_grad,
-                 A.want_prof, A.wprof, A.partials, A.gldw_pv, A.gist_pv);
+    // one part per vector: the profile sums are final and go to gldw_pv
+    const bool one = A.nparts == 1;
+    launch_timed(k_adjoint<R, NPBT, kProf>, dim3(unsigned(int64_t(A.nparts) * A.npv)),
+                 dim3(kAdjBlock), lds, s, ev.before, ev.after, A.times, A.lcids, A.npt, *A.lc,
+                 A.pv, A.npar, A.pvc, A.g, static_cast<const R*>(A.T), A.inv_istar,
+                 static_cast<const R*>(A.obs), A.inv_sig2, A.ntiles, A.nparts, A.tpp,
+                 A.want_grad, A.wprof, A.partials, one ? A.gldw_pv : A.seg_gw,
+                 one ? A.gist_pv : A.seg_gi, one ? nullptr : A.seg_flag);
 }
 
 template <typename R>
 void launch_adjoint_r(const AdjointArgs& A, size_t lds, hipStream_t s, const KernelEvents& ev) {
-    if (A.g.npb <= 1) launch_adjoint_t<R, 1>(A, lds, s, ev);
-    else if (A.g.npb <= 4) launch_adjoint_t<R, 4>(A, lds, s, ev);
-    else launch_adjoint_t<R, 16>(A, lds, s, ev);
+    if (A.want_prof) {
+        if (A.g.npb <= 1) launch_adjoint_t<R, 1, true>(A, lds, s, ev);
+        else if (A.g.npb <= 4) launch_adjoint_t<R, 4, true>(A, lds, s, ev);
+        else launch_adjoint_t<R, 16, true>(A, lds, s, ev);
+    } else {
+        if (A.g.npb <= 1) launch_adjoint_t<R, 1, false>(A, lds, s, ev);
+        else if (A.g.npb <= 4) launch_adjoint_t<R, 4, false>(A, lds, s, ev);
+        else launch_adjoint_t<R, 16, false>(A, lds, s, ev);
+    }
 }
 
 }  // namespace
@@ -595,21 +701,22 @@ size_t adjoint_lds_bytes(int32_t precision, int32_t npb, int32_t ng) {
 }
 
 hipError_t launch_adjoint(const AdjointArgs& A, int32_t precision, hipStream_t s) {
-    const size_t lds = adjoint_lds_bytes(precision, A.g.npb, A.g.ng);
-    if (A.want_prof) {
-        const int64_t n1 = int64_t(A.npv) * A.g.npb * A.g.ng, n2 = int64_t(A.npv) * A.g.npb;
-        hipLaunchKernelGGL(k_fill, dim3(nblocks(n1)), dim3(kBlock), 0, s, A.gldw_pv, n1);
-        hipLaunchKernelGGL(k_fill, dim3(nblocks(n2)), dim3(kBlock), 0, s, A.gist_pv, n2);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
+    const size_t lds = A.want_prof ? adjoint_lds_bytes(precision, A.g.npb, A.g.ng)
+                                   : 2 * (precision == RR_FP64 ? sizeof(double) : sizeof(float)) *
+                                         size_t(A.g.npb) * A.g.ng;
     const KernelEvents ev = kernel_events();
     if (precision == RR_FP64) launch_adjoint_r<double>(A, lds, s, ev);
     else launch_adjoint_r<float>(A, lds, s, ev);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_adjoint_reduce, dim3(nblocks(int64_t(A.npv) * (kNq + A.g.npb))),
-                       dim3(kBlock), 0, s, A.partials, A.npv, A.ntiles, A.g.npb, A.logl,
+    if (A.want_prof && A.nparts > 1) {
+        const int32_t nw = A.g.npb * A.g.ng;
+        hipLaunchKernelGGL(k_prof_seg_sum, dim3(nblocks(int64_t(A.npv) * (nw + A.g.npb))),
+                           dim3(kBlock), 0, s, A.seg_gw, A.seg_gi, A.seg_flag, A.npv, A.nparts,
+                           nw, A.g.npb, A.gldw_pv, A.gist_pv);
+    }
+    hipLaunchKernelGGL(k_adjoint_reduce, dim3(nblocks(int64_t(A.npv) * (kNq + A.g.npb) * 64)),
+                       dim3(kBlock), 0, s, A.partials, A.npv, A.nparts, A.g.npb, A.logl,
                        A.grad);
     return hipGetLastError();
 }
@@ -620,9 +727,14 @@ hipError_t launch_profile_grad(const rr_tables* t, const AdjointArgs& A,
     const int64_t nrk = int64_t(A.npv) * g.npb;
     hipLaunchKernelGGL(k_row_kidx, dim3(nblocks(nrk)), dim3(kBlock), 0, s, A.pv, A.npv, A.npar,
                        A.pvc, g, w.kidx, w.kfrac);
+    const int32_t rpc = (A.npv + w.nchunks - 1) / w.nchunks;
     hipLaunchKernelGGL(k_table_grad,
-                       dim3(unsigned((g.ng + kBlock - 1) / kBlock), unsigned(g.nk), unsigned(g.npb)),
-                       dim3(kBlock), 0, s, A.gldw_pv, w.kidx, w.kfrac, A.npv, g, w.GT);
+                       dim3(unsigned((g.ng + kBlock - 1) / kBlock), unsigned(g.nk),
+                            unsigned(w.nchunks * g.npb)),
+                       dim3(kBlock), 0, s, A.gldw_pv, w.kidx, w.kfrac, A.npv, rpc, g,
+                       w.gt_part, w.gt_flags);
+    hipLaunchKernelGGL(k_table_grad_sum, dim3(nblocks(int64_t(g.npb) * g.nk * g.ng)),
+                       dim3(kBlock), 0, s, w.gt_part, w.gt_flags, w.nchunks, g, w.GT);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_ldp_grad, dim3(unsigned(kLdpChunks), unsigned(g.nz), unsigned(g.npb)),

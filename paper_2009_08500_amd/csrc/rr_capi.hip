@@ -298,11 +298,24 @@ RR_API int rr_loglik_grad(const rr_tables* t, const double* times_d,
     const int32_t nq = 7 + t->npb;
     const bool prof = grad_prof_d != nullptr;
     const GridDev g = grid_dev(t);
+    // With the profile gradient each workgroup runs tpp consecutive tiles of
+    // one vector: enough workgroups to fill the chip (~16384), at most 256
+    // MiB of per-workgroup profile partials.  Without it, one tile each.
+    int64_t nseg = ntiles;
+    int32_t tpp = 1;
+    if (prof) {
+        const size_t row_bytes = sizeof(double) * size_t(t->npb) * (size_t(g.ng) + 1);
+        int64_t want = std::min<int64_t>(ntiles, (16384 + npv - 1) / npv);
+        want = std::min<int64_t>(want, std::max<int64_t>(
+                                           1, int64_t((size_t(256) << 20) / (row_bytes * npv))));
+        tpp = int32_t((ntiles + want - 1) / std::max<int64_t>(1, want));
+        nseg = (ntiles + tpp - 1) / tpp;
+    }
     // one stream-ordered allocation for every temporary
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off += (bytes + 255) / 256 * 256; return o; };
     const size_t o_pvc = take(sizeof(PvConst) * size_t(npv));
-    const size_t o_part = take(sizeof(double) * size_t(npv) * ntiles * nq);
+    const size_t o_part = take(sizeof(double) * size_t(npv) * nseg * nq);
     const size_t o_gldw = prof ? take(sizeof(double) * size_t(npv) * t->npb * g.ng) : 0;
     const size_t o_gist = prof ? take(sizeof(double) * size_t(npv) * t->npb) : 0;
     const size_t o_gt = prof ? take(sizeof(double) * size_t(t->npb) * g.nk * g.ng) : 0;
@@ -311,6 +324,18 @@ RR_API int rr_loglik_grad(const rr_tables* t, const double* times_d,
     const size_t o_kidx = prof ? take(sizeof(int32_t) * size_t(npv) * t->npb) : 0;
     const size_t o_kfrac = prof ? take(sizeof(double) * size_t(npv) * t->npb) : 0;
     const size_t o_gist_sum = prof ? take(sizeof(double) * size_t(t->npb)) : 0;
+    // table-gradient row chunks: up to 32 rows each, at most 64 chunks and
+    // 256 MiB of partial tables
+    const size_t table_bytes = sizeof(double) * size_t(t->npb) * g.nk * g.ng;
+    int32_t nchunks = std::max<int32_t>(1, std::min<int32_t>(64, (npv + 31) / 32));
+    nchunks = int32_t(std::max<size_t>(1, std::min<size_t>(size_t(nchunks),
+                                                           (size_t(256) << 20) / table_bytes)));
+    const size_t o_gtp = prof ? take(table_bytes * nchunks) : 0;
+    const size_t o_gtf = prof ? take(sizeof(int32_t) * size_t(nchunks) * t->npb * g.nk) : 0;
+    const bool segs = prof && nseg > 1;
+    const size_t o_sgw = segs ? take(sizeof(double) * size_t(npv) * nseg * t->npb * g.ng) : 0;
+    const size_t o_sgi = segs ? take(sizeof(double) * size_t(npv) * nseg * t->npb) : 0;
+    const size_t o_sfl = segs ? take(sizeof(int32_t) * size_t(npv) * nseg) : 0;
     char* base = nullptr;
     e = hipMallocAsync((void**)&base, off, stream);
     if (e != hipSuccess) return e == hipErrorOutOfMemory ? RR_ENOMEM : hip_fail(e, "hipMallocAsync");
@@ -323,6 +348,11 @@ RR_API int rr_loglik_grad(const rr_tables* t, const double* times_d,
     A.partials = reinterpret_cast<double*>(base + o_part);
     A.gldw_pv = prof ? reinterpret_cast<double*>(base + o_gldw) : nullptr;
     A.gist_pv = prof ? reinterpret_cast<double*>(base + o_gist) : nullptr;
+    A.nparts = int32_t(nseg);
+    A.tpp = tpp;
+    A.seg_gw = segs ? reinterpret_cast<double*>(base + o_sgw) : nullptr;
+    A.seg_gi = segs ? reinterpret_cast<double*>(base + o_sgi) : nullptr;
+    A.seg_flag = segs ? reinterpret_cast<int32_t*>(base + o_sfl) : nullptr;
     A.logl = logl_d; A.grad = grad_d;
     e = launch_pv_setup(t, pv_d, npv, npar, const_cast<PvConst*>(A.pvc), stream);
     if (e == hipSuccess) e = launch_adjoint(A, precision, stream);
@@ -330,6 +360,9 @@ RR_API int rr_loglik_grad(const rr_tables* t, const double* times_d,
         ProfGradScratch w;
         w.kidx = reinterpret_cast<int32_t*>(base + o_kidx);
         w.kfrac = reinterpret_cast<double*>(base + o_kfrac);
+        w.nchunks = nchunks;
+        w.gt_part = reinterpret_cast<double*>(base + o_gtp);
+        w.gt_flags = reinterpret_cast<int32_t*>(base + o_gtf);
         w.GT = reinterpret_cast<double*>(base + o_gt);
         w.ldp_part = reinterpret_cast<double*>(base + o_ldpp);
         w.gldp = reinterpret_cast<double*>(base + o_gldp);

@@ -106,9 +106,14 @@ struct AdjointArgs {
     double inv_sig2;
     int32_t ntiles, want_grad, want_prof;
     const double* wprof;      // per-vector weights of the profile gradient
-    double* partials;         // [npv * ntiles][7 + npb]
+    double* partials;         // [npv * nparts][7 + npb]
     double* gldw_pv;          // [npv][npb][ng]
     double* gist_pv;          // [npv][npb]
+    int32_t nparts;           // workgroups per vector (ntiles without the profile gradient)
+    int32_t tpp;              // tiles per workgroup
+    double* seg_gw;           // [npv][nparts][npb][ng] (nparts > 1)
+    double* seg_gi;           // [npv][nparts][npb]
+    int32_t* seg_flag;        // [npv][nparts]
     double* logl;             // [npv] or null
     double* grad;             // [npv][npar] or null
 };
@@ -172,6 +177,9 @@ hipError_t launch_adjoint(const AdjointArgs& a, int32_t precision, hipStream_t s
 struct ProfGradScratch {
     int32_t* kidx;        // [npv][npb]
     double* kfrac;        // [npv][npb]
+    int32_t nchunks;      // row chunks of the table gradient
+    double* gt_part;      // [nchunks][npb][nk][ng]
+    int32_t* gt_flags;    // [nchunks][npb][nk]
     double* GT;           // [npb][nk][ng]
     double* ldp_part;     // [npb][nz][16]
     double* gldp;         // [npb][nz]

@@ -107,6 +107,35 @@ def test_full_size_sampled_rows(rr):
     assert np.isfinite(ll).all() and np.isfinite(g).all()
 
 
+@pytest.mark.parametrize("npv,npt,span", [(5, 900, 4.0), (4000, 21000, 60.0)])
+def test_profile_gradient_work_partition(rr, npv, npt, span):
+    """The profile gradient when each vector is one workgroup (all times in
+    one tile: the sums are stored directly) and when workgroups run several
+    tiles over a ragged tile count (21 tiles, 5 per workgroup) and their
+    partial sums are added per vector afterwards.  An invalid row with a
+    nonzero profile weight must not contribute.  Sampled rows against the
+    oracle."""
+    import torch
+    w, grid, otab, obs = make(npv=npv, npt=npt, nss=2, span=span)
+    pv = w["pv"].copy()
+    pv[1, 4] = 1.5                                   # e >= 1: invalid row
+    rows = [0, 2, npv - 1]
+    wprof = np.zeros(npv)
+    wprof[rows] = 1.0
+    wprof[1] = 1.0
+    tab = rr.Tables(w["mu_s"], w["I_s"], grid)
+    ser = rr.TimeSeries(w["times"], nss=w["nss"], exptimes=w["exptimes"])
+    ll, g, gp = rr.loglik_grad(tab, ser, pv, obs, w["sigma"], "fp64", grad=True, profile=True,
+                               wprof=torch.tensor(wprof, device="cuda"))
+    ll, g, gp = ll.cpu().numpy(), g.cpu().numpy(), gp.cpu().numpy()
+    oll, og, ogp = ogr.loglik_grad(otab, w["times"], pv[rows], obs, w["sigma"], nss=w["nss"],
+                                   exptimes=w["exptimes"])
+    assert np.isnan(ll[1])
+    np.testing.assert_allclose(ll[rows], oll, rtol=1e-11)
+    rowwise_close(g[rows], og, 1e-7)
+    rowwise_close(gp, ogp, 1e-7)
+
+
 def test_loglik_only_and_invalid_rows(rr):
     w, grid, otab, obs = make(npv=6, npt=3000, nss=1, span=10.0)
     pv = w["pv"].copy()
