@@ -160,6 +160,27 @@ __device__ inline T wave_sum(T v) {
 // seg_gw / seg_gi with flag 1 (flag 0 and nothing else if no exposure was in
 // the window), or, with seg_flag NULL (one part per vector), as the final
 // per-vector sums.
+// sum over c = 0 .. n-1, in order, of (flag(c) ? val(c) : 0), with eight
+// flags and then eight values loaded at a time (their loads are independent,
+// so a flagged sum over many parts costs n/8 memory round trips, not n)
+template <typename F, typename V>
+__device__ inline double flagged_sum(int n, F flag, V val, bool* any = nullptr) {
+    double s = 0.0;
+    bool a = false;
+    for (int c0 = 0; c0 < n; c0 += 8) {
+        bool f[8];
+        double v[8];
+#pragma unroll
+        for (int b = 0; b < 8; ++b) f[b] = c0 + b < n && flag(c0 + b);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) v[b] = f[b] ? val(c0 + b) : 0.0;
+#pragma unroll
+        for (int b = 0; b < 8; ++b) { s += v[b]; a = a || f[b]; }
+    }
+    if (any) *any = a;
+    return s;
+}
+
 template <typename R, int NPBT, bool kProf>
 __global__ __launch_bounds__(kAdjBlock) void k_adjoint(
     const double* __restrict__ times, const int32_t* __restrict__ lcids,
@@ -415,16 +436,14 @@ __global__ void k_prof_seg_sum(const double* __restrict__ seg_gw,
     const int64_t n1 = int64_t(npv) * nw;
     if (idx < n1) {
         const int64_t ipv = idx / nw, e = idx - ipv * nw;
-        double s = 0.0;
-        for (int sg = 0; sg < nseg; ++sg)
-            if (seg_flag[ipv * nseg + sg]) s += seg_gw[(ipv * nseg + sg) * nw + e];
-        gldw_pv[idx] = s;
+        gldw_pv[idx] = flagged_sum(
+            nseg, [&](int sg) { return seg_flag[ipv * nseg + sg] != 0; },
+            [&](int sg) { return seg_gw[(ipv * nseg + sg) * nw + e]; });
     } else if (idx < n1 + int64_t(npv) * npb) {
         const int64_t j = idx - n1, ipv = j / npb, pb = j - ipv * npb;
-        double s = 0.0;
-        for (int sg = 0; sg < nseg; ++sg)
-            if (seg_flag[ipv * nseg + sg]) s += seg_gi[(ipv * nseg + sg) * npb + pb];
-        gist_pv[j] = s;
+        gist_pv[j] = flagged_sum(
+            nseg, [&](int sg) { return seg_flag[ipv * nseg + sg] != 0; },
+            [&](int sg) { return seg_gi[(ipv * nseg + sg) * npb + pb]; });
     }
 }
 
@@ -530,17 +549,20 @@ __global__ void k_table_grad(const double* __restrict__ gldw_pv,
     if (touched && m < g.ng) part[slot * g.ng + m] = s;
 }
 
+// GT = the flagged chunk partials in chunk order; rowflag[pb nk + i] = 1 if
+// any chunk touched k-row i (k_ldp_grad skips the other rows).
 __global__ void k_table_grad_sum(const double* __restrict__ part,
                                  const int32_t* __restrict__ flags, int32_t nchunks, GridDev g,
-                                 double* __restrict__ GT) {
+                                 double* __restrict__ GT, int32_t* __restrict__ rowflag) {
     const int64_t per = int64_t(g.npb) * g.nk * g.ng;
     const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (idx >= per) return;
     const int64_t row = idx / g.ng;                       // pb nk + i
-    double s = 0.0;
-    for (int c = 0; c < nchunks; ++c)
-        if (flags[int64_t(c) * g.npb * g.nk + row]) s += part[int64_t(c) * per + idx];
-    GT[idx] = s;
+    bool any;
+    GT[idx] = flagged_sum(
+        nchunks, [&](int c) { return flags[int64_t(c) * g.npb * g.nk + row] != 0; },
+        [&](int c) { return part[int64_t(c) * per + idx]; }, &any);
+    if (idx - row * g.ng == 0) rowflag[row] = any ? 1 : 0;
 }
 
 // dlogL/dldp[pb][j] = sum_{i,m} W[i][j][m] dlogL/dT[pb][i][m], in two fixed-
@@ -548,7 +570,8 @@ __global__ void k_table_grad_sum(const double* __restrict__ part,
 // fixed-shape tree, then k_ldp_sum adds the chunks in order.
 constexpr int kLdpChunks = 16;
 __global__ void k_ldp_grad(const double* __restrict__ W, const double* __restrict__ GT,
-                           GridDev g, double* __restrict__ part_out) {
+                           const int32_t* __restrict__ rowflag, GridDev g,
+                           double* __restrict__ part_out) {
     __shared__ double part[kBlock];
     const int c = blockIdx.x;
     const int j = int(blockIdx.y), pb = int(blockIdx.z);
@@ -556,9 +579,11 @@ __global__ void k_ldp_grad(const double* __restrict__ W, const double* __restric
     const int i0 = c * per_chunk, i1 = min(g.nk, i0 + per_chunk);
     const int64_t per = int64_t(g.nk) * g.ng;
     double s = 0.0;
-    for (int i = i0; i < i1; ++i)
+    for (int i = i0; i < i1; ++i) {
+        if (!rowflag[pb * g.nk + i]) continue;          // GT row i is zero
         for (int m = threadIdx.x; m < g.ng; m += kBlock)
             s += W[(int64_t(i) * g.nz + j) * g.ng + m] * GT[pb * per + int64_t(i) * g.ng + m];
+    }
     part[threadIdx.x] = s;
     __syncthreads();
     for (int w = kBlock / 2; w > 0; w >>= 1) {
@@ -598,66 +623,98 @@ __global__ void k_gist_sum(const double* __restrict__ gist_pv, int32_t npv,
 // Profile gradient: chain dlogL/dldp (profile at the bin means, linear in
 // the samples with the weights of the piecewise-linear interpolant) and
 // dlogL/dI_star (I_star linear in the samples, Eq. 2 / Eq. 4) back to the
-// samples prof[pb][s].  Each workgroup first tabulates, for every bin j, the
-// interpolation segment of mu_j in LDS; then one thread per sample gathers
-// over j in order.
-constexpr int kMaxNzLds = 4096;
+// samples prof[pb][s].  Workgroup (x, pb) handles samples x 256 .. + 255 of
+// passband pb.  It walks the bins in chunks of kJChunk: for every bin j of
+// the chunk it tabulates in LDS the interpolation segment of mu_j (a binary
+// search over the samples, staged in LDS when there are at most kMuLds of
+// them) and dlogL/dldp[pb][j]; then each thread adds its sample's weights
+// times dlogL/dldp over the chunk's bins in order (only the run of bins that
+// interpolate from its sample).
+constexpr int kJChunk = 1024;
+constexpr int kMuLds = 1024;
 __global__ void k_prof_grad(const double* __restrict__ gldp, const double* __restrict__ gist,
                             const double* __restrict__ mu_s, int32_t nmu,
                             const double* __restrict__ zm, int32_t nz, int32_t npb,
                             double* __restrict__ out) {
-    __shared__ int seg_lo[kMaxNzLds];
-    __shared__ double seg_tau[kMaxNzLds];
-    for (int j = threadIdx.x; j < nz; j += kBlock) {
-        const double z = zm[j];
-        const double mu = sqrt(1.0 - z * z);
-        int lo;
-        double tau;
-        if (mu <= mu_s[0]) {
-            lo = -1; tau = 0.0;                     // weight 1 on sample 0
-        } else if (mu >= mu_s[nmu - 1]) {
-            lo = nmu - 1; tau = 1.0;                // weight 1 on sample nmu - 1
-        } else {
-            int a = 0, b = nmu - 1;
-            while (b - a > 1) {
-                const int mid = (a + b) >> 1;
-                if (mu_s[mid] <= mu) a = mid; else b = mid;
-            }
-            lo = a;
-            tau = (mu - mu_s[a]) / (mu_s[a + 1] - mu_s[a]);
-        }
-        seg_lo[j] = lo;
-        seg_tau[j] = tau;
-    }
+    __shared__ int seg_lo[kJChunk];
+    __shared__ double seg_tau[kJChunk];
+    __shared__ double gl[kJChunk];
+    __shared__ double mu_l[kMuLds];
+    const int pb = blockIdx.y;
+    const int s = int(blockIdx.x) * kBlock + int(threadIdx.x);
+    const bool staged = nmu <= kMuLds;
+    if (staged)
+        for (int i = threadIdx.x; i < nmu; i += kBlock) mu_l[i] = mu_s[i];
     __syncthreads();
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= npb * nmu) return;
-    const int pb = idx / nmu, s = idx - pb * nmu;
+    const double* ms = staged ? mu_l : mu_s;
     double acc = 0.0;
-    for (int j = 0; j < nz; ++j) {
-        const int lo = seg_lo[j];
-        const double tau = seg_tau[j];
-        double w = 0.0;
-        if (lo < 0) w = (s == 0) ? 1.0 : 0.0;
-        else if (lo == nmu - 1) w = (s == nmu - 1) ? 1.0 : 0.0;
-        else if (s == lo) w = 1.0 - tau;
-        else if (s == lo + 1) w = tau;
-        if (w != 0.0) acc += w * gldp[pb * nz + j];
+    for (int j0 = 0; j0 < nz; j0 += kJChunk) {
+        const int jn = min(kJChunk, nz - j0);
+        for (int jj = threadIdx.x; jj < jn; jj += kBlock) {
+            const double z = zm[j0 + jj];
+            const double mu = sqrt(1.0 - z * z);
+            int lo;
+            double tau;
+            if (mu <= ms[0]) {
+                lo = -1; tau = 0.0;                     // weight 1 on sample 0
+            } else if (mu >= ms[nmu - 1]) {
+                lo = nmu - 1; tau = 1.0;                // weight 1 on sample nmu - 1
+            } else {
+                int a = 0, b = nmu - 1;
+                while (b - a > 1) {
+                    const int mid = (a + b) >> 1;
+                    if (ms[mid] <= mu) a = mid; else b = mid;
+                }
+                lo = a;
+                tau = (mu - ms[a]) / (ms[a + 1] - ms[a]);
+            }
+            seg_lo[jj] = lo;
+            seg_tau[jj] = tau;
+            gl[jj] = gldp[int64_t(pb) * nz + j0 + jj];
+        }
+        __syncthreads();
+        if (s < nmu) {
+            // mu_j decreases with j, so seg_lo is non-increasing in j and
+            // the bins with a nonzero weight for sample s (seg_lo in
+            // {s - 1, s}) are one contiguous run: two binary searches find
+            // it, and the run is added in bin order
+            int lo_i = 0, hi_i = jn;
+            while (lo_i < hi_i) {                       // first bin with seg_lo <= s
+                const int mid = (lo_i + hi_i) >> 1;
+                if (seg_lo[mid] <= s) hi_i = mid; else lo_i = mid + 1;
+            }
+            const int ja = lo_i;
+            hi_i = jn;
+            while (lo_i < hi_i) {                       // first bin with seg_lo < s - 1
+                const int mid = (lo_i + hi_i) >> 1;
+                if (seg_lo[mid] < s - 1) hi_i = mid; else lo_i = mid + 1;
+            }
+            for (int jj = ja; jj < lo_i; ++jj) {
+                const int lo = seg_lo[jj];
+                // lo == s: 1 - tau (1 for the last sample); lo == s - 1: tau
+                // (1 for sample 0, whose run holds the bins below mu_s[0])
+                const double w = lo == s ? (s == nmu - 1 ? 1.0 : 1.0 - seg_tau[jj])
+                                         : (s == 0 ? 1.0 : seg_tau[jj]);
+                if (w != 0.0) acc += w * gl[jj];
+            }
+        }
+        __syncthreads();
     }
+    if (s >= nmu) return;
     // I_star weight of sample s
     double qs = 0.0;
     if (s < nmu - 1) {
-        const double ma = mu_s[s], mb = mu_s[s + 1];
+        const double ma = ms[s], mb = ms[s + 1];
         qs += (mb - ma) / 6.0 * (2.0 * ma + mb);
     }
     if (s > 0) {
-        const double ma = mu_s[s - 1], mb = mu_s[s];
+        const double ma = ms[s - 1], mb = ms[s];
         qs += (mb - ma) / 6.0 * (ma + 2.0 * mb);
     }
-    if (s == 0) qs += 0.5 * mu_s[0] * mu_s[0];
-    if (s == nmu - 1) qs += 0.5 * (1.0 - mu_s[nmu - 1] * mu_s[nmu - 1]);
+    if (s == 0) qs += 0.5 * ms[0] * ms[0];
+    if (s == nmu - 1) qs += 0.5 * (1.0 - ms[nmu - 1] * ms[nmu - 1]);
     qs *= 2.0 * Num<double>::pi;
-    out[idx] = acc + qs * gist[pb];
+    out[int64_t(pb) * nmu + s] = acc + qs * gist[pb];
 }
 
 inline unsigned nblocks(int64_t n) { return unsigned((n + kBlock - 1) / kBlock); }
@@ -734,18 +791,19 @@ hipError_t launch_profile_grad(const rr_tables* t, const AdjointArgs& A,
                        dim3(kBlock), 0, s, A.gldw_pv, w.kidx, w.kfrac, A.npv, rpc, g,
                        w.gt_part, w.gt_flags);
     hipLaunchKernelGGL(k_table_grad_sum, dim3(nblocks(int64_t(g.npb) * g.nk * g.ng)),
-                       dim3(kBlock), 0, s, w.gt_part, w.gt_flags, w.nchunks, g, w.GT);
+                       dim3(kBlock), 0, s, w.gt_part, w.gt_flags, w.nchunks, g, w.GT,
+                       w.gt_rowflag);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_ldp_grad, dim3(unsigned(kLdpChunks), unsigned(g.nz), unsigned(g.npb)),
-                       dim3(kBlock), 0, s, t->W, w.GT, g, w.ldp_part);
+                       dim3(kBlock), 0, s, t->W, w.GT, w.gt_rowflag, g, w.ldp_part);
     hipLaunchKernelGGL(k_ldp_sum, dim3(nblocks(int64_t(g.npb) * g.nz)), dim3(kBlock), 0, s,
                        w.ldp_part, g.npb * g.nz, w.gldp);
     hipLaunchKernelGGL(k_gist_sum, dim3(unsigned(g.npb)), dim3(kBlock), 0, s, A.gist_pv, A.npv,
                        A.pvc, g.npb, w.gist);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_prof_grad, dim3(nblocks(int64_t(g.npb) * t->nmu)), dim3(kBlock), 0, s,
+    hipLaunchKernelGGL(k_prof_grad, dim3(nblocks(t->nmu), unsigned(g.npb)), dim3(kBlock), 0, s,
                        w.gldp, w.gist, t->mu_s, t->nmu, t->zm, t->nz, g.npb, out);
     return hipGetLastError();
 }

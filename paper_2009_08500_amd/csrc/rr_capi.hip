@@ -332,6 +332,7 @@ RR_API int rr_loglik_grad(const rr_tables* t, const double* times_d,
                                                            (size_t(256) << 20) / table_bytes)));
     const size_t o_gtp = prof ? take(table_bytes * nchunks) : 0;
     const size_t o_gtf = prof ? take(sizeof(int32_t) * size_t(nchunks) * t->npb * g.nk) : 0;
+    const size_t o_gtr = prof ? take(sizeof(int32_t) * size_t(t->npb) * g.nk) : 0;
     const bool segs = prof && nseg > 1;
     const size_t o_sgw = segs ? take(sizeof(double) * size_t(npv) * nseg * t->npb * g.ng) : 0;
     const size_t o_sgi = segs ? take(sizeof(double) * size_t(npv) * nseg * t->npb) : 0;
@@ -363,6 +364,7 @@ RR_API int rr_loglik_grad(const rr_tables* t, const double* times_d,
         w.nchunks = nchunks;
         w.gt_part = reinterpret_cast<double*>(base + o_gtp);
         w.gt_flags = reinterpret_cast<int32_t*>(base + o_gtf);
+        w.gt_rowflag = reinterpret_cast<int32_t*>(base + o_gtr);
         w.GT = reinterpret_cast<double*>(base + o_gt);
         w.ldp_part = reinterpret_cast<double*>(base + o_ldpp);
         w.gldp = reinterpret_cast<double*>(base + o_gldp);

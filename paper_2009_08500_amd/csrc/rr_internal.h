@@ -180,6 +180,7 @@ struct ProfGradScratch {
     int32_t nchunks;      // row chunks of the table gradient
     double* gt_part;      // [nchunks][npb][nk][ng]
     int32_t* gt_flags;    // [nchunks][npb][nk]
+    int32_t* gt_rowflag;  // [npb][nk]: k-row touched by any chunk
     double* GT;           // [npb][nk][ng]
     double* ldp_part;     // [npb][nz][16]
     double* gldp;         // [npb][nz]
