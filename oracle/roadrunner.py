@@ -247,3 +247,34 @@ def evaluate(tab, times, pv, lcids=None, pbids=None, nss=None, exptimes=None):
             z, front, _ = _orbit.projected_separation(dt, P, a, b, e, w)
             out[ipv, sel] = 1.0 - occulted(tab, pb, k, z, front).mean(axis=1)
     return out
+
+
+# ------------------------------------------------- per-vector limb darkening
+def with_profile(tab, I_s):
+    """The same grid and weight table for other profile samples I_s[npb][nmu]
+    on the same mu samples: only the LD-dependent steps 2, 3 and 5 are
+    redone (T = w . l is linear in the profile at the bin means, Sect. 3.1.2),
+    W is shared."""
+    t = object.__new__(Tables)
+    t.__dict__.update(tab.__dict__)
+    t.I_s = np.atleast_2d(np.asarray(I_s, float))
+    if t.I_s.shape != tab.I_s.shape:
+        raise ValueError("profile samples must have the tables' shape")
+    t.ldp = profile_on_grid(t.mu_s, t.I_s, t.mu)
+    t.istar = istar_of_profile(t.mu_s, t.I_s)
+    t.T = ld_tables(t.W, t.ldp)
+    return t
+
+
+def evaluate_ld(tab, times, pv, prof, lcids=None, pbids=None, nss=None, exptimes=None):
+    """Fluxes with a limb-darkening profile per parameter row (the model's LD
+    coefficients given per evaluation, Sect. 4.2): row i is evaluated as in
+    ``evaluate`` with the tables rebuilt for prof[i] ([npb][nmu] samples on
+    the tables' mu samples)."""
+    pv = np.atleast_2d(np.asarray(pv, float))
+    prof = np.asarray(prof, float).reshape(pv.shape[0], tab.npb, tab.mu_s.size)
+    out = np.empty((pv.shape[0], np.asarray(times).size))
+    for i in range(pv.shape[0]):
+        out[i] = evaluate(with_profile(tab, prof[i]), times, pv[i:i + 1], lcids=lcids,
+                          pbids=pbids, nss=nss, exptimes=exptimes)[0]
+    return out

@@ -67,6 +67,10 @@ def _declare(L):
     L.rr_evaluate.argtypes = [c_void_p, c_void_p, c_void_p, i32, c_void_p, c_void_p,
                               c_void_p, i32, c_void_p, i32, i32, i32, c_void_p, c_void_p]
     L.rr_evaluate.restype = ctypes.c_int
+    L.rr_evaluate_ld.argtypes = [c_void_p, c_void_p, c_void_p, i32, c_void_p, c_void_p,
+                                 c_void_p, i32, c_void_p, i32, i32, c_void_p, i32, c_void_p,
+                                 c_void_p]
+    L.rr_evaluate_ld.restype = ctypes.c_int
     L.rr_set_kernel_events.argtypes = [c_void_p, c_void_p]
     L.rr_set_kernel_events.restype = ctypes.c_int
     L.rr_free_tables.argtypes = [c_void_p]

@@ -176,6 +176,37 @@ def evaluate(tables, series, pv, precision="fp64", out=None, stream=None):
     return out
 
 
+def evaluate_ld(tables, series, pv, prof, precision="fp64", out=None, stream=None):
+    """Fluxes (npv, npt) with a limb-darkening profile per parameter row
+    (rr_evaluate_ld).  ``prof`` holds the radial profile samples of every
+    row and passband on the tables' mu samples, shape (npv, npb, nmu) (or
+    (npv, nmu) with one passband), e.g. from :mod:`ldlaws`.  Returns a
+    device tensor, float64 for "fp64" and float32 for "mixed"."""
+    prec = PRECISIONS[precision]
+    if not isinstance(series, TimeSeries):
+        series = TimeSeries(series)
+    pv = _dev(pv, torch.float64)
+    if pv.dim() == 1:
+        pv = pv.unsqueeze(0)
+    npv, npar = pv.shape
+    prof = _dev(prof, torch.float64)
+    if prof.numel() != npv * tables.npb * tables.nmu:
+        raise ValueError("prof must have npv * npb * nmu samples")
+    dtype = torch.float64 if prec == RR_FP64 else torch.float32
+    if out is None:
+        out = torch.empty((npv, series.npt), dtype=dtype, device=pv.device)
+    elif out.dtype != dtype or not out.is_contiguous() or out.numel() != npv * series.npt:
+        raise ValueError("out has the wrong dtype, layout or size")
+    lc, npt, pb, nss, ex, nlc = series.lc_args()
+    check(_lib.lib().rr_evaluate_ld(tables.handle, ctypes.c_void_p(series.times.data_ptr()),
+                                    lc, npt, pb, nss, ex, nlc,
+                                    ctypes.c_void_p(pv.data_ptr()), npv, npar,
+                                    ctypes.c_void_p(prof.data_ptr()), prec,
+                                    ctypes.c_void_p(out.data_ptr()), _stream(stream)),
+          "rr_evaluate_ld")
+    return out
+
+
 class Evaluator:
     """rr_evaluate for repeated calls with populations of one size over one
     time series (the MCMC pattern): every argument except the parameter

@@ -267,6 +267,53 @@ RR_API int rr_evaluate(const rr_tables* t, const double* times_d,
     return RR_OK;
 }
 
+RR_API int rr_evaluate_ld(const rr_tables* t, const double* times_d,
+                          const int32_t* lcids_d, int32_t npt,
+                          const int32_t* pbids, const int32_t* nss,
+                          const double* exptimes, int32_t nlc,
+                          const double* pv_d, int32_t npv, int32_t npar,
+                          const double* prof_d, int32_t precision, void* out_d,
+                          hipStream_t stream) {
+    LcInfo lc;
+    int rc = check_eval_args(t, times_d, lcids_d, npt, pbids, nss, exptimes, nlc,
+                             pv_d, npv, npar, precision, &lc);
+    if (rc) return rc;
+    if (npt == 0 || npv == 0) return RR_OK;
+    if (!out_d) return einval("out is NULL");
+    if (!prof_d) return einval("prof is NULL");
+    const int64_t nr = int64_t(npv) * t->npb;
+    if (nr * t->nz >= (int64_t(1) << 31))
+        return elimit("npv * npb * nz must stay below 2^31");
+    rc = check_device(t);
+    if (rc) return rc;
+    const size_t elt = precision == RR_FP64 ? sizeof(double) : sizeof(float);
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off += (bytes + 255) / 256 * 256; return o; };
+    const size_t o_pvc = take(sizeof(PvConst) * size_t(npv));
+    const size_t o_ldp = take(sizeof(double) * size_t(nr) * t->nz);
+    const size_t o_is = take(sizeof(double) * size_t(nr));
+    const size_t o_iis = take(sizeof(double) * size_t(nr));
+    const size_t o_ldw = take(elt * size_t(nr) * 2 * t->grid.ng);
+    char* base = nullptr;
+    hipError_t e = hipMallocAsync((void**)&base, off, stream);
+    if (e != hipSuccess) return e == hipErrorOutOfMemory ? RR_ENOMEM : hip_fail(e, "hipMallocAsync");
+    PvConst* pvc = reinterpret_cast<PvConst*>(base + o_pvc);
+    double* inv_is = reinterpret_cast<double*>(base + o_iis);
+    void* ldw = base + o_ldw;
+    e = launch_pv_setup(t, pv_d, npv, npar, pvc, stream);
+    if (e == hipSuccess)
+        e = launch_pv_ld(t, prof_d, pv_d, npv, npar, precision,
+                         reinterpret_cast<double*>(base + o_ldp),
+                         reinterpret_cast<double*>(base + o_is), inv_is, ldw, stream);
+    if (e == hipSuccess)
+        e = launch_forward(t, times_d, lcids_d, npt, lc, pv_d, npv, npar, pvc, precision,
+                           out_d, stream, ldw, inv_is);
+    hipError_t ef = hipFreeAsync(base, stream);
+    if (e != hipSuccess) return hip_fail(e, "per-vector LD kernels");
+    if (ef != hipSuccess) return hip_fail(ef, "hipFreeAsync");
+    return RR_OK;
+}
+
 RR_API int rr_loglik_grad(const rr_tables* t, const double* times_d,
                           const int32_t* lcids_d, int32_t npt,
                           const int32_t* pbids, const int32_t* nss,

@@ -51,9 +51,21 @@ struct PbConst {
 template <typename R>
 __device__ inline PbConst<R> pb_const(const double* __restrict__ pv, int ipv, int npar, int pb,
                                       const GridDev& g, const R* __restrict__ T,
-                                      const double* __restrict__ inv_istar) {
+                                      const double* __restrict__ inv_istar, const FwdJob& job) {
     PbConst<R> c;
     const double kd = pv[int64_t(ipv) * npar + 6 + pb];
+    if (job.ldw_pv) {
+        // per-vector LD: the vector's own k-interpolated vector, stored twice
+        // so that the k-lerp below (weight 0 on the copy) returns it exactly
+        const int64_t r = int64_t(ipv) * g.npb + pb;
+        c.ak = R(0);
+        c.t0r = static_cast<const R*>(job.ldw_pv) + r * 2 * g.ng;
+        c.k = R(kd);
+        c.onepk = R(1) + c.k;
+        c.inv1pk = R(1) / c.onepk;
+        c.istar_inv = R(job.inv_istar_pv[r]);
+        return c;
+    }
     const double u = (kd - g.k0) / g.dk;
     int ik = int(floor(u));
     ik = ik < 0 ? 0 : (ik > g.nk - 2 ? g.nk - 2 : ik);
@@ -279,7 +291,7 @@ __device__ inline void forward_block(const FwdJob& job, const LcInfo& lc, int ip
                     const int pb = lc.pb[l];
                     if (pb != pb_cached) {
                         pb_cached = pb;
-                        c = pb_const<R>(pv, ipv, npar, pb, g, T, inv_istar);
+                        c = pb_const<R>(pv, ipv, npar, pb, g, T, inv_istar, job);
                     }
                     val = subsample_delta<R>(p, orb, c, times[it], lc.exptime[l], inv_nss, sub, g);
                 }
@@ -301,7 +313,7 @@ __device__ inline void forward_block(const FwdJob& job, const LcInfo& lc, int ip
         const int pb = lc.pb[l];                      // registers free here
         if (pb != pb_cached) {
             pb_cached = pb;
-            c = pb_const<R>(pv, ipv, npar, pb, g, T, inv_istar);
+            c = pb_const<R>(pv, ipv, npar, pb, g, T, inv_istar, job);
         }
         orow[it] = exposure_flux<R>(p, orb, c, times[it], lc.exptime[l], lc.nss[l], g);
     }
@@ -361,9 +373,10 @@ hipError_t launch_forward(const rr_tables* t, const double* times,
                           const int32_t* lcids, int32_t npt, const LcInfo& lc,
                           const double* pv, int32_t npv, int32_t npar,
                           const PvConst* pvc, int32_t precision, void* out,
-                          hipStream_t s) {
+                          hipStream_t s, const void* ldw_pv, const double* inv_istar_pv) {
     const GridDev g = grid_dev(t);
     FwdJob job;
+    job.ldw_pv = ldw_pv; job.inv_istar_pv = inv_istar_pv;
     job.times = times; job.lcids = lcids; job.lc = nullptr; job.pv = pv; job.pvc = pvc;
     job.out = out; job.npt = npt; job.npar = npar; job.pv0 = 0; job.npv = npv;
     job.ntiles = (npt + kFwdTile - 1) / kFwdTile; job.block0 = 0; job.max_nss = 1;

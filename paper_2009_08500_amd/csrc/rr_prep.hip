@@ -163,6 +163,82 @@ hipError_t launch_prepare_grid_weights(rr_tables* t, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Per-vector LD vector: ldw[r][m] = (1 - ak) sum_j W[ik][j][m] ldp[r][j]
+// + ak sum_j W[ik+1][j][m] ldp[r][j] for r = (vector, passband), the same
+// T = W . l contraction as k_tables restricted to the two k-rows around the
+// vector's k (Sect. 3.1.2), summed over bins in order in FP64.  Workgroup
+// (r, x): 256 consecutive m; the vector's ldp row is staged in LDS.  The
+// result goes out twice ([2][ng]) in the evaluation precision.
+template <typename R>
+__global__ void k_pv_ldw(const double* __restrict__ W, const double* __restrict__ ldp,
+                         const double* __restrict__ pv, int32_t npar, int32_t nz, GridDev g,
+                         R* __restrict__ ldw) {
+    __shared__ double lp[4096];
+    const int nmb = (g.ng + kBlock - 1) / kBlock;
+    const int64_t r = int64_t(blockIdx.x) / nmb;
+    const int mb = int(int64_t(blockIdx.x) - r * nmb);
+    const int64_t ipv = r / g.npb;
+    const int pb = int(r - ipv * g.npb);
+    for (int j = threadIdx.x; j < nz; j += kBlock) lp[j] = ldp[r * nz + j];
+    __syncthreads();
+    const int m = mb * kBlock + int(threadIdx.x);
+    if (m >= g.ng) return;
+    const double u = (pv[ipv * npar + 6 + pb] - g.k0) / g.dk;
+    double uf = floor(u);
+    if (!(uf >= 0.0)) uf = 0.0;                  // also a non-finite k (row is NaN anyway)
+    if (uf > g.nk - 2) uf = g.nk - 2;
+    const int ik = int(uf);
+    const double ak = u - ik;
+    const double* w0 = W + int64_t(ik) * nz * g.ng + m;
+    const double* w1 = w0 + int64_t(nz) * g.ng;
+    double a0 = 0.0, a1 = 0.0;
+    int j = 0;
+    for (; j + 4 <= nz; j += 4) {                 // four bins' loads in flight
+        double x0[4], x1[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            x0[b] = w0[int64_t(j + b) * g.ng];
+            x1[b] = w1[int64_t(j + b) * g.ng];
+        }
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            a0 += x0[b] * lp[j + b];
+            a1 += x1[b] * lp[j + b];
+        }
+    }
+    for (; j < nz; ++j) {
+        a0 += w0[int64_t(j) * g.ng] * lp[j];
+        a1 += w1[int64_t(j) * g.ng] * lp[j];
+    }
+    const R v = R((1.0 - ak) * a0 + ak * a1);
+    R* o = ldw + r * 2 * g.ng;
+    o[m] = v;
+    o[g.ng + m] = v;
+}
+
+hipError_t launch_pv_ld(const rr_tables* t, const double* prof, const double* pv,
+                        int32_t npv, int32_t npar, int32_t precision, double* ldp,
+                        double* istar, double* inv_istar, void* ldw, hipStream_t s) {
+    const GridDev g = grid_dev(t);
+    const int64_t nr = int64_t(npv) * t->npb;     // (vector, passband) rows
+    // the table kernels with every (vector, passband) as one profile
+    hipLaunchKernelGGL(k_profile, dim3(nblocks(int64_t(t->nz) * nr)), dim3(kBlock), 0, s,
+                       t->mu_s, prof, t->nmu, t->zm, t->nz, int32_t(nr), ldp);
+    hipLaunchKernelGGL(k_istar, dim3(unsigned(nr)), dim3(kBlock), 0, s, t->mu_s, prof, t->nmu,
+                       istar, inv_istar);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int nmb = (g.ng + kBlock - 1) / kBlock;
+    const dim3 grid(unsigned(nr * nmb));
+    if (precision == RR_FP64)
+        hipLaunchKernelGGL(k_pv_ldw<double>, grid, dim3(kBlock), 0, s, t->W, ldp, pv, npar,
+                           t->nz, g, static_cast<double*>(ldw));
+    else
+        hipLaunchKernelGGL(k_pv_ldw<float>, grid, dim3(kBlock), 0, s, t->W, ldp, pv, npar,
+                           t->nz, g, static_cast<float*>(ldw));
+    return hipGetLastError();
+}
+
 hipError_t launch_prepare_profile(rr_tables* t, hipStream_t s) {
     const GridDev g = grid_dev(t);
     hipLaunchKernelGGL(k_profile, dim3(nblocks(int64_t(t->nz) * t->npb)), dim3(kBlock), 0, s,

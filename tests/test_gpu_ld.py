@@ -1,0 +1,119 @@
+"""GPU parity of per-vector limb darkening (rr_evaluate_ld: every parameter
+vector with its own LD profile) against the oracle's evaluate_ld, through the
+C ABI.  Tolerances as the shared-table parity tests: 1e-9 absolute for the
+FP64 path (a logic check), 1 ppm for the mixed path, and exactly 1.0 where
+the oracle has no occultation."""
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import roadrunner as orr
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-9
+TOL_MIXED = 1e-6
+
+
+@pytest.fixture(scope="module")
+def rr():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2009_08500_amd as rr
+    return rr
+
+
+def check(ref, f64, f32):
+    nan = np.isnan(ref)
+    assert np.array_equal(nan, np.isnan(f64)) and np.array_equal(nan, np.isnan(f32))
+    r, a, b = ref[~nan], f64[~nan], f32[~nan]
+    assert np.abs(a - r).max(initial=0.0) <= TOL64
+    assert np.abs(b - r).max(initial=0.0) <= TOL_MIXED
+    out = r == 1.0
+    assert np.all(a[out] == 1.0) and np.all(b[out] == 1.0)
+
+
+@pytest.mark.parametrize("npt", [1, 511, 513, 1537, 5000])
+def test_population_ld_matches_oracle(rr, npt):
+    """Ragged time tails around the 512-time tiles, one invalid row."""
+    w = wl.population_ld(npv=10, npt=npt)
+    w["times"] = np.linspace(0.0, 12.0, npt)
+    pv = w["pv"].copy()
+    pv[4, 6] = 0.5                                          # k outside the table: NaN row
+    tab = rr.Tables(w["mu_s"], w["I_s"], wl.TEST_GRID)
+    otab = orr.Tables(w["mu_s"], w["I_s"], **wl.TEST_GRID)
+    ser = rr.TimeSeries(w["times"])
+    f64 = rr.evaluate_ld(tab, ser, pv, w["prof_pv"], "fp64").cpu().numpy()
+    f32 = rr.evaluate_ld(tab, ser, pv, w["prof_pv"], "mixed").cpu().numpy().astype(np.float64)
+    ref = orr.evaluate_ld(otab, w["times"], pv, w["prof_pv"])
+    assert np.isnan(ref[4]).all()
+    check(ref, f64, f32)
+
+
+def test_heterogeneous_passbands_and_supersampling(rr):
+    """Four passbands, each vector with four profiles of its own, chromatic k,
+    nss 10 and 1 light curves."""
+    w = wl.heterogeneous(npv=6, days=4.0)
+    rng = np.random.default_rng(11)
+    c = rng.uniform(0.3, 0.7, (6, 4))
+    al = rng.uniform(0.4, 0.8, (6, 4))
+    prof = 1.0 - c[..., None] * (1.0 - w["mu_s"][None, None, :] ** al[..., None])
+    kw = dict(lcids=w["lcids"], pbids=w["pbids"], nss=w["nss"], exptimes=w["exptimes"])
+    tab = rr.Tables(w["mu_s"], w["I_s"], wl.TEST_GRID)
+    otab = orr.Tables(w["mu_s"], w["I_s"], **wl.TEST_GRID)
+    ser = rr.TimeSeries(w["times"], w["lcids"], w["pbids"], w["nss"], w["exptimes"])
+    f64 = rr.evaluate_ld(tab, ser, w["pv"], prof, "fp64").cpu().numpy()
+    f32 = rr.evaluate_ld(tab, ser, w["pv"], prof, "mixed").cpu().numpy().astype(np.float64)
+    ref = orr.evaluate_ld(otab, w["times"], w["pv"], prof, **kw)
+    check(ref, f64, f32)
+
+
+def test_own_profile_equals_shared_tables(rr):
+    """Every vector given the tables' own profile: rr_evaluate_ld and
+    rr_evaluate agree to rounding (the same T rows, contracted per vector)."""
+    w = wl.population(npv=64, npt=6000)
+    tab = rr.Tables(w["mu_s"], w["I_s"], wl.DEFAULT_GRID)
+    ser = rr.TimeSeries(w["times"])
+    prof = np.broadcast_to(w["I_s"], (64,) + w["I_s"].shape).copy()
+    for prec, tol in (("fp64", 1e-14), ("mixed", 2e-7)):
+        a = rr.evaluate_ld(tab, ser, w["pv"], prof, prec).cpu().numpy().astype(np.float64)
+        b = rr.evaluate(tab, ser, w["pv"], prec).cpu().numpy().astype(np.float64)
+        assert np.abs(a - b).max() <= tol, (prec, np.abs(a - b).max())
+
+
+def test_full_size_sampled_rows(rr):
+    """The per-vector LD population at full size (512 x 20 000, default
+    grid), in the launch configuration the benchmark times; six sampled rows
+    against the oracle."""
+    w = wl.population_ld()
+    tab = rr.Tables(w["mu_s"], w["I_s"], wl.DEFAULT_GRID)
+    otab = orr.Tables(w["mu_s"], w["I_s"], **wl.DEFAULT_GRID)
+    ser = rr.TimeSeries(w["times"])
+    f64 = rr.evaluate_ld(tab, ser, w["pv"], w["prof_pv"], "fp64").cpu().numpy()
+    f32 = rr.evaluate_ld(tab, ser, w["pv"], w["prof_pv"], "mixed").cpu().numpy()
+    rows = np.random.default_rng(5).choice(512, 6, replace=False)
+    ref = orr.evaluate_ld(otab, w["times"], w["pv"][rows], w["prof_pv"][rows])
+    check(ref, f64[rows], f32[rows].astype(np.float64))
+    assert np.isfinite(f64).all() and np.isfinite(f32).all()
+
+
+def test_arguments(rr):
+    import torch
+    w = wl.population_ld(npv=3, npt=100)
+    tab = rr.Tables(w["mu_s"], w["I_s"], wl.TEST_GRID)
+    ser = rr.TimeSeries(w["times"])
+    with pytest.raises(ValueError):
+        rr.evaluate_ld(tab, ser, w["pv"], w["prof_pv"][:2], "fp64")
+    out = rr.evaluate_ld(tab, ser, w["pv"][:0], w["prof_pv"][:0], "fp64")
+    assert out.shape == (0, 100)
+    from paper_2009_08500_amd import _lib
+    pv = torch.as_tensor(w["pv"], device="cuda")
+    lc, npt, pb, nss, ex, nlc = ser.lc_args()
+    import ctypes
+    o = torch.empty((3, 100), dtype=torch.float64, device="cuda")
+    rc = _lib.lib().rr_evaluate_ld(tab.handle, ctypes.c_void_p(ser.times.data_ptr()), lc, npt,
+                                   pb, nss, ex, nlc, ctypes.c_void_p(pv.data_ptr()), 3, 7, None,
+                                   0, ctypes.c_void_p(o.data_ptr()), None)
+    assert rc == _lib.RR_EINVAL and "prof" in _lib.last_error()

@@ -114,6 +114,23 @@ def population(npv=512, npt=20000, seed_extra=0):
                      name=f"population_npv{npv}_npt{npt}")
 
 
+def population_ld(npv=512, npt=20000, seed_extra=0):
+    """Population evaluation with a profile per parameter vector (LD sampled
+    with the orbit): the orbits, times and mu samples of ``population``, and
+    for every vector its own power-2 profile with c ~ U(0.5, 0.8),
+    alpha ~ U(0.4, 0.8) at 200 mu.  ``prof_pv`` is (npv, 1, 200); the shared
+    ``I_s`` (the tables' own profile) is the population's."""
+    w = population(npv, npt, seed_extra)
+    rng = rng_for(6, seed_extra)
+    c = rng.uniform(0.5, 0.8, npv)
+    alpha = rng.uniform(0.4, 0.8, npv)
+    w["prof_pv"] = np.stack([profile_power2(w["mu_s"], c[i], alpha[i])
+                             for i in range(npv)])[:, None, :]
+    w["ld_c_pv"], w["ld_alpha_pv"] = c, alpha
+    w["name"] = f"population_ld_npv{npv}_npt{npt}"
+    return w
+
+
 def heterogeneous(npv=256, days=27.0, seed_extra=0):
     """Four passbands with their own profiles and chromatic k; two 30-min
     light curves with nss = 10 and two 2-min light curves with nss = 1, all
