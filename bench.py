@@ -80,9 +80,16 @@ def valu_view(kernel, kernel_ms):
     if not k or "SQ_INSTS_VALU" not in k:
         return None
     slots = 64.0 * k["SQ_INSTS_VALU"]
-    return dict(valu_instrs_per_launch=k["SQ_INSTS_VALU"], lane_slots_per_launch=slots,
-                peak_lane_slots_per_s=VALU_LANE_SLOTS,
-                issue_frac=slots / (kernel_ms * 1e-3) / VALU_LANE_SLOTS)
+    v = dict(valu_instrs_per_launch=k["SQ_INSTS_VALU"], lane_slots_per_launch=slots,
+             peak_lane_slots_per_s=VALU_LANE_SLOTS,
+             issue_frac=slots / (kernel_ms * 1e-3) / VALU_LANE_SLOTS)
+    if "fp32_flop_per_launch" in k:
+        # upper bounds (all 64 lanes counted); peaks: unpacked FP32 and FP64 vector
+        v["fp32_tflops"] = k["fp32_flop_per_launch"] / (kernel_ms * 1e-3) / 1e12
+        v["fp64_tflops"] = k["fp64_flop_per_launch"] / (kernel_ms * 1e-3) / 1e12
+        v["fp32_peak_tflops"] = 78.6
+        v["fp64_peak_tflops"] = 78.6
+    return v
 
 
 def time_path(rr, tab, series, pv, prec, steps, warmup, lib):
@@ -191,6 +198,66 @@ def heterogeneous_leg(rr, wl, steps, warmup, lib):
     res["accuracy_vs_oracle"] = dict(rows_checked=npv,
                                      max_abs_err_fp64=float(np.abs(outs["fp64"] - ref).max()),
                                      max_abs_err_mixed_ppm=float(np.abs(outs["mixed"] - ref).max()) * 1e6)
+    return res
+
+
+def per_vector_ld_leg(rr, wl, steps, warmup, lib):
+    """The population (512 x 20 000, nss 1) with a power-2 LD profile of its
+    own for every row (rr_evaluate_ld): points/s and per-call latency for
+    both precisions, the forward kernel's own time (launch events), and the
+    error of eight sampled rows against the oracle."""
+    import numpy as np
+    import torch
+    from oracle import roadrunner as orr
+    w = wl.population_ld()
+    grid = wl.DEFAULT_GRID
+    tab = rr.Tables(w["mu_s"], w["I_s"], grid)
+    ser = rr.TimeSeries(w["times"])
+    pv = torch.as_tensor(w["pv"], device="cuda")
+    prof = torch.as_tensor(w["prof_pv"], device="cuda")
+    npv, npt = pv.shape[0], int(w["times"].size)
+    res = dict(workload=f"population with per-vector power-2 LD: npv={npv} npt={npt} nss=1, "
+                        "profiles at 200 mu", npv=npv, npt=npt)
+    outs = {}
+    for prec in ("mixed", "fp64"):
+        dtype = torch.float64 if prec == "fp64" else torch.float32
+        out = torch.empty((npv, npt), dtype=dtype, device="cuda")
+        for _ in range(warmup):
+            rr.evaluate_ld(tab, ser, pv, prof, prec, out=out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            rr.evaluate_ld(tab, ser, pv, prof, prec, out=out)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / steps
+        step_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                   for _ in range(steps)]
+        kern_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                   for _ in range(steps)]
+        for a, b in kern_ev:
+            a.record()
+            b.record()
+        torch.cuda.synchronize()
+        for i in range(steps):
+            step_ev[i][0].record()
+            lib.rr_set_kernel_events(kern_ev[i][0].cuda_event, kern_ev[i][1].cuda_event)
+            rr.evaluate_ld(tab, ser, pv, prof, prec, out=out)
+            step_ev[i][1].record()
+        torch.cuda.synchronize()
+        lib.rr_set_kernel_events(None, None)
+        step_ms = [a.elapsed_time(b) for a, b in step_ev]
+        kern_ms = [a.elapsed_time(b) for a, b in kern_ev]
+        res[prec] = dict(points_per_s=npv * npt / (ms / 1e3), ms_per_step=ms,
+                         forward_kernel_ms=float(np.mean(kern_ms)),
+                         latency_ms=dict(p50=pct(step_ms, 50), p99=pct(step_ms, 99)))
+        outs[prec] = out.cpu().numpy().astype(np.float64)
+    rows = np.random.default_rng(9).choice(npv, 8, replace=False)
+    otab = orr.Tables(w["mu_s"], w["I_s"], **grid)
+    ref = orr.evaluate_ld(otab, w["times"], w["pv"][rows], w["prof_pv"][rows])
+    res["accuracy_vs_oracle"] = dict(
+        rows_checked=len(rows),
+        max_abs_err_fp64=float(np.abs(outs["fp64"][rows] - ref).max()),
+        max_abs_err_mixed_ppm=float(np.abs(outs["mixed"][rows] - ref).max()) * 1e6)
     return res
 
 
@@ -420,6 +487,7 @@ def main():
         line["serving"] = serving_leg(rr, wl, args.serving_requests)
     if not args.no_extra:
         line["heterogeneous"] = heterogeneous_leg(rr, wl, min(args.steps, 50), 5, lib)
+        line["per_vector_ld"] = per_vector_ld_leg(rr, wl, min(args.steps, 50), 5, lib)
         line["loglik_grad"] = loglik_leg(rr, wl, 10, 2)
     if not args.no_cpu_baseline:
         cb, acc = cpu_baseline(w, grid, args.cpu_seconds, o64, o32)

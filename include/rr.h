@@ -147,6 +147,35 @@ RR_API int rr_evaluate(const rr_tables* t, const double* times_d,
                        const double* pv_d, int32_t npv, int32_t npar,
                        int32_t precision, void* out_d, hipStream_t stream);
 
+/* Fluxes as rr_evaluate, but with a limb-darkening profile of its own for
+ * every parameter vector, as when the LD coefficients are sampled together
+ * with the orbit (each row of the population carries its own stellar
+ * profile; the paper's model takes LD coefficients per evaluation,
+ * Sect. 4.2).  prof_d[npv][npb][nmu] is a device FP64 array of radial
+ * profile samples of vector ipv in passband pb, on the tables' mu samples
+ * (the mu grid given to rr_prepare_ld).  The tables' z-grid and annulus
+ * weights W are reused; per vector and passband the library interpolates
+ * the profile to the bin means, integrates I_star exactly for the
+ * piecewise-linear profile (as rr_prepare_ld does) and contracts W with it
+ * over the two k-rows around the vector's k (T = W . l of Sect. 3.1.2,
+ * restricted to those rows, in the same bin order as the shared table) in
+ * FP64, then interpolates them in k as the shared rows are; the
+ * evaluation then follows rr_evaluate with those rows in place of the
+ * shared ones.  With every vector given the tables' own profile the fluxes
+ * equal rr_evaluate's bitwise.  Other arguments, errors and
+ * invalid rows as rr_evaluate; non-finite profile samples give non-finite
+ * in-transit fluxes of that vector only.  npv * npb * nz < 2^31
+ * (RR_ELIMIT beyond).  Temporary device memory, ~(144 + npb (32 + 8 nz +
+ * 2 ng sizeof(real))) bytes per vector, is the per-stream buffer that
+ * rr_evaluate uses (same growth and reuse rules). */
+RR_API int rr_evaluate_ld(const rr_tables* t, const double* times_d,
+                          const int32_t* lcids_d, int32_t npt,
+                          const int32_t* pbids, const int32_t* nss,
+                          const double* exptimes, int32_t nlc,
+                          const double* pv_d, int32_t npv, int32_t npar,
+                          const double* prof_d, int32_t precision, void* out_d,
+                          hipStream_t stream);
+
 /* Gaussian log-likelihood of observed fluxes obs_d[npt] under each
  * parameter vector, and its gradient, with the same time-series and
  * parameter arguments as rr_evaluate:
@@ -172,34 +201,6 @@ RR_API int rr_evaluate(const rr_tables* t, const double* times_d,
  * allocator: ~(160 + 8 (7 + npb) npt / 1024) bytes per parameter vector,
  * and with grad_prof a further 8 npb ng bytes per vector plus at most
  * 512 MiB of partial sums. */
-/* Fluxes as rr_evaluate, but with a limb-darkening profile of its own for
- * every parameter vector, as when the LD coefficients are sampled together
- * with the orbit (each row of the population carries its own stellar
- * profile; the paper's model takes LD coefficients per evaluation,
- * Sect. 4.2).  prof_d[npv][npb][nmu] is a device FP64 array of radial
- * profile samples of vector ipv in passband pb, on the tables' mu samples
- * (the mu grid given to rr_prepare_ld).  The tables' z-grid and annulus
- * weights W are reused; per vector and passband the library interpolates
- * the profile to the bin means, integrates I_star exactly for the
- * piecewise-linear profile (as rr_prepare_ld does) and contracts W with it
- * over the two k-rows around the vector's k (T = W . l of Sect. 3.1.2,
- * restricted to those rows, then the k-interpolation), all in FP64; the
- * evaluation then follows rr_evaluate with that vector in place of the
- * shared table row.  With every vector given the tables' own profile the
- * fluxes equal rr_evaluate's to rounding.  Other arguments, errors and
- * invalid rows as rr_evaluate; non-finite profile samples give non-finite
- * in-transit fluxes of that vector only.  npv * npb * nz < 2^31
- * (RR_ELIMIT beyond).  Temporary device memory, ~(144 + npb (24 + 8 nz +
- * 2 ng sizeof(real))) bytes per vector, comes from the stream-ordered
- * allocator. */
-RR_API int rr_evaluate_ld(const rr_tables* t, const double* times_d,
-                          const int32_t* lcids_d, int32_t npt,
-                          const int32_t* pbids, const int32_t* nss,
-                          const double* exptimes, int32_t nlc,
-                          const double* pv_d, int32_t npv, int32_t npar,
-                          const double* prof_d, int32_t precision, void* out_d,
-                          hipStream_t stream);
-
 RR_API int rr_loglik_grad(const rr_tables* t, const double* times_d,
                           const int32_t* lcids_d, int32_t npt,
                           const int32_t* pbids, const int32_t* nss,

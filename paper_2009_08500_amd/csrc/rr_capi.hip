@@ -294,9 +294,14 @@ RR_API int rr_evaluate_ld(const rr_tables* t, const double* times_d,
     const size_t o_is = take(sizeof(double) * size_t(nr));
     const size_t o_iis = take(sizeof(double) * size_t(nr));
     const size_t o_ldw = take(elt * size_t(nr) * 2 * t->grid.ng);
-    char* base = nullptr;
-    hipError_t e = hipMallocAsync((void**)&base, off, stream);
-    if (e != hipSuccess) return e == hipErrorOutOfMemory ? RR_ENOMEM : hip_fail(e, "hipMallocAsync");
+    const size_t o_ikr = take(sizeof(int32_t) * size_t(nr));
+    const size_t o_perm = take(sizeof(int32_t) * size_t(nr));
+    // the tables' per-stream workspace (as rr_evaluate): reused without
+    // waiting by later calls on the same stream
+    void* ws = nullptr;
+    hipError_t e = stream_workspace(const_cast<rr_tables*>(t), stream, off, &ws);
+    if (e != hipSuccess) return e == hipErrorOutOfMemory ? RR_ENOMEM : hip_fail(e, "workspace");
+    char* base = static_cast<char*>(ws);
     PvConst* pvc = reinterpret_cast<PvConst*>(base + o_pvc);
     double* inv_is = reinterpret_cast<double*>(base + o_iis);
     void* ldw = base + o_ldw;
@@ -304,13 +309,13 @@ RR_API int rr_evaluate_ld(const rr_tables* t, const double* times_d,
     if (e == hipSuccess)
         e = launch_pv_ld(t, prof_d, pv_d, npv, npar, precision,
                          reinterpret_cast<double*>(base + o_ldp),
-                         reinterpret_cast<double*>(base + o_is), inv_is, ldw, stream);
+                         reinterpret_cast<double*>(base + o_is), inv_is,
+                         reinterpret_cast<int32_t*>(base + o_ikr),
+                         reinterpret_cast<int32_t*>(base + o_perm), ldw, stream);
     if (e == hipSuccess)
         e = launch_forward(t, times_d, lcids_d, npt, lc, pv_d, npv, npar, pvc, precision,
                            out_d, stream, ldw, inv_is);
-    hipError_t ef = hipFreeAsync(base, stream);
     if (e != hipSuccess) return hip_fail(e, "per-vector LD kernels");
-    if (ef != hipSuccess) return hip_fail(ef, "hipFreeAsync");
     return RR_OK;
 }
 

@@ -55,10 +55,13 @@ __device__ inline PbConst<R> pb_const(const double* __restrict__ pv, int ipv, in
     PbConst<R> c;
     const double kd = pv[int64_t(ipv) * npar + 6 + pb];
     if (job.ldw_pv) {
-        // per-vector LD: the vector's own k-interpolated vector, stored twice
-        // so that the k-lerp below (weight 0 on the copy) returns it exactly
+        // per-vector LD: the vector's own copies of the two table rows
+        // around its k, interpolated in k below as the shared rows are
         const int64_t r = int64_t(ipv) * g.npb + pb;
-        c.ak = R(0);
+        const double u = (kd - g.k0) / g.dk;
+        int ik = int(floor(u));
+        ik = ik < 0 ? 0 : (ik > g.nk - 2 ? g.nk - 2 : ik);
+        c.ak = R(u - ik);
         c.t0r = static_cast<const R*>(job.ldw_pv) + r * 2 * g.ng;
         c.k = R(kd);
         c.onepk = R(1) + c.k;

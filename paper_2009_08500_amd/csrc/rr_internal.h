@@ -68,8 +68,8 @@ struct FwdJob {
     int32_t npt, npar, pv0, npv, ntiles, block0;
     int32_t max_nss;           // largest nss of the job's light curves
     // per-vector LD (rr_evaluate_ld), NULL with the shared tables: the
-    // vector's own k-interpolated LD vector, [npv][npb][2][ng] in the
-    // evaluation precision (the two rows are equal), and 1/I_star [npv][npb]
+    // vector's own two table rows around its k, [npv][npb][2][ng] in the
+    // evaluation precision, and 1/I_star [npv][npb]
     const void* ldw_pv;
     const double* inv_istar_pv;
 };
@@ -206,10 +206,12 @@ hipError_t launch_forward(const rr_tables* t, const double* times,
                           const double* inv_istar_pv = nullptr);
 // Per-vector LD (rr_evaluate_ld): from prof[npv][npb][nmu] on the tables'
 // mu samples, the profile at the bin means (ldp, [npv][npb][nz]), I_star and
-// 1/I_star ([npv][npb]) and the vector's k-interpolated LD vector ldw
-// ([npv][npb][2][ng], double or float by precision).
+// 1/I_star ([npv][npb]) and the vector's own two table rows around its k
+// (rows, [npv][npb][2][ng], double or float by precision); ikr and perm are
+// [npv npb] int32 scratch.
 hipError_t launch_pv_ld(const rr_tables* t, const double* prof, const double* pv,
                         int32_t npv, int32_t npar, int32_t precision, double* ldp,
-                        double* istar, double* inv_istar, void* ldw, hipStream_t s);
+                        double* istar, double* inv_istar, int32_t* ikr, int32_t* perm,
+                        void* rows, hipStream_t s);
 
 }  // namespace rr

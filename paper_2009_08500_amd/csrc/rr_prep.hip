@@ -61,6 +61,22 @@ __global__ void k_weights(const double* __restrict__ ze, GridDev g,
     W[idx] = w;
 }
 
+// The profile's piecewise-linear interpolant at the mean of bin j.
+__device__ inline double profile_at_bin(const double* __restrict__ mu_s,
+                                        const double* __restrict__ f, int32_t nmu,
+                                        double z) {
+    const double mu = sqrt(1.0 - z * z);
+    if (mu <= mu_s[0]) return f[0];
+    if (mu >= mu_s[nmu - 1]) return f[nmu - 1];
+    int lo = 0, hi = nmu - 1;          // mu_s[lo] <= mu < mu_s[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (mu_s[mid] <= mu) lo = mid; else hi = mid;
+    }
+    const double slope = (f[lo + 1] - f[lo]) / (mu_s[lo + 1] - mu_s[lo]);
+    return slope * (mu - mu_s[lo]) + f[lo];
+}
+
 __global__ void k_profile(const double* __restrict__ mu_s,
                           const double* __restrict__ prof, int32_t nmu,
                           const double* __restrict__ zm, int32_t nz,
@@ -68,43 +84,25 @@ __global__ void k_profile(const double* __restrict__ mu_s,
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= nz * npb) return;
     const int pb = idx / nz, j = idx - pb * nz;
-    const double z = zm[j];
-    const double mu = sqrt(1.0 - z * z);
-    const double* f = prof + int64_t(pb) * nmu;
-    double v;
-    if (mu <= mu_s[0]) {
-        v = f[0];
-    } else if (mu >= mu_s[nmu - 1]) {
-        v = f[nmu - 1];
-    } else {
-        int lo = 0, hi = nmu - 1;      // mu_s[lo] <= mu < mu_s[hi]
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (mu_s[mid] <= mu) lo = mid; else hi = mid;
-        }
-        const double slope = (f[lo + 1] - f[lo]) / (mu_s[lo + 1] - mu_s[lo]);
-        v = slope * (mu - mu_s[lo]) + f[lo];
-    }
-    ldp[idx] = v;
+    ldp[idx] = profile_at_bin(mu_s, prof + int64_t(pb) * nmu, nmu, zm[j]);
 }
 
-// One workgroup per passband; per-thread partial sums over a fixed stride,
-// then a fixed-shape tree in LDS: deterministic.
-__global__ void k_istar(const double* __restrict__ mu_s,
-                        const double* __restrict__ prof, int32_t nmu,
-                        double* __restrict__ istar,
-                        double* __restrict__ inv_istar) {
+// I_star of one profile by one workgroup of kBlock threads: per-thread
+// partial sums over a fixed stride, then a fixed-shape tree in LDS
+// (deterministic).  Thread 0 stores I_star and 1/I_star.
+__device__ inline void istar_block(const double* __restrict__ mu_s,
+                                   const double* __restrict__ f, int32_t nmu,
+                                   double* __restrict__ istar,
+                                   double* __restrict__ inv_istar) {
     __shared__ double part[kBlock];
-    const int pb = blockIdx.x;
-    const double* f = prof + int64_t(pb) * nmu;
     double acc = 0.0;
-    for (int s = threadIdx.x; s < nmu - 1; s += blockDim.x) {
+    for (int s = threadIdx.x; s < nmu - 1; s += kBlock) {
         const double ma = mu_s[s], mb = mu_s[s + 1];
         acc += (mb - ma) / 6.0 * (f[s] * (2.0 * ma + mb) + f[s + 1] * (ma + 2.0 * mb));
     }
     part[threadIdx.x] = acc;
     __syncthreads();
-    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
         if (threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
         __syncthreads();
     }
@@ -113,9 +111,18 @@ __global__ void k_istar(const double* __restrict__ mu_s,
         const double tot = part[0] + f[0] * 0.5 * m0 * m0 +
                            f[nmu - 1] * 0.5 * (1.0 - m1 * m1);
         const double is = 2.0 * Num<double>::pi * tot;
-        istar[pb] = is;
-        inv_istar[pb] = 1.0 / is;
+        *istar = is;
+        *inv_istar = 1.0 / is;
     }
+}
+
+// One workgroup (kBlock threads) per passband.
+__global__ __launch_bounds__(kBlock) void k_istar(const double* __restrict__ mu_s,
+                                                  const double* __restrict__ prof, int32_t nmu,
+                                                  double* __restrict__ istar,
+                                                  double* __restrict__ inv_istar) {
+    const int pb = blockIdx.x;
+    istar_block(mu_s, prof + int64_t(pb) * nmu, nmu, istar + pb, inv_istar + pb);
 }
 
 __global__ void k_tables(const double* __restrict__ W,
@@ -163,45 +170,129 @@ hipError_t launch_prepare_grid_weights(rr_tables* t, hipStream_t s) {
     return hipGetLastError();
 }
 
-// Per-vector LD vector: ldw[r][m] = (1 - ak) sum_j W[ik][j][m] ldp[r][j]
-// + ak sum_j W[ik+1][j][m] ldp[r][j] for r = (vector, passband), the same
-// T = W . l contraction as k_tables restricted to the two k-rows around the
-// vector's k (Sect. 3.1.2), summed over bins in order in FP64.  Workgroup
-// (r, x): 256 consecutive m; the vector's ldp row is staged in LDS.  The
-// result goes out twice ([2][ng]) in the evaluation precision.
+// Per-vector LD rows.  Row r = (vector, passband) needs the two table rows
+// T_r[s][m] = sum_j W[ik_r + s][j][m] ldp[r][j], s = 0, 1, around its k
+// (Sect. 3.1.2: T = W . l, then the k-interpolation in the forward kernel).
+// k_pv_prep sorts the rows by ik (counting sort in one workgroup; the order
+// within a bin is arbitrary and does not affect any result), so that the
+// rows with equal ik are handled one after another (k_pv_tables below).
+// Sums run over bins in order in FP64, the same order as k_tables, so a
+// vector with the tables' own profile gets exactly the shared rows.
+// Counting sort of the rows by ik, by one workgroup of kBlock threads
+// (thread t owns bins 16 t .. 16 t + 15 of at most 4096).
+__device__ inline void sort_rows(const double* __restrict__ pv, int32_t npv, int32_t npar,
+                                 const GridDev& g, int32_t* __restrict__ ikr,
+                                 int32_t* __restrict__ perm) {
+    constexpr int kPer = 4096 / kBlock;
+    __shared__ int cnt[4096];
+    __shared__ int wsum[kBlock / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t n = int64_t(npv) * g.npb;
+    for (int b = tid; b < g.nk; b += kBlock) cnt[b] = 0;
+    __syncthreads();
+    for (int64_t r = tid; r < n; r += kBlock) {
+        const int64_t ipv = r / g.npb;
+        const int pb = int(r - ipv * g.npb);
+        const double u = (pv[ipv * npar + 6 + pb] - g.k0) / g.dk;
+        double uf = floor(u);
+        if (!(uf >= 0.0)) uf = 0.0;              // also a non-finite k (NaN row anyway)
+        if (uf > g.nk - 2) uf = g.nk - 2;
+        const int ik = int(uf);
+        ikr[r] = ik;
+        atomicAdd(&cnt[ik], 1);
+    }
+    __syncthreads();
+    int v[kPer], local = 0;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int b = kPer * tid + q;
+        v[q] = b < g.nk ? cnt[b] : 0;
+        local += v[q];
+    }
+    int x = local;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[wave] = x;
+    __syncthreads();
+    int excl = x - local;
+    for (int w = 0; w < wave; ++w) excl += wsum[w];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int b = kPer * tid + q;
+        if (b < g.nk) cnt[b] = excl;
+        excl += v[q];
+    }
+    __syncthreads();
+    for (int64_t r = tid; r < n; r += kBlock) perm[atomicAdd(&cnt[ikr[r]], 1)] = int32_t(r);
+}
+
+// One launch for the per-vector preparation: workgroup r < nr interpolates
+// row r's profile to the bin means and integrates its I_star (the table
+// kernels' arithmetic); workgroup nr sorts the rows by ik.
+__global__ __launch_bounds__(kBlock) void k_pv_prep(const double* __restrict__ mu_s,
+                                                    const double* __restrict__ prof,
+                                                    int32_t nmu, const double* __restrict__ zm,
+                                                    int32_t nz, const double* __restrict__ pv,
+                                                    int32_t npv, int32_t npar, GridDev g,
+                                                    double* __restrict__ ldp,
+                                                    double* __restrict__ istar,
+                                                    double* __restrict__ inv_istar,
+                                                    int32_t* __restrict__ ikr,
+                                                    int32_t* __restrict__ perm) {
+    const int64_t nr = int64_t(npv) * g.npb;
+    const int64_t r = blockIdx.x;
+    if (r == nr) {
+        sort_rows(pv, npv, npar, g, ikr, perm);
+        return;
+    }
+    const double* f = prof + r * nmu;
+    for (int j = threadIdx.x; j < nz; j += kBlock) ldp[r * nz + j] = profile_at_bin(mu_s, f, nmu, zm[j]);
+    istar_block(mu_s, f, nmu, istar + r, inv_istar + r);
+}
+
+// One workgroup per (row, 256 m), rows taken in sorted order, with an
+// XCD-aware block order: blocks go round-robin to the eight XCDs, so block
+// p works on sorted item (p mod 8) * (blocks / 8) + p / 8 (rounded for a
+// remainder) and each XCD walks a contiguous stretch of the sorted rows,
+// whose W rows its L2 then serves to the following rows of equal ik.
+constexpr int kXcds = 8;
 template <typename R>
-__global__ void k_pv_ldw(const double* __restrict__ W, const double* __restrict__ ldp,
-                         const double* __restrict__ pv, int32_t npar, int32_t nz, GridDev g,
-                         R* __restrict__ ldw) {
+__global__ __launch_bounds__(kBlock) void k_pv_tables(const double* __restrict__ W,
+                                                      const double* __restrict__ ldp,
+                                                      const int32_t* __restrict__ ikr,
+                                                      const int32_t* __restrict__ perm,
+                                                      int32_t nz, GridDev g,
+                                                      R* __restrict__ out) {
     __shared__ double lp[4096];
+    const int64_t nb = gridDim.x, p = blockIdx.x;
+    const int64_t q = nb / kXcds, rem = nb % kXcds;
+    const int64_t x = p % kXcds;
+    const int64_t L = (x < rem ? x * (q + 1) : rem * (q + 1) + (x - rem) * q) + p / kXcds;
     const int nmb = (g.ng + kBlock - 1) / kBlock;
-    const int64_t r = int64_t(blockIdx.x) / nmb;
-    const int mb = int(int64_t(blockIdx.x) - r * nmb);
-    const int64_t ipv = r / g.npb;
-    const int pb = int(r - ipv * g.npb);
+    const int64_t pos = L / nmb;
+    const int mb = int(L - pos * nmb);
+    const int64_t r = perm[pos];
+    const int ik = ikr[r];
     for (int j = threadIdx.x; j < nz; j += kBlock) lp[j] = ldp[r * nz + j];
     __syncthreads();
     const int m = mb * kBlock + int(threadIdx.x);
     if (m >= g.ng) return;
-    const double u = (pv[ipv * npar + 6 + pb] - g.k0) / g.dk;
-    double uf = floor(u);
-    if (!(uf >= 0.0)) uf = 0.0;                  // also a non-finite k (row is NaN anyway)
-    if (uf > g.nk - 2) uf = g.nk - 2;
-    const int ik = int(uf);
-    const double ak = u - ik;
     const double* w0 = W + int64_t(ik) * nz * g.ng + m;
     const double* w1 = w0 + int64_t(nz) * g.ng;
     double a0 = 0.0, a1 = 0.0;
     int j = 0;
-    for (; j + 4 <= nz; j += 4) {                 // four bins' loads in flight
-        double x0[4], x1[4];
+    for (; j + 8 <= nz; j += 8) {                 // sixteen loads in flight
+        double x0[8], x1[8];
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
+        for (int b = 0; b < 8; ++b) {
             x0[b] = w0[int64_t(j + b) * g.ng];
             x1[b] = w1[int64_t(j + b) * g.ng];
         }
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
+        for (int b = 0; b < 8; ++b) {
             a0 += x0[b] * lp[j + b];
             a1 += x1[b] * lp[j + b];
         }
@@ -210,32 +301,28 @@ __global__ void k_pv_ldw(const double* __restrict__ W, const double* __restrict_
         a0 += w0[int64_t(j) * g.ng] * lp[j];
         a1 += w1[int64_t(j) * g.ng] * lp[j];
     }
-    const R v = R((1.0 - ak) * a0 + ak * a1);
-    R* o = ldw + r * 2 * g.ng;
-    o[m] = v;
-    o[g.ng + m] = v;
+    R* o = out + r * 2 * g.ng;
+    o[m] = R(a0);
+    o[g.ng + m] = R(a1);
 }
 
 hipError_t launch_pv_ld(const rr_tables* t, const double* prof, const double* pv,
                         int32_t npv, int32_t npar, int32_t precision, double* ldp,
-                        double* istar, double* inv_istar, void* ldw, hipStream_t s) {
+                        double* istar, double* inv_istar, int32_t* ikr, int32_t* perm,
+                        void* rows, hipStream_t s) {
     const GridDev g = grid_dev(t);
     const int64_t nr = int64_t(npv) * t->npb;     // (vector, passband) rows
-    // the table kernels with every (vector, passband) as one profile
-    hipLaunchKernelGGL(k_profile, dim3(nblocks(int64_t(t->nz) * nr)), dim3(kBlock), 0, s,
-                       t->mu_s, prof, t->nmu, t->zm, t->nz, int32_t(nr), ldp);
-    hipLaunchKernelGGL(k_istar, dim3(unsigned(nr)), dim3(kBlock), 0, s, t->mu_s, prof, t->nmu,
-                       istar, inv_istar);
+    hipLaunchKernelGGL(k_pv_prep, dim3(unsigned(nr + 1)), dim3(kBlock), 0, s, t->mu_s, prof,
+                       t->nmu, t->zm, t->nz, pv, npv, npar, g, ldp, istar, inv_istar, ikr, perm);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int nmb = (g.ng + kBlock - 1) / kBlock;
-    const dim3 grid(unsigned(nr * nmb));
+    const dim3 grid(unsigned(nr * ((g.ng + kBlock - 1) / kBlock)));
     if (precision == RR_FP64)
-        hipLaunchKernelGGL(k_pv_ldw<double>, grid, dim3(kBlock), 0, s, t->W, ldp, pv, npar,
-                           t->nz, g, static_cast<double*>(ldw));
+        hipLaunchKernelGGL(k_pv_tables<double>, grid, dim3(kBlock), 0, s, t->W, ldp, ikr, perm,
+                           t->nz, g, static_cast<double*>(rows));
     else
-        hipLaunchKernelGGL(k_pv_ldw<float>, grid, dim3(kBlock), 0, s, t->W, ldp, pv, npar,
-                           t->nz, g, static_cast<float*>(ldw));
+        hipLaunchKernelGGL(k_pv_tables<float>, grid, dim3(kBlock), 0, s, t->W, ldp, ikr, perm,
+                           t->nz, g, static_cast<float*>(rows));
     return hipGetLastError();
 }
 
