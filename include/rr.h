@@ -17,6 +17,7 @@
  *                   g-interpolation x lens area -> supersample mean;
  *   rr_evaluate_ld  the same with a limb-darkening profile per parameter
  *                   vector (LD sampled with the orbit);
+ *   rr_flux_at_z    Eq. 5 at given separations and radius ratios;
  *   rr_loglik_grad  Gaussian log-likelihood of observed fluxes and its
  *                   gradient with respect to every parameter and to the
  *                   LD profile samples (hand-written adjoint);
@@ -146,6 +147,19 @@ RR_API int rr_evaluate(const rr_tables* t, const double* times_d,
                        const double* exptimes, int32_t nlc,
                        const double* pv_d, int32_t npv, int32_t npar,
                        int32_t precision, void* out_d, hipStream_t stream);
+
+/* The model as a function of the separation: out_d[i] = Eq. 5 for a planet
+ * in front of the star at separation z_d[i] (in stellar radii) with radius
+ * ratio k_d[i] (or the scalar k when k_d is NULL), passband pb of the
+ * tables -- the k- and g-interpolated LD vector times the lens area over
+ * I_star (Sect. 3.1.1, Sect. 3.1.2), without orbit or supersampling.
+ * z_d, k_d: device FP64 arrays of n values; out_d: device double[n]
+ * (RR_FP64) or float[n] (RR_MIXED).  A k outside [k0, k1] or a z that is
+ * negative or not finite gives NaN for that point.  n >= 0 (zero enqueues
+ * nothing); errors as rr_evaluate.  No temporary memory. */
+RR_API int rr_flux_at_z(const rr_tables* t, const double* z_d, const double* k_d,
+                        double k, int64_t n, int32_t pb, int32_t precision, void* out_d,
+                        hipStream_t stream);
 
 /* Fluxes as rr_evaluate, but with a limb-darkening profile of its own for
  * every parameter vector, as when the LD coefficients are sampled together

@@ -176,6 +176,30 @@ def evaluate(tables, series, pv, precision="fp64", out=None, stream=None):
     return out
 
 
+def flux_at_z(tables, z, k, pb=0, precision="fp64", stream=None):
+    """Eq. 5 at separations ``z`` for radius ratio ``k`` (a scalar or one per
+    separation), planet in front of the star (rr_flux_at_z).  Returns a
+    device tensor shaped like ``z``."""
+    prec = PRECISIONS[precision]
+    z = _dev(z, torch.float64)
+    kd = None
+    if isinstance(k, (int, float)):
+        kc = float(k)
+    else:
+        kd = _dev(k, torch.float64)
+        if kd.numel() != z.numel():
+            raise ValueError("k must be a scalar or have one value per separation")
+        kc = 0.0
+    out = torch.empty(z.shape, dtype=torch.float64 if prec == RR_FP64 else torch.float32,
+                      device=z.device)
+    check(_lib.lib().rr_flux_at_z(tables.handle, ctypes.c_void_p(z.data_ptr()),
+                                  ctypes.c_void_p(kd.data_ptr()) if kd is not None else None,
+                                  kc, z.numel(), int(pb), prec,
+                                  ctypes.c_void_p(out.data_ptr()), _stream(stream)),
+          "rr_flux_at_z")
+    return out
+
+
 def evaluate_ld(tables, series, pv, prof, precision="fp64", out=None, stream=None):
     """Fluxes (npv, npt) with a limb-darkening profile per parameter row
     (rr_evaluate_ld).  ``prof`` holds the radial profile samples of every

@@ -267,6 +267,23 @@ RR_API int rr_evaluate(const rr_tables* t, const double* times_d,
     return RR_OK;
 }
 
+RR_API int rr_flux_at_z(const rr_tables* t, const double* z_d, const double* k_d,
+                        double k, int64_t n, int32_t pb, int32_t precision, void* out_d,
+                        hipStream_t stream) {
+    if (!t) return einval("tables handle is NULL");
+    if (n < 0) return einval("n must be >= 0");
+    if (n >= (int64_t(1) << 40)) return elimit("n too large");
+    if (pb < 0 || pb >= t->npb) return einval("pb out of range");
+    if (precision != RR_FP64 && precision != RR_MIXED) return einval("unknown precision");
+    if (n == 0) return RR_OK;
+    if (!z_d || !out_d) return einval("z and out are required");
+    int rc = check_device(t);
+    if (rc) return rc;
+    hipError_t e = launch_flux_at_z(t, z_d, k_d, k, n, pb, precision, out_d, stream);
+    if (e != hipSuccess) return hip_fail(e, "flux kernel");
+    return RR_OK;
+}
+
 RR_API int rr_evaluate_ld(const rr_tables* t, const double* times_d,
                           const int32_t* lcids_d, int32_t npt,
                           const int32_t* pbids, const int32_t* nss,

@@ -81,6 +81,24 @@ __device__ inline PbConst<R> pb_const(const double* __restrict__ pv, int ipv, in
     return c;
 }
 
+// Eq. 5 without the leading 1 at separation z for a planet in front of the
+// star: zero without overlap, else the LD vector interpolated in k and g
+// from the two table rows (Sect. 3.1.1, Sect. 3.1.2) times the lens area
+// over I_star.
+template <typename R>
+__device__ inline R occulted_at(R z, const PbConst<R>& c, const GridDev& g) {
+    if (!(z < c.onepk)) return R(0);
+    const R v = z * c.inv1pk * R(g.gscale);
+    int m = int(v);
+    m = m > g.ng - 2 ? g.ng - 2 : m;
+    const R al = v - R(m);
+    const R* t0r = c.t0r;
+    const R l0 = (R(1) - c.ak) * t0r[m] + c.ak * t0r[g.ng + m];
+    const R l1 = (R(1) - c.ak) * t0r[m + 1] + c.ak * t0r[g.ng + m + 1];
+    const R ip = (R(1) - al) * l0 + al * l1;
+    return ip * lens_area<R>(R(1), c.k, z) * c.istar_inv;
+}
+
 // Occulted fraction of subsample s of an exposure at mid-time t (the term
 // of Eq. 5 after the leading 1): the orbit (z), the LD vector interpolated
 // in k and g from the resident table (Sect. 3.1.1, Sect. 3.1.2) and the lens
@@ -95,16 +113,8 @@ __device__ inline R subsample_delta(const PvConst& p, const OrbitR<R>& orb,
     const double dt = x - p.P * rint(u);
     bool front;
     const R z = separation<R>(R(dt), orb, &front);
-    if (!front || !(z < c.onepk)) return R(0);
-    const R v = z * c.inv1pk * R(g.gscale);
-    int m = int(v);
-    m = m > g.ng - 2 ? g.ng - 2 : m;
-    const R al = v - R(m);
-    const R* t0r = c.t0r;
-    const R l0 = (R(1) - c.ak) * t0r[m] + c.ak * t0r[g.ng + m];
-    const R l1 = (R(1) - c.ak) * t0r[m + 1] + c.ak * t0r[g.ng + m + 1];
-    const R ip = (R(1) - al) * l0 + al * l1;
-    return ip * lens_area<R>(R(1), c.k, z) * c.istar_inv;
+    if (!front) return R(0);
+    return occulted_at<R>(z, c, g);
 }
 
 // Flux of one exposure: 1 - mean over its nss subsamples (Sect. 4.1),
@@ -350,6 +360,36 @@ __global__ __launch_bounds__(kFwdBlock) void k_forward_jobs(JobTable jt, GridDev
     forward_block<R, kSubPar>(job, *job.lc, ipv, tile, g, T, inv_istar);
 }
 
+// Eq. 5 at given separations (the model as a function of z and k, the
+// form of the paper's listings): out[i] = 1 - occulted_at(z_i) for passband
+// pb with k = kv[i] (or kconst); NaN for a k outside the table or a z that
+// is negative or not finite.
+template <typename R>
+__global__ void k_flux_at_z(const double* __restrict__ z, const double* __restrict__ kv,
+                            double kconst, int64_t n, int32_t pb, GridDev g, double k1,
+                            const R* __restrict__ T, const double* __restrict__ inv_istar,
+                            R* __restrict__ out) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double k = kv ? kv[i] : kconst;
+    const double zi = z[i];
+    if (!(k >= g.k0 && k <= k1) || !(zi >= 0.0) || !is_finite(zi)) {
+        out[i] = R(NAN);
+        return;
+    }
+    PbConst<R> c;
+    const double u = (k - g.k0) / g.dk;
+    int ik = int(floor(u));
+    ik = ik < 0 ? 0 : (ik > g.nk - 2 ? g.nk - 2 : ik);
+    c.ak = R(u - ik);
+    c.t0r = T + (int64_t(pb) * g.nk + ik) * g.ng;
+    c.k = R(k);
+    c.onepk = R(1) + c.k;
+    c.inv1pk = R(1) / c.onepk;
+    c.istar_inv = R(inv_istar[pb]);
+    out[i] = R(1) - occulted_at<R>(R(zi), c, g);
+}
+
 __global__ void k_pv_setup_jobs(SetupTable st, double k0, double k1) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     int jj = 0;
@@ -434,6 +474,21 @@ hipError_t launch_forward_jobs(const rr_tables* t, const JobTable& jt, int32_t n
             hipLaunchKernelGGL((k_forward_jobs<float, false>), grid, dim3(kFwdBlock), 0, s, jt, g,
                                t->T32, t->inv_istar);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_flux_at_z(const rr_tables* t, const double* z, const double* kv,
+                           double kconst, int64_t n, int32_t pb, int32_t precision, void* out,
+                           hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const GridDev g = grid_dev(t);
+    const dim3 grid(unsigned((n + kBlock - 1) / kBlock));
+    if (precision == RR_FP64)
+        hipLaunchKernelGGL(k_flux_at_z<double>, grid, dim3(kBlock), 0, s, z, kv, kconst, n, pb,
+                           g, t->grid.k1, t->T64, t->inv_istar, static_cast<double*>(out));
+    else
+        hipLaunchKernelGGL(k_flux_at_z<float>, grid, dim3(kBlock), 0, s, z, kv, kconst, n, pb,
+                           g, t->grid.k1, t->T32, t->inv_istar, static_cast<float*>(out));
     return hipGetLastError();
 }
 

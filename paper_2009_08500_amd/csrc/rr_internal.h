@@ -204,6 +204,10 @@ hipError_t launch_forward(const rr_tables* t, const double* times,
                           const PvConst* pvc, int32_t precision, void* out,
                           hipStream_t s, const void* ldw_pv = nullptr,
                           const double* inv_istar_pv = nullptr);
+// Eq. 5 at separations z[n] (rr_flux_at_z); kv[n] or, if NULL, kconst.
+hipError_t launch_flux_at_z(const rr_tables* t, const double* z, const double* kv,
+                           double kconst, int64_t n, int32_t pb, int32_t precision, void* out,
+                           hipStream_t s);
 // Per-vector LD (rr_evaluate_ld): from prof[npv][npb][nmu] on the tables'
 // mu samples, the profile at the bin means (ldp, [npv][npb][nz]), I_star and
 // 1/I_star ([npv][npb]) and the vector's own two table rows around its k
