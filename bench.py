@@ -261,6 +261,46 @@ def per_vector_ld_leg(rr, wl, steps, warmup, lib):
     return res
 
 
+def direct_leg(rr, wl, steps, warmup):
+    """The population (512 x 20 000, nss 1) through the direct model
+    (rr_evaluate_direct: weights for each row's own k): points/s and
+    per-call latency for both precisions, and the error of eight sampled
+    rows against the oracle's direct model."""
+    import numpy as np
+    import torch
+    from oracle import roadrunner as orr
+    w = wl.population()
+    grid = wl.DEFAULT_GRID
+    tab = rr.Tables(w["mu_s"], w["I_s"], grid)
+    ser = rr.TimeSeries(w["times"])
+    pv = torch.as_tensor(w["pv"], device="cuda")
+    npv, npt = pv.shape[0], int(w["times"].size)
+    res = dict(workload=f"population through the direct model: npv={npv} npt={npt} nss=1",
+               npv=npv, npt=npt)
+    outs = {}
+    for prec in ("mixed", "fp64"):
+        dtype = torch.float64 if prec == "fp64" else torch.float32
+        out = torch.empty((npv, npt), dtype=dtype, device="cuda")
+        for _ in range(warmup):
+            rr.evaluate_direct(tab, ser, pv, prec, out=out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            rr.evaluate_direct(tab, ser, pv, prec, out=out)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / steps
+        res[prec] = dict(points_per_s=npv * npt / (ms / 1e3), ms_per_step=ms)
+        outs[prec] = out.cpu().numpy().astype(np.float64)
+    rows = np.random.default_rng(10).choice(npv, 8, replace=False)
+    otab = orr.Tables(w["mu_s"], w["I_s"], **grid)
+    ref = orr.evaluate_direct(otab, w["times"], w["pv"][rows])
+    res["accuracy_vs_oracle"] = dict(
+        rows_checked=len(rows),
+        max_abs_err_fp64=float(np.abs(outs["fp64"][rows] - ref).max()),
+        max_abs_err_mixed_ppm=float(np.abs(outs["mixed"][rows] - ref).max()) * 1e6)
+    return res
+
+
 def loglik_leg(rr, wl, steps, warmup):
     """Gaussian log-likelihood and its adjoint for 1024 walkers around a truth
     vector, 50 000 times at 2-min cadence with nss = 5 (data = the oracle's
@@ -488,6 +528,7 @@ def main():
     if not args.no_extra:
         line["heterogeneous"] = heterogeneous_leg(rr, wl, min(args.steps, 50), 5, lib)
         line["per_vector_ld"] = per_vector_ld_leg(rr, wl, min(args.steps, 50), 5, lib)
+        line["direct_model"] = direct_leg(rr, wl, min(args.steps, 20), 2)
         line["loglik_grad"] = loglik_leg(rr, wl, 10, 2)
     if not args.no_cpu_baseline:
         cb, acc = cpu_baseline(w, grid, args.cpu_seconds, o64, o32)

@@ -17,6 +17,8 @@
  *                   g-interpolation x lens area -> supersample mean;
  *   rr_evaluate_ld  the same with a limb-darkening profile per parameter
  *                   vector (LD sampled with the orbit);
+ *   rr_evaluate_direct  the direct model: weights for each vector's own k,
+ *                   no k-interpolation and no k limits (Sect. 3.1.1);
  *   rr_flux_at_z    Eq. 5 at given separations and radius ratios;
  *   rr_loglik_grad  Gaussian log-likelihood of observed fluxes and its
  *                   gradient with respect to every parameter and to the
@@ -147,6 +149,24 @@ RR_API int rr_evaluate(const rr_tables* t, const double* times_d,
                        const double* exptimes, int32_t nlc,
                        const double* pv_d, int32_t npv, int32_t npar,
                        int32_t precision, void* out_d, hipStream_t stream);
+
+/* The direct model (Sect. 3.1.1): fluxes as rr_evaluate, but every
+ * (vector, passband) gets the LD-weighted vector built from annulus weights
+ * for its own k instead of interpolating the tables in k, so k is not
+ * limited to the tables' [k0, k1] (any k in (0, 1]) and carries no
+ * k-interpolation error; the tables' z-grid, profile and I_star are used.
+ * Costs ng (nz + 1) lens areas per vector and passband (about 0.5 ms for
+ * 512 vectors at the default grid) before the forward kernel.  Arguments,
+ * errors and invalid rows as rr_evaluate, except that the k limits are
+ * (0, 1].  A k on a table node gives that node's row of the tables.
+ * Temporary device memory (144 + 2 npb ng sizeof(real) bytes per vector)
+ * is the per-stream buffer that rr_evaluate uses. */
+RR_API int rr_evaluate_direct(const rr_tables* t, const double* times_d,
+                              const int32_t* lcids_d, int32_t npt,
+                              const int32_t* pbids, const int32_t* nss,
+                              const double* exptimes, int32_t nlc,
+                              const double* pv_d, int32_t npv, int32_t npar,
+                              int32_t precision, void* out_d, hipStream_t stream);
 
 /* The model as a function of the separation: out_d[i] = Eq. 5 for a planet
  * in front of the star at separation z_d[i] (in stellar radii) with radius

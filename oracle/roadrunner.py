@@ -172,12 +172,16 @@ def occulted(tab, pb, k, z, front):
     the leading 1), zero when the planet is behind the star or the disks do
     not overlap.  g-interpolation as in Sect. 3.1.1, index clamped to
     ng - 2."""
+    return occulted_with(tab, ldw_for_k(tab, pb, k), pb, k, z, front)
+
+
+def occulted_with(tab, ldw, pb, k, z, front):
+    """``occulted`` for a given LD-weighted vector ldw over g."""
     z = np.asarray(z, float)
     delta = np.zeros(z.shape)
     hit = front & (z < 1.0 + k)
     if not hit.any():
         return delta
-    ldw = ldw_for_k(tab, pb, k)
     zz = z[hit]
     v = (zz / (1.0 + k)) / tab.dg
     m = np.minimum(np.floor(v).astype(np.int64), tab.ng - 2)
@@ -277,4 +281,72 @@ def evaluate_ld(tab, times, pv, prof, lcids=None, pbids=None, nss=None, exptimes
     for i in range(pv.shape[0]):
         out[i] = evaluate(with_profile(tab, prof[i]), times, pv[i:i + 1], lcids=lcids,
                           pbids=pbids, nss=nss, exptimes=exptimes)[0]
+    return out
+
+
+# ------------------------------------------------------------ direct model
+def weights_for_k(ze, k, ng):
+    """The direct model's weights W[ng][nz] for one radius ratio k: the
+    formula of ``weights_3d`` at that k alone, so no k-grid, no
+    k-interpolation and no k limits (Sect. 3.1.1)."""
+    nz = ze.size - 1
+    g = np.arange(ng) / (ng - 1.0)
+    c = g * (1.0 + k)
+    A = lens_area(ze[None, :], k, c[:, None])
+    total = A[:, -1]
+    W = np.zeros((ng, nz))
+    ok = total > 0.0
+    W[ok] = np.diff(A, axis=-1)[ok] / total[ok][:, None]
+    W[~ok, nz - 1] = 1.0
+    return W
+
+
+def pv_is_valid_direct(row):
+    """Physical parameter vector for the direct model: any k in (0, 1]."""
+    ks = row[NPAR_ORBIT:]
+    if not np.all(np.isfinite(row)):
+        return False
+    t0, P, a, b, e, w = row[:NPAR_ORBIT]
+    if not (P > 0.0 and a > 0.0 and b >= 0.0 and 0.0 <= e < 1.0):
+        return False
+    if np.any(ks <= 0.0) or np.any(ks > 1.0):
+        return False
+    return abs(_orbit.cos_inclination(a, b, e, w)) <= 1.0
+
+
+def evaluate_direct(tab, times, pv, lcids=None, pbids=None, nss=None, exptimes=None):
+    """Fluxes of the direct model (Sect. 3.1.1): as ``evaluate``, but each
+    row's LD-weighted vector comes from weights built for its own k
+    (``weights_for_k``) and the tables' profile at the bin means, with no
+    interpolation in k."""
+    times = np.asarray(times, float)
+    pv = np.atleast_2d(np.asarray(pv, float))
+    npt = times.size
+    lcids = np.zeros(npt, np.int64) if lcids is None else np.asarray(lcids)
+    if pbids is None:
+        nlc = int(lcids.max()) + 1 if npt else 1
+        pbids = np.zeros(nlc, np.int64)
+    else:
+        pbids = np.asarray(pbids)
+        nlc = pbids.size
+    nss = np.ones(nlc, np.int64) if nss is None else np.broadcast_to(nss, (nlc,))
+    exptimes = (np.zeros(nlc) if exptimes is None
+                else np.broadcast_to(np.asarray(exptimes, float), (nlc,)))
+    out = np.empty((pv.shape[0], npt))
+    for ipv, row in enumerate(pv):
+        if not pv_is_valid_direct(row):
+            out[ipv] = np.nan
+            continue
+        t0, P, a, b, e, w = row[:NPAR_ORBIT]
+        for lc in range(nlc):
+            sel = np.nonzero(lcids == lc)[0]
+            if sel.size == 0:
+                continue
+            pb = int(pbids[lc])
+            k = row[NPAR_ORBIT + pb]
+            ldw = weights_for_k(tab.ze, k, tab.ng) @ tab.ldp[pb]
+            ts = _orbit.subsample_times(times[sel], int(nss[lc]), exptimes[lc])
+            dt = _orbit.phase_offset(ts, t0, P)
+            z, front, _ = _orbit.projected_separation(dt, P, a, b, e, w)
+            out[ipv, sel] = 1.0 - occulted_with(tab, ldw, pb, k, z, front).mean(axis=1)
     return out

@@ -176,6 +176,31 @@ def evaluate(tables, series, pv, precision="fp64", out=None, stream=None):
     return out
 
 
+def evaluate_direct(tables, series, pv, precision="fp64", out=None, stream=None):
+    """Fluxes of the direct model (rr_evaluate_direct): weights built for
+    each row's own k, no k-interpolation, any k in (0, 1].  Arguments and
+    result as ``evaluate``."""
+    prec = PRECISIONS[precision]
+    if not isinstance(series, TimeSeries):
+        series = TimeSeries(series)
+    pv = _dev(pv, torch.float64)
+    if pv.dim() == 1:
+        pv = pv.unsqueeze(0)
+    npv, npar = pv.shape
+    dtype = torch.float64 if prec == RR_FP64 else torch.float32
+    if out is None:
+        out = torch.empty((npv, series.npt), dtype=dtype, device=pv.device)
+    elif out.dtype != dtype or not out.is_contiguous() or out.numel() != npv * series.npt:
+        raise ValueError("out has the wrong dtype, layout or size")
+    lc, npt, pb, nss, ex, nlc = series.lc_args()
+    check(_lib.lib().rr_evaluate_direct(tables.handle, ctypes.c_void_p(series.times.data_ptr()),
+                                        lc, npt, pb, nss, ex, nlc,
+                                        ctypes.c_void_p(pv.data_ptr()), npv, npar, prec,
+                                        ctypes.c_void_p(out.data_ptr()), _stream(stream)),
+          "rr_evaluate_direct")
+    return out
+
+
 def flux_at_z(tables, z, k, pb=0, precision="fp64", stream=None):
     """Eq. 5 at separations ``z`` for radius ratio ``k`` (a scalar or one per
     separation), planet in front of the star (rr_flux_at_z).  Returns a

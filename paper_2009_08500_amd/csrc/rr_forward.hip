@@ -56,17 +56,23 @@ __device__ inline PbConst<R> pb_const(const double* __restrict__ pv, int ipv, in
     const double kd = pv[int64_t(ipv) * npar + 6 + pb];
     if (job.ldw_pv) {
         // per-vector LD: the vector's own copies of the two table rows
-        // around its k, interpolated in k below as the shared rows are
+        // around its k, interpolated in k below as the shared rows are; or
+        // (direct model) its LD vector for its exact k, stored twice and
+        // read with zero k-weight
         const int64_t r = int64_t(ipv) * g.npb + pb;
-        const double u = (kd - g.k0) / g.dk;
-        int ik = int(floor(u));
-        ik = ik < 0 ? 0 : (ik > g.nk - 2 ? g.nk - 2 : ik);
-        c.ak = R(u - ik);
+        if (job.ldw_exact_k) {
+            c.ak = R(0);
+        } else {
+            const double u = (kd - g.k0) / g.dk;
+            int ik = int(floor(u));
+            ik = ik < 0 ? 0 : (ik > g.nk - 2 ? g.nk - 2 : ik);
+            c.ak = R(u - ik);
+        }
         c.t0r = static_cast<const R*>(job.ldw_pv) + r * 2 * g.ng;
         c.k = R(kd);
         c.onepk = R(1) + c.k;
         c.inv1pk = R(1) / c.onepk;
-        c.istar_inv = R(job.inv_istar_pv[r]);
+        c.istar_inv = R(job.inv_istar_pv ? job.inv_istar_pv[r] : inv_istar[pb]);
         return c;
     }
     const double u = (kd - g.k0) / g.dk;
@@ -407,8 +413,13 @@ inline unsigned nblocks(int64_t n) { return unsigned((n + kBlock - 1) / kBlock);
 
 hipError_t launch_pv_setup(const rr_tables* t, const double* pv, int32_t npv,
                            int32_t npar, PvConst* pvc, hipStream_t s) {
+    return launch_pv_setup_k(pv, npv, npar, t->grid.k0, t->grid.k1, pvc, s);
+}
+
+hipError_t launch_pv_setup_k(const double* pv, int32_t npv, int32_t npar, double k_lo,
+                             double k_hi, PvConst* pvc, hipStream_t s) {
     hipLaunchKernelGGL(k_pv_setup, dim3(nblocks(npv)), dim3(kBlock), 0, s, pv, npv,
-                       npar, t->grid.k0, t->grid.k1, pvc);
+                       npar, k_lo, k_hi, pvc);
     return hipGetLastError();
 }
 
@@ -416,10 +427,11 @@ hipError_t launch_forward(const rr_tables* t, const double* times,
                           const int32_t* lcids, int32_t npt, const LcInfo& lc,
                           const double* pv, int32_t npv, int32_t npar,
                           const PvConst* pvc, int32_t precision, void* out,
-                          hipStream_t s, const void* ldw_pv, const double* inv_istar_pv) {
+                          hipStream_t s, const void* ldw_pv, const double* inv_istar_pv,
+                          int32_t ldw_exact_k) {
     const GridDev g = grid_dev(t);
     FwdJob job;
-    job.ldw_pv = ldw_pv; job.inv_istar_pv = inv_istar_pv;
+    job.ldw_pv = ldw_pv; job.inv_istar_pv = inv_istar_pv; job.ldw_exact_k = ldw_exact_k;
     job.times = times; job.lcids = lcids; job.lc = nullptr; job.pv = pv; job.pvc = pvc;
     job.out = out; job.npt = npt; job.npar = npar; job.pv0 = 0; job.npv = npv;
     job.ntiles = (npt + kFwdTile - 1) / kFwdTile; job.block0 = 0; job.max_nss = 1;

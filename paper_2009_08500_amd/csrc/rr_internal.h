@@ -71,7 +71,8 @@ struct FwdJob {
     // vector's own two table rows around its k, [npv][npb][2][ng] in the
     // evaluation precision, and 1/I_star [npv][npb]
     const void* ldw_pv;
-    const double* inv_istar_pv;
+    const double* inv_istar_pv;   // NULL: the tables' 1/I_star
+    int32_t ldw_exact_k;          // 1: ldw_pv rows are for the row's exact k (direct model)
 };
 constexpr int kMaxJobs = 24;   // jobs per grouped launch (kernel arguments)
 struct JobTable {
@@ -174,8 +175,12 @@ rr::GridDev grid_dev(const rr_tables* t);
 // Kernel launchers (rr_prep.hip, rr_forward.hip).
 hipError_t launch_prepare_grid_weights(rr_tables* t, hipStream_t s);
 hipError_t launch_prepare_profile(rr_tables* t, hipStream_t s);
+// Per-row constants; k must lie in [k_lo, k_hi] (the tables' k range by
+// default; the direct model takes (0, 1]).
 hipError_t launch_pv_setup(const rr_tables* t, const double* pv, int32_t npv,
                            int32_t npar, PvConst* pvc, hipStream_t s);
+hipError_t launch_pv_setup_k(const double* pv, int32_t npv, int32_t npar, double k_lo,
+                             double k_hi, PvConst* pvc, hipStream_t s);
 size_t adjoint_lds_bytes(int32_t precision, int32_t npb, int32_t ng);
 hipError_t launch_adjoint(const AdjointArgs& a, int32_t precision, hipStream_t s);
 // Temporaries of the profile gradient.
@@ -203,7 +208,11 @@ hipError_t launch_forward(const rr_tables* t, const double* times,
                           const double* pv, int32_t npv, int32_t npar,
                           const PvConst* pvc, int32_t precision, void* out,
                           hipStream_t s, const void* ldw_pv = nullptr,
-                          const double* inv_istar_pv = nullptr);
+                          const double* inv_istar_pv = nullptr, int32_t ldw_exact_k = 0);
+// Direct model (rr_evaluate_direct): each (vector, passband) row's
+// LD-weighted vector for its own k, rows [npv][npb][2][ng] by precision.
+hipError_t launch_direct_rows(const rr_tables* t, const double* pv, int32_t npv, int32_t npar,
+                              int32_t precision, void* rows, hipStream_t s);
 // Eq. 5 at separations z[n] (rr_flux_at_z); kv[n] or, if NULL, kconst.
 hipError_t launch_flux_at_z(const rr_tables* t, const double* z, const double* kv,
                            double kconst, int64_t n, int32_t pb, int32_t precision, void* out,

@@ -37,6 +37,15 @@ __global__ void k_zgrid(int32_t nzin, int32_t nzlimb, double zcut,
     if (j < nz) zm[j] = 0.5 * (e0 + edge(j + 1));
 }
 
+// Weight of annulus j for radius ratio k with the planet centre at c
+// (Sect. 2): occluded area of the annulus over the total occluded area tot;
+// at zero overlap its limit, all weight in the limb annulus.
+__device__ inline double annulus_weight(const double* __restrict__ ze, int nz, int j,
+                                        double k, double c, double tot) {
+    if (!(tot > 0.0)) return j == nz - 1 ? 1.0 : 0.0;
+    return (lens_area<double>(ze[j + 1], k, c) - lens_area<double>(ze[j], k, c)) / tot;
+}
+
 __global__ void k_weights(const double* __restrict__ ze, GridDev g,
                           double* __restrict__ W) {
     const int64_t total = int64_t(g.nk) * g.nz * g.ng;
@@ -49,16 +58,7 @@ __global__ void k_weights(const double* __restrict__ ze, GridDev g,
     const double k = g.k0 + i * g.dk;
     const double gv = double(m) / double(g.ng - 1);
     const double c = gv * (1.0 + k);
-    const double tot = lens_area<double>(1.0, k, c);
-    double w;
-    if (tot > 0.0) {
-        const double hi = lens_area<double>(ze[j + 1], k, c);
-        const double lo = lens_area<double>(ze[j], k, c);
-        w = (hi - lo) / tot;
-    } else {
-        w = (j == g.nz - 1) ? 1.0 : 0.0;
-    }
-    W[idx] = w;
+    W[idx] = annulus_weight(ze, g.nz, j, k, c, lens_area<double>(1.0, k, c));
 }
 
 // The profile's piecewise-linear interpolant at the mean of bin j.
@@ -304,6 +304,59 @@ __global__ __launch_bounds__(kBlock) void k_pv_tables(const double* __restrict__
     R* o = out + r * 2 * g.ng;
     o[m] = R(a0);
     o[g.ng + m] = R(a1);
+}
+
+// Direct model (Sect. 3.1.1): the LD-weighted vector of row r = (vector,
+// passband) from weights built for the row's own k -- no k-grid, no
+// k-interpolation, any k in (0, 1] -- with the tables' profile at the bin
+// means: ldw_r[m] = sum_j w_j(k, g_m) ldp[pb][j], bins in order, FP64 (the
+// same weights and order as the table, so a k on a table node gives that
+// node's row).  Workgroup (r, 256 m); stored twice ([2][ng]) in the
+// evaluation precision for the forward kernel, which reads it with zero
+// k-weight.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_direct_rows(const double* __restrict__ ze,
+                                                        const double* __restrict__ ldp,
+                                                        const double* __restrict__ pv,
+                                                        int32_t npar, int32_t nz, GridDev g,
+                                                        R* __restrict__ out) {
+    __shared__ double lp[4096];
+    const int nmb = (g.ng + kBlock - 1) / kBlock;
+    const int64_t r = int64_t(blockIdx.x) / nmb;
+    const int mb = int(int64_t(blockIdx.x) - r * nmb);
+    const int64_t ipv = r / g.npb;
+    const int pb = int(r - ipv * g.npb);
+    for (int j = threadIdx.x; j < nz; j += kBlock) lp[j] = ldp[int64_t(pb) * nz + j];
+    __syncthreads();
+    const int m = mb * kBlock + int(threadIdx.x);
+    if (m >= g.ng) return;
+    const double k = pv[ipv * npar + 6 + pb];
+    R* o = out + r * 2 * g.ng;
+    if (!(k > 0.0 && k <= 1.0)) {           // invalid row: the forward writes NaN
+        o[m] = R(0);
+        o[g.ng + m] = R(0);
+        return;
+    }
+    const double c = (double(m) / double(g.ng - 1)) * (1.0 + k);
+    const double tot = lens_area<double>(1.0, k, c);
+    double acc = 0.0;
+    for (int j = 0; j < nz; ++j) acc += annulus_weight(ze, nz, j, k, c, tot) * lp[j];
+    o[m] = R(acc);
+    o[g.ng + m] = R(acc);
+}
+
+hipError_t launch_direct_rows(const rr_tables* t, const double* pv, int32_t npv, int32_t npar,
+                              int32_t precision, void* rows, hipStream_t s) {
+    const GridDev g = grid_dev(t);
+    const int64_t nr = int64_t(npv) * t->npb;
+    const dim3 grid(unsigned(nr * ((g.ng + kBlock - 1) / kBlock)));
+    if (precision == RR_FP64)
+        hipLaunchKernelGGL(k_direct_rows<double>, grid, dim3(kBlock), 0, s, t->ze, t->ldp, pv,
+                           npar, t->nz, g, static_cast<double*>(rows));
+    else
+        hipLaunchKernelGGL(k_direct_rows<float>, grid, dim3(kBlock), 0, s, t->ze, t->ldp, pv,
+                           npar, t->nz, g, static_cast<float*>(rows));
+    return hipGetLastError();
 }
 
 hipError_t launch_pv_ld(const rr_tables* t, const double* prof, const double* pv,
