@@ -23,6 +23,8 @@
  *   rr_loglik_grad  Gaussian log-likelihood of observed fluxes and its
  *                   gradient with respect to every parameter and to the
  *                   LD profile samples (hand-written adjoint);
+ *   rr_loglik_grad_ld  the same with a profile per parameter vector and
+ *                   the gradient with respect to each one;
  *   rr_server_*     a continuous-batching request loop over resident tables.
  *
  * Conventions shared by all entry points
@@ -243,6 +245,27 @@ RR_API int rr_loglik_grad(const rr_tables* t, const double* times_d,
                           int32_t precision, const void* obs_d, double sigma,
                           const double* wprof_d, double* logl_d, double* grad_d,
                           double* grad_prof_d, hipStream_t stream);
+
+/* rr_loglik_grad with a limb-darkening profile per parameter vector (as
+ * rr_evaluate_ld; prof_d[npv][npb][nmu] device FP64 on the tables' mu
+ * samples): logl_d and grad_d as rr_loglik_grad, and grad_prof_d, if not
+ * NULL, a device double[npv][npb][nmu] holding d logl_d[ipv] / d
+ * prof_d[ipv][pb][s] -- each vector's gradient with respect to its own
+ * profile, through the profile at the bin means, I_star and its own two
+ * table rows (the transpose of their contraction with W).  Invalid rows
+ * give NaN in logl and grad and a zero profile gradient.  With every
+ * vector given the tables' own profile, logl and grad equal
+ * rr_loglik_grad's bitwise and the per-vector profile gradients sum to its
+ * shared one (to rounding).  Other arguments, errors and limits as
+ * rr_loglik_grad (no wprof); npv * npb * nz < 2^31. */
+RR_API int rr_loglik_grad_ld(const rr_tables* t, const double* times_d,
+                             const int32_t* lcids_d, int32_t npt,
+                             const int32_t* pbids, const int32_t* nss,
+                             const double* exptimes, int32_t nlc,
+                             const double* pv_d, int32_t npv, int32_t npar,
+                             const double* prof_d, int32_t precision, const void* obs_d,
+                             double sigma, double* logl_d, double* grad_d,
+                             double* grad_prof_d, hipStream_t stream);
 
 /* Instrumentation: the next rr_evaluate / rr_loglik_grad calls made by the
  * calling thread launch their main kernel with `before` and `after` as the

@@ -91,6 +91,11 @@ def _declare(L):
                                      c_void_p, i32, c_void_p, i32, i32, i32, c_void_p, dbl,
                                      c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
         L.rr_loglik_grad.restype = ctypes.c_int
+        L.rr_loglik_grad_ld.argtypes = [c_void_p, c_void_p, c_void_p, i32, c_void_p,
+                                        c_void_p, c_void_p, i32, c_void_p, i32, i32, c_void_p,
+                                        i32, c_void_p, dbl, c_void_p, c_void_p, c_void_p,
+                                        c_void_p]
+        L.rr_loglik_grad_ld.restype = ctypes.c_int
     _ = dbl
 
 

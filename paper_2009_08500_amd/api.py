@@ -323,6 +323,63 @@ def loglik_grad(tables, series, pv, obs, sigma, precision="fp64", grad=True, pro
     return logl, g, gp
 
 
+def loglik_grad_ld(tables, series, pv, prof, obs, sigma, precision="fp64", grad=True,
+                   profile=True, stream=None):
+    """rr_loglik_grad_ld: the log-likelihood with a profile per parameter row
+    ``prof`` (npv, npb, nmu).  Returns (logl[npv], grad[npv, npar] or None,
+    grad_profile[npv, npb, nmu] or None), float64 device tensors;
+    grad_profile[i] is d logl[i] / d prof[i]."""
+    prec = PRECISIONS[precision]
+    if not isinstance(series, TimeSeries):
+        series = TimeSeries(series)
+    pv = _dev(pv, torch.float64)
+    if pv.dim() == 1:
+        pv = pv.unsqueeze(0)
+    npv, npar = pv.shape
+    prof = _dev(prof, torch.float64)
+    if prof.numel() != npv * tables.npb * tables.nmu:
+        raise ValueError("prof must have npv * npb * nmu samples")
+    obs = _dev(obs, torch.float64 if prec == RR_FP64 else torch.float32)
+    if obs.numel() != series.npt:
+        raise ValueError("obs must have one value per time")
+    logl = torch.empty(npv, dtype=torch.float64, device=pv.device)
+    g = torch.empty((npv, npar), dtype=torch.float64, device=pv.device) if grad else None
+    gp = (torch.empty((npv, tables.npb, tables.nmu), dtype=torch.float64, device=pv.device)
+          if profile else None)
+
+    def p(t):
+        return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+    lc, npt, pb, nss, ex, nlc = series.lc_args()
+    check(_lib.lib().rr_loglik_grad_ld(tables.handle, p(series.times), lc, npt, pb, nss, ex,
+                                       nlc, p(pv), npv, npar, p(prof), prec, p(obs),
+                                       float(sigma), p(logl), p(g), p(gp), _stream(stream)),
+          "rr_loglik_grad_ld")
+    return logl, g, gp
+
+
+class RRLogLikLD(torch.autograd.Function):
+    """logL[npv] = rr_loglik_grad_ld(...) as a differentiable function of the
+    parameter rows ``pv`` [npv, npar] and the per-row LD profiles ``prof``
+    [npv, npb, nmu]; backward returns the hand-written adjoint's gradients."""
+
+    @staticmethod
+    def forward(ctx, pv, prof, tables, series, obs, sigma, precision):
+        want_prof = prof.requires_grad
+        logl, g, gp = loglik_grad_ld(tables, series, pv.detach(), prof.detach(), obs, sigma,
+                                     precision, grad=True, profile=want_prof)
+        ctx.save_for_backward(g, gp if gp is not None else torch.empty(0))
+        ctx.want_prof = want_prof
+        return logl
+
+    @staticmethod
+    def backward(ctx, gout):
+        g, gp = ctx.saved_tensors
+        gpv = gout[:, None] * g
+        gprof = gout[:, None, None] * gp if ctx.want_prof else None
+        return gpv, gprof, None, None, None, None, None
+
+
 class RRLogLik(torch.autograd.Function):
     """logL[npv] = rr_loglik_grad(...) as a differentiable function of the
     parameter rows ``pv`` [npv, npar] and the LD profile samples ``profile``

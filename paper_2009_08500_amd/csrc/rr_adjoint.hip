@@ -189,7 +189,8 @@ __global__ __launch_bounds__(kAdjBlock) void k_adjoint(
     const double* __restrict__ inv_istar, const R* __restrict__ obs,
     double inv_sig2, int32_t ntiles, int32_t nparts, int32_t tpp, int32_t want_grad,
     const double* __restrict__ wprof, double* __restrict__ partials,
-    double* __restrict__ seg_gw, double* __restrict__ seg_gi, int32_t* __restrict__ seg_flag) {
+    double* __restrict__ seg_gw, double* __restrict__ seg_gi, int32_t* __restrict__ seg_flag,
+    int32_t rows_per_vector) {
     extern __shared__ unsigned char smem_raw[];
     const int npb = g.npb, ng = g.ng;
     R* ldw = reinterpret_cast<R*>(smem_raw);                    // [npb][ng]
@@ -290,7 +291,9 @@ __global__ __launch_bounds__(kAdjBlock) void k_adjoint(
                 int ik = int(floor(u));
                 ik = ik < 0 ? 0 : (ik > g.nk - 2 ? g.nk - 2 : ik);
                 const R ak = R(u - ik);
-                const R* t0r = T + (int64_t(pb) * g.nk + ik) * ng;
+                // the shared table's two rows, or the vector's own copies
+                const R* t0r = rows_per_vector ? T + (int64_t(ipv) * npb + pb) * 2 * ng
+                                               : T + (int64_t(pb) * g.nk + ik) * ng;
                 ldw[idx] = (R(1) - ak) * t0r[m] + ak * t0r[ng + m];
                 dTk[idx] = (t0r[ng + m] - t0r[m]) * R(g.inv_dk);
                 if (kProf) gw[idx] = 0.0;
@@ -318,7 +321,8 @@ __global__ __launch_bounds__(kAdjBlock) void k_adjoint(
             const R k = R(pv[int64_t(ipv) * npar + 6 + pb]);
             const R onepk = R(1) + k;
             const R inv1pk = R(1) / onepk;
-            const R istar_inv = R(inv_istar[pb]);
+            const R istar_inv =
+                R(inv_istar[rows_per_vector ? int64_t(ipv) * npb + pb : int64_t(pb)]);
             const R* lw = ldw + pb * ng;
             const R* dk_ = dTk + pb * ng;
             R acc = R(0);
@@ -719,6 +723,45 @@ __global__ void k_prof_grad(const double* __restrict__ gldp, const double* __res
 
 inline unsigned nblocks(int64_t n) { return unsigned((n + kBlock - 1) / kBlock); }
 
+// Per-vector LD: dlogL/dldp_r[j] = sum_m (W[ik][j][m] (1 - ak) +
+// W[ik+1][j][m] ak) dlogL/dldw_r[m] for row r = (vector, passband): the
+// transpose of the row's k-interpolated T = W . l.  Workgroup (r, j), a
+// fixed-shape tree over m.
+__global__ __launch_bounds__(kBlock) void k_pv_ldp_grad(const double* __restrict__ W,
+                                                        const double* __restrict__ gldw,
+                                                        const double* __restrict__ pv,
+                                                        int32_t npar, int32_t nz, GridDev g,
+                                                        double* __restrict__ gldp) {
+    __shared__ double part[kBlock];
+    const int64_t b = blockIdx.x;
+    const int64_t r = b / nz;
+    const int j = int(b - r * nz);
+    const int64_t ipv = r / g.npb;
+    const int pb = int(r - ipv * g.npb);
+    const double u = (pv[ipv * npar + 6 + pb] - g.k0) / g.dk;
+    double uf = floor(u);
+    if (!(uf >= 0.0)) uf = 0.0;                  // invalid rows carry zero gldw
+    if (uf > g.nk - 2) uf = g.nk - 2;
+    const int ik = int(uf);
+    const double ak = u - ik;
+    const double* w0 = W + (int64_t(ik) * nz + j) * g.ng;
+    const double* w1 = w0 + int64_t(nz) * g.ng;
+    const double* gr = gldw + r * g.ng;
+    double s = 0.0;
+    for (int m = threadIdx.x; m < g.ng; m += kBlock) {
+        const double gv = gr[m];
+        s += ((1.0 - ak) * w0[m] + ak * w1[m]) * gv;
+    }
+    if (!(ak == ak)) s = 0.0;                    // non-finite k: no contribution
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) gldp[r * nz + j] = part[0];
+}
+
 template <typename R, int NPBT, bool kProf>
 void launch_adjoint_t(const AdjointArgs& A, size_t lds, hipStream_t s, const KernelEvents& ev) {
     // one part per vector: the profile sums are final and go to gldw_pv
@@ -728,7 +771,7 @@ void launch_adjoint_t(const AdjointArgs& A, size_t lds, hipStream_t s, const Ker
                  A.pv, A.npar, A.pvc, A.g, static_cast<const R*>(A.T), A.inv_istar,
                  static_cast<const R*>(A.obs), A.inv_sig2, A.ntiles, A.nparts, A.tpp,
                  A.want_grad, A.wprof, A.partials, one ? A.gldw_pv : A.seg_gw,
-                 one ? A.gist_pv : A.seg_gi, one ? nullptr : A.seg_flag);
+                 one ? A.gist_pv : A.seg_gi, one ? nullptr : A.seg_flag, A.rows_per_vector);
 }
 
 template <typename R>
@@ -775,6 +818,25 @@ hipError_t launch_adjoint(const AdjointArgs& A, int32_t precision, hipStream_t s
     hipLaunchKernelGGL(k_adjoint_reduce, dim3(nblocks(int64_t(A.npv) * (kNq + A.g.npb) * 64)),
                        dim3(kBlock), 0, s, A.partials, A.npv, A.nparts, A.g.npb, A.logl,
                        A.grad);
+    return hipGetLastError();
+}
+
+hipError_t launch_pv_prof_grad(const rr_tables* t, const AdjointArgs& A, double* gldp,
+                               double* out, hipStream_t s) {
+    const GridDev g = A.g;
+    const int64_t nr = int64_t(A.npv) * g.npb;
+    hipLaunchKernelGGL(k_pv_ldp_grad, dim3(unsigned(nr * t->nz)), dim3(kBlock), 0, s, t->W,
+                       A.gldw_pv, A.pv, A.npar, t->nz, g, gldp);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // the shared profile's last step with every (vector, passband) as one
+    // profile: its own dlogL/dldp and dlogL/dI_star
+    for (int64_t r0 = 0; r0 < nr; r0 += 65535) {
+        const int32_t n = int32_t(std::min<int64_t>(65535, nr - r0));
+        hipLaunchKernelGGL(k_prof_grad, dim3(nblocks(t->nmu), unsigned(n)), dim3(kBlock), 0, s,
+                           gldp + r0 * t->nz, A.gist_pv + r0, t->mu_s, t->nmu, t->zm, t->nz, n,
+                           out + r0 * t->nmu);
+    }
     return hipGetLastError();
 }
 

@@ -374,14 +374,18 @@ RR_API int rr_evaluate_ld(const rr_tables* t, const double* times_d,
     return RR_OK;
 }
 
-RR_API int rr_loglik_grad(const rr_tables* t, const double* times_d,
-                          const int32_t* lcids_d, int32_t npt,
-                          const int32_t* pbids, const int32_t* nss,
-                          const double* exptimes, int32_t nlc,
-                          const double* pv_d, int32_t npv, int32_t npar,
-                          int32_t precision, const void* obs_d, double sigma,
-                          const double* wprof_d, double* logl_d, double* grad_d,
-                          double* grad_prof_d, hipStream_t stream) {
+// The log-likelihood and its adjoint; with per_row (per-vector LD) every
+// vector uses its own profile prof_pv_d[npv][npb][nmu] and grad_prof_d is
+// [npv][npb][nmu].
+static int loglik_impl(const rr_tables* t, const double* times_d,
+                       const int32_t* lcids_d, int32_t npt,
+                       const int32_t* pbids, const int32_t* nss,
+                       const double* exptimes, int32_t nlc,
+                       const double* pv_d, int32_t npv, int32_t npar,
+                       int32_t precision, const void* obs_d, double sigma,
+                       const double* wprof_d, double* logl_d, double* grad_d,
+                       double* grad_prof_d, bool per_row, const double* prof_pv_d,
+                       hipStream_t stream) {
     LcInfo lc;
     int rc = check_eval_args(t, times_d, lcids_d, npt, pbids, nss, exptimes, nlc,
                              pv_d, npv, npar, precision, &lc);
@@ -394,8 +398,12 @@ RR_API int rr_loglik_grad(const rr_tables* t, const double* times_d,
     rc = check_device(t);
     if (rc) return rc;
     hipError_t e;
+    const int64_t nr = int64_t(npv) * t->npb;
+    if (per_row && nr * std::max<int64_t>(t->nz, (t->grid.ng + kBlock - 1) / kBlock) >=
+                       (int64_t(1) << 31))
+        return elimit("npv * npb * nz must stay below 2^31");
     if (npv == 0) {
-        if (grad_prof_d) {
+        if (grad_prof_d && !per_row) {
             e = launch_fill(grad_prof_d, int64_t(t->npb) * t->nmu, stream);
             if (e != hipSuccess) return hip_fail(e, "fill");
         }
@@ -425,21 +433,31 @@ RR_API int rr_loglik_grad(const rr_tables* t, const double* times_d,
     const size_t o_part = take(sizeof(double) * size_t(npv) * nseg * nq);
     const size_t o_gldw = prof ? take(sizeof(double) * size_t(npv) * t->npb * g.ng) : 0;
     const size_t o_gist = prof ? take(sizeof(double) * size_t(npv) * t->npb) : 0;
-    const size_t o_gt = prof ? take(sizeof(double) * size_t(t->npb) * g.nk * g.ng) : 0;
-    const size_t o_gldp = prof ? take(sizeof(double) * size_t(t->npb) * t->nz) : 0;
-    const size_t o_ldpp = prof ? take(sizeof(double) * size_t(t->npb) * t->nz * 16) : 0;
-    const size_t o_kidx = prof ? take(sizeof(int32_t) * size_t(npv) * t->npb) : 0;
-    const size_t o_kfrac = prof ? take(sizeof(double) * size_t(npv) * t->npb) : 0;
-    const size_t o_gist_sum = prof ? take(sizeof(double) * size_t(t->npb)) : 0;
+    // shared-profile chain (table gradient) or per-vector LD temporaries
+    const bool shared_prof = prof && !per_row;
+    const size_t elt = precision == RR_FP64 ? sizeof(double) : sizeof(float);
+    const size_t o_ldp = per_row ? take(sizeof(double) * size_t(nr) * t->nz) : 0;
+    const size_t o_isr = per_row ? take(sizeof(double) * size_t(nr)) : 0;
+    const size_t o_iisr = per_row ? take(sizeof(double) * size_t(nr)) : 0;
+    const size_t o_ikr = per_row ? take(sizeof(int32_t) * size_t(nr)) : 0;
+    const size_t o_perm = per_row ? take(sizeof(int32_t) * size_t(nr)) : 0;
+    const size_t o_rows = per_row ? take(elt * size_t(nr) * 2 * g.ng) : 0;
+    const size_t o_gldpr = per_row && prof ? take(sizeof(double) * size_t(nr) * t->nz) : 0;
+    const size_t o_gt = shared_prof ? take(sizeof(double) * size_t(t->npb) * g.nk * g.ng) : 0;
+    const size_t o_gldp = shared_prof ? take(sizeof(double) * size_t(t->npb) * t->nz) : 0;
+    const size_t o_ldpp = shared_prof ? take(sizeof(double) * size_t(t->npb) * t->nz * 16) : 0;
+    const size_t o_kidx = shared_prof ? take(sizeof(int32_t) * size_t(npv) * t->npb) : 0;
+    const size_t o_kfrac = shared_prof ? take(sizeof(double) * size_t(npv) * t->npb) : 0;
+    const size_t o_gist_sum = shared_prof ? take(sizeof(double) * size_t(t->npb)) : 0;
     // table-gradient row chunks: up to 32 rows each, at most 64 chunks and
     // 256 MiB of partial tables
     const size_t table_bytes = sizeof(double) * size_t(t->npb) * g.nk * g.ng;
     int32_t nchunks = std::max<int32_t>(1, std::min<int32_t>(64, (npv + 31) / 32));
     nchunks = int32_t(std::max<size_t>(1, std::min<size_t>(size_t(nchunks),
                                                            (size_t(256) << 20) / table_bytes)));
-    const size_t o_gtp = prof ? take(table_bytes * nchunks) : 0;
-    const size_t o_gtf = prof ? take(sizeof(int32_t) * size_t(nchunks) * t->npb * g.nk) : 0;
-    const size_t o_gtr = prof ? take(sizeof(int32_t) * size_t(t->npb) * g.nk) : 0;
+    const size_t o_gtp = shared_prof ? take(table_bytes * nchunks) : 0;
+    const size_t o_gtf = shared_prof ? take(sizeof(int32_t) * size_t(nchunks) * t->npb * g.nk) : 0;
+    const size_t o_gtr = shared_prof ? take(sizeof(int32_t) * size_t(t->npb) * g.nk) : 0;
     const bool segs = prof && nseg > 1;
     const size_t o_sgw = segs ? take(sizeof(double) * size_t(npv) * nseg * t->npb * g.ng) : 0;
     const size_t o_sgi = segs ? take(sizeof(double) * size_t(npv) * nseg * t->npb) : 0;
@@ -452,6 +470,11 @@ RR_API int rr_loglik_grad(const rr_tables* t, const double* times_d,
     A.npv = npv; A.npar = npar; A.pvc = reinterpret_cast<PvConst*>(base + o_pvc); A.g = g;
     A.T = precision == RR_FP64 ? static_cast<const void*>(t->T64) : static_cast<const void*>(t->T32);
     A.inv_istar = t->inv_istar; A.obs = obs_d; A.inv_sig2 = 1.0 / (sigma * sigma);
+    A.rows_per_vector = per_row ? 1 : 0;
+    if (per_row) {
+        A.T = base + o_rows;
+        A.inv_istar = reinterpret_cast<double*>(base + o_iisr);
+    }
     A.ntiles = ntiles; A.want_grad = grad_d != nullptr; A.want_prof = prof; A.wprof = wprof_d;
     A.partials = reinterpret_cast<double*>(base + o_part);
     A.gldw_pv = prof ? reinterpret_cast<double*>(base + o_gldw) : nullptr;
@@ -463,8 +486,18 @@ RR_API int rr_loglik_grad(const rr_tables* t, const double* times_d,
     A.seg_flag = segs ? reinterpret_cast<int32_t*>(base + o_sfl) : nullptr;
     A.logl = logl_d; A.grad = grad_d;
     e = launch_pv_setup(t, pv_d, npv, npar, const_cast<PvConst*>(A.pvc), stream);
+    if (e == hipSuccess && per_row)
+        e = launch_pv_ld(t, prof_pv_d, pv_d, npv, npar, precision,
+                         reinterpret_cast<double*>(base + o_ldp),
+                         reinterpret_cast<double*>(base + o_isr),
+                         reinterpret_cast<double*>(base + o_iisr),
+                         reinterpret_cast<int32_t*>(base + o_ikr),
+                         reinterpret_cast<int32_t*>(base + o_perm), base + o_rows, stream);
     if (e == hipSuccess) e = launch_adjoint(A, precision, stream);
-    if (e == hipSuccess && prof) {
+    if (e == hipSuccess && prof && per_row)
+        e = launch_pv_prof_grad(t, A, reinterpret_cast<double*>(base + o_gldpr), grad_prof_d,
+                                stream);
+    if (e == hipSuccess && shared_prof) {
         ProfGradScratch w;
         w.kidx = reinterpret_cast<int32_t*>(base + o_kidx);
         w.kfrac = reinterpret_cast<double*>(base + o_kfrac);
@@ -482,6 +515,33 @@ RR_API int rr_loglik_grad(const rr_tables* t, const double* times_d,
     if (e != hipSuccess) return hip_fail(e, "log-likelihood kernels");
     if (ef != hipSuccess) return hip_fail(ef, "hipFreeAsync");
     return RR_OK;
+}
+
+RR_API int rr_loglik_grad(const rr_tables* t, const double* times_d,
+                          const int32_t* lcids_d, int32_t npt,
+                          const int32_t* pbids, const int32_t* nss,
+                          const double* exptimes, int32_t nlc,
+                          const double* pv_d, int32_t npv, int32_t npar,
+                          int32_t precision, const void* obs_d, double sigma,
+                          const double* wprof_d, double* logl_d, double* grad_d,
+                          double* grad_prof_d, hipStream_t stream) {
+    return loglik_impl(t, times_d, lcids_d, npt, pbids, nss, exptimes, nlc, pv_d, npv, npar,
+                       precision, obs_d, sigma, wprof_d, logl_d, grad_d, grad_prof_d, false,
+                       nullptr, stream);
+}
+
+RR_API int rr_loglik_grad_ld(const rr_tables* t, const double* times_d,
+                             const int32_t* lcids_d, int32_t npt,
+                             const int32_t* pbids, const int32_t* nss,
+                             const double* exptimes, int32_t nlc,
+                             const double* pv_d, int32_t npv, int32_t npar,
+                             const double* prof_d, int32_t precision, const void* obs_d,
+                             double sigma, double* logl_d, double* grad_d,
+                             double* grad_prof_d, hipStream_t stream) {
+    if (npv > 0 && !prof_d) return einval("prof is NULL");
+    return loglik_impl(t, times_d, lcids_d, npt, pbids, nss, exptimes, nlc, pv_d, npv, npar,
+                       precision, obs_d, sigma, nullptr, logl_d, grad_d, grad_prof_d, true,
+                       prof_d, stream);
 }
 
 RR_API void rr_free_tables(rr_tables* t) { free_tables(t); }

@@ -115,6 +115,8 @@ struct AdjointArgs {
     double* partials;         // [npv * nparts][7 + npb]
     double* gldw_pv;          // [npv][npb][ng]
     double* gist_pv;          // [npv][npb]
+    int32_t rows_per_vector;  // 1: T holds each vector's own two rows [npv][npb][2][ng]
+                              // and inv_istar is [npv][npb] (per-vector LD)
     int32_t nparts;           // workgroups per vector (ntiles without the profile gradient)
     int32_t tpp;              // tiles per workgroup
     double* seg_gw;           // [npv][nparts][npb][ng] (nparts > 1)
@@ -196,6 +198,10 @@ struct ProfGradScratch {
     double* gldp;         // [npb][nz]
     double* gist;         // [npb]
 };
+// Per-vector LD: d logL / d prof[ipv][pb][s] from the adjoint's per-vector
+// d logL / d ldw and d logL / d I_star; gldp is [npv][npb][nz] scratch.
+hipError_t launch_pv_prof_grad(const rr_tables* t, const AdjointArgs& A, double* gldp,
+                               double* out, hipStream_t s);
 hipError_t launch_profile_grad(const rr_tables* t, const AdjointArgs& a,
                                const ProfGradScratch& w, double* out, hipStream_t s);
 hipError_t launch_fill(double* p, int64_t n, hipStream_t s);
