@@ -369,6 +369,27 @@ def loglik_leg(rr, wl, steps, warmup):
         step()
     torch.cuda.synchronize()
     res["autograd_step_ms_mixed"] = 1e3 * (time.perf_counter() - t0) / max(2, steps // 2)
+    # the same walkers with a power-2 profile each (rr_loglik_grad_ld), with
+    # the gradient with respect to every walker's profile
+    rng = np.random.default_rng(31)
+    cw = w["ld_c"] * (1.0 + 0.01 * rng.standard_normal(npv))
+    aw = w["ld_alpha"] * (1.0 + 0.01 * rng.standard_normal(npv))
+    prof_pv = torch.as_tensor(
+        (1.0 - cw[:, None] * (1.0 - w["mu_s"][None, :] ** aw[:, None]))[:, None, :],
+        device="cuda")
+    per_row = {}
+    for prec in ("mixed", "fp64"):
+        obs_d = torch.as_tensor(obs, device="cuda",
+                                dtype=torch.float64 if prec == "fp64" else torch.float32)
+        for _ in range(warmup):
+            rr.loglik_grad_ld(tab, ser, pv, prof_pv, obs_d, w["sigma"], prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            rr.loglik_grad_ld(tab, ser, pv, prof_pv, obs_d, w["sigma"], prec)
+        torch.cuda.synchronize()
+        per_row[prec] = dict(ms_per_step=1e3 * (time.perf_counter() - t0) / steps)
+    res["per_walker_ld_with_profile_gradients"] = per_row
     return res
 
 
