@@ -725,41 +725,55 @@ inline unsigned nblocks(int64_t n) { return unsigned((n + kBlock - 1) / kBlock);
 
 // Per-vector LD: dlogL/dldp_r[j] = sum_m (W[ik][j][m] (1 - ak) +
 // W[ik+1][j][m] ak) dlogL/dldw_r[m] for row r = (vector, passband): the
-// transpose of the row's k-interpolated T = W . l.  Workgroup (r, j), a
-// fixed-shape tree over m.
+// transpose of the row's k-interpolated T = W . l.  Workgroup (r, 16 bins):
+// each wave takes 4 bins; per bin, lane l sums m = l, l + 64, ... in order,
+// then a fixed butterfly across the lanes.
+constexpr int kLdpBins = 16;
 __global__ __launch_bounds__(kBlock) void k_pv_ldp_grad(const double* __restrict__ W,
                                                         const double* __restrict__ gldw,
                                                         const double* __restrict__ pv,
                                                         int32_t npar, int32_t nz, GridDev g,
                                                         double* __restrict__ gldp) {
-    __shared__ double part[kBlock];
+    const int nchunk = (nz + kLdpBins - 1) / kLdpBins;
     const int64_t b = blockIdx.x;
-    const int64_t r = b / nz;
-    const int j = int(b - r * nz);
+    const int64_t r = b / nchunk;
+    const int jc = int(b - r * nchunk);
     const int64_t ipv = r / g.npb;
     const int pb = int(r - ipv * g.npb);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const double u = (pv[ipv * npar + 6 + pb] - g.k0) / g.dk;
     double uf = floor(u);
     if (!(uf >= 0.0)) uf = 0.0;                  // invalid rows carry zero gldw
     if (uf > g.nk - 2) uf = g.nk - 2;
     const int ik = int(uf);
     const double ak = u - ik;
-    const double* w0 = W + (int64_t(ik) * nz + j) * g.ng;
-    const double* w1 = w0 + int64_t(nz) * g.ng;
+    const bool finite_k = ak == ak;
     const double* gr = gldw + r * g.ng;
-    double s = 0.0;
-    for (int m = threadIdx.x; m < g.ng; m += kBlock) {
-        const double gv = gr[m];
-        s += ((1.0 - ak) * w0[m] + ak * w1[m]) * gv;
+    constexpr int kPerWave = kLdpBins / (kBlock / 64);
+#pragma unroll
+    for (int q = 0; q < kPerWave; ++q) {
+        const int j = jc * kLdpBins + wave * kPerWave + q;
+        if (j >= nz) break;                      // uniform per wave
+        const double* w0 = W + (int64_t(ik) * nz + j) * g.ng;
+        const double* w1 = w0 + int64_t(nz) * g.ng;
+        // eight columns' loads in flight, added in column order
+        double s = 0.0;
+        for (int m0 = lane; m0 < g.ng; m0 += 8 * 64) {
+            double x0[8], x1[8], gv[8];
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                const int m = m0 + 64 * b;
+                const bool in = m < g.ng;
+                x0[b] = in ? w0[m] : 0.0;
+                x1[b] = in ? w1[m] : 0.0;
+                gv[b] = in ? gr[m] : 0.0;
+            }
+#pragma unroll
+            for (int b = 0; b < 8; ++b) s += ((1.0 - ak) * x0[b] + ak * x1[b]) * gv[b];
+        }
+        s = wave_sum(finite_k ? s : 0.0);
+        if (lane == 0) gldp[r * nz + j] = s;
     }
-    if (!(ak == ak)) s = 0.0;                    // non-finite k: no contribution
-    part[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = kBlock / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) gldp[r * nz + j] = part[0];
 }
 
 template <typename R, int NPBT, bool kProf>
@@ -825,7 +839,8 @@ hipError_t launch_pv_prof_grad(const rr_tables* t, const AdjointArgs& A, double*
                                double* out, hipStream_t s) {
     const GridDev g = A.g;
     const int64_t nr = int64_t(A.npv) * g.npb;
-    hipLaunchKernelGGL(k_pv_ldp_grad, dim3(unsigned(nr * t->nz)), dim3(kBlock), 0, s, t->W,
+    const int64_t nchunk = (t->nz + kLdpBins - 1) / kLdpBins;
+    hipLaunchKernelGGL(k_pv_ldp_grad, dim3(unsigned(nr * nchunk)), dim3(kBlock), 0, s, t->W,
                        A.gldw_pv, A.pv, A.npar, t->nz, g, gldp);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -174,10 +174,9 @@ hipError_t launch_prepare_grid_weights(rr_tables* t, hipStream_t s) {
 // T_r[s][m] = sum_j W[ik_r + s][j][m] ldp[r][j], s = 0, 1, around its k
 // (Sect. 3.1.2: T = W . l, then the k-interpolation in the forward kernel).
 // k_pv_prep sorts the rows by ik (counting sort in one workgroup; the order
-// within a bin is arbitrary and does not affect any result), so that the
-// rows with equal ik are handled one after another (k_pv_tables below).
-// Sums run over bins in order in FP64, the same order as k_tables, so a
-// vector with the tables' own profile gets exactly the shared rows.
+// within a bin is arbitrary and does not affect any result), so that rows
+// with equal ik share the W reads of one matrix-core tile
+// (k_pv_tables_mfma, k_pv_tables below).
 // Counting sort of the rows by ik, by one workgroup of kBlock threads
 // (thread t owns bins 16 t .. 16 t + 15 of at most 4096).
 __device__ inline void sort_rows(const double* __restrict__ pv, int32_t npv, int32_t npar,
@@ -253,8 +252,28 @@ __global__ __launch_bounds__(kBlock) void k_pv_prep(const double* __restrict__ m
     istar_block(mu_s, f, nmu, istar + r, inv_istar + r);
 }
 
-// One workgroup per (row, 256 m), rows taken in sorted order, with an
-// XCD-aware block order: blocks go round-robin to the eight XCDs, so block
+// Rows of a sorted 16-row tile with at most two distinct k-rows go to the
+// matrix cores (k_pv_tables_mfma, which then reads each W value once for up
+// to 16 rows); the rows of the other tiles (k spread over many k-rows, where
+// a tile would need a pass per k-row) to k_pv_tables, one workgroup per
+// (row, 256 m).  Both kernels evaluate the same test on the sorted keys, so
+// every row is written by exactly one of them.
+constexpr int kMfmaMaxRuns = 2;
+__device__ inline bool tile_on_matrix_cores(const int32_t* __restrict__ ikr,
+                                            const int32_t* __restrict__ perm, int64_t nr,
+                                            int64_t tile) {
+    int runs = 0, prev = -1;
+    for (int q = 0; q < 16; ++q) {
+        const int64_t pos = tile * 16 + q;
+        if (pos >= nr) break;
+        const int ik = ikr[perm[pos]];
+        runs += ik != prev ? 1 : 0;
+        prev = ik;
+    }
+    return runs <= kMfmaMaxRuns;
+}
+
+// k_pv_tables: rows taken in sorted order, with an XCD-aware block order: blocks go round-robin to the eight XCDs, so block
 // p works on sorted item (p mod 8) * (blocks / 8) + p / 8 (rounded for a
 // remainder) and each XCD walks a contiguous stretch of the sorted rows,
 // whose W rows its L2 then serves to the following rows of equal ik.
@@ -274,6 +293,7 @@ __global__ __launch_bounds__(kBlock) void k_pv_tables(const double* __restrict__
     const int nmb = (g.ng + kBlock - 1) / kBlock;
     const int64_t pos = L / nmb;
     const int mb = int(L - pos * nmb);
+    if (tile_on_matrix_cores(ikr, perm, int64_t(nb / nmb), pos / 16)) return;   // uniform
     const int64_t r = perm[pos];
     const int ik = ikr[r];
     for (int j = threadIdx.x; j < nz; j += kBlock) lp[j] = ldp[r * nz + j];
@@ -304,6 +324,81 @@ __global__ __launch_bounds__(kBlock) void k_pv_tables(const double* __restrict__
     R* o = out + r * 2 * g.ng;
     o[m] = R(a0);
     o[g.ng + m] = R(a1);
+}
+
+// The per-vector table rows on the matrix cores: per wave a 16 (m) x 16 (sorted
+// rows) tile of T_r[s][m] = sum_j W[ik_r + s][j][m] ldp_r[j], s = 0, 1, as
+// D = A B with A[m][j] = W[ik + s][j][m] and B[j][q] = ldp of row q when the
+// row's k-row is ik, else 0, over the distinct ik of the tile's rows (sorted,
+// so usually one or two), with v_mfma_f64_16x16x4f64 (FP64 products and
+// sums; only the order of the additions over j differs from k_tables).
+// Lane l holds A[l & 15][l >> 4], B[l >> 4][l & 15] and D[4 i + (l >> 4)][l & 15]
+// (checked on the device).  Block = 4 waves = 64 m x 16 rows.
+typedef double v4d __attribute__((ext_vector_type(4)));
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_pv_tables_mfma(const double* __restrict__ W,
+                                                           const double* __restrict__ ldp,
+                                                           const int32_t* __restrict__ ikr,
+                                                           const int32_t* __restrict__ perm,
+                                                           int64_t nr, int32_t nz, GridDev g,
+                                                           R* __restrict__ out) {
+    const int nmb = (g.ng + 63) / 64;
+    const int64_t rt = int64_t(blockIdx.x) / nmb;            // row tile
+    const int mb = int(int64_t(blockIdx.x) - rt * nmb);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int m0 = mb * 64 + wave * 16;
+    const int ka = lane >> 4, col = lane & 15;
+    const int mm = m0 + col;                                   // A row of this lane
+    const int64_t pos = rt * 16 + col;                         // B column of this lane
+    const int64_t r = pos < nr ? perm[pos] : -1;
+    const int ik = r >= 0 ? ikr[r] : 0x7fffffff;
+    const bool mok = mm < g.ng;
+    // tiles whose rows span more than kMfmaMaxRuns k-rows are k_pv_tables' work
+    const int prev_ik = __shfl(ik, (lane & 48) | ((col + 15) & 15), 64);
+    const uint64_t starts = __ballot(lane < 16 && r >= 0 && (col == 0 || ik != prev_ik));
+    if (__popcll(starts) > kMfmaMaxRuns) return;                  // uniform per wave
+    v4d d0 = {0.0, 0.0, 0.0, 0.0}, d1 = {0.0, 0.0, 0.0, 0.0};
+    // distinct k-rows of the tile, smallest first (wave-uniform loop)
+    int cur = ik;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) cur = min(cur, __shfl_xor(cur, off, 64));
+    while (cur != 0x7fffffff) {
+        const bool take = ik == cur;
+        const double* w0 = W + int64_t(cur) * nz * g.ng + (mok ? mm : 0);
+        const double* w1 = w0 + int64_t(nz) * g.ng;
+        const double* lr = ldp + (take ? r : 0) * nz;
+        for (int j0 = 0; j0 < nz; j0 += 16) {
+            double a0[4], a1[4], b[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {               // four k-steps' loads in flight
+                const int j = j0 + 4 * u + ka;
+                const bool jin = j < nz;
+                a0[u] = jin && mok ? w0[int64_t(j) * g.ng] : 0.0;
+                a1[u] = jin && mok ? w1[int64_t(j) * g.ng] : 0.0;
+                b[u] = jin && take ? lr[j] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                d0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[u], b[u], d0, 0, 0, 0);
+                d1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[u], b[u], d1, 0, 0, 0);
+            }
+        }
+        int nxt = ik > cur ? ik : 0x7fffffff;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) nxt = min(nxt, __shfl_xor(nxt, off, 64));
+        cur = nxt;
+    }
+    // lane l holds rows m0 + 4 i + ka of column col
+    if (r < 0) return;
+    R* o = out + r * 2 * g.ng;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int m = m0 + 4 * i + ka;
+        if (m < g.ng) {
+            o[m] = R(d0[i]);
+            o[g.ng + m] = R(d1[i]);
+        }
+    }
 }
 
 // Direct model (Sect. 3.1.1): the LD-weighted vector of row r = (vector,
@@ -340,7 +435,18 @@ __global__ __launch_bounds__(kBlock) void k_direct_rows(const double* __restrict
     const double c = (double(m) / double(g.ng - 1)) * (1.0 + k);
     const double tot = lens_area<double>(1.0, k, c);
     double acc = 0.0;
-    for (int j = 0; j < nz; ++j) acc += annulus_weight(ze, nz, j, k, c, tot) * lp[j];
+    if (tot > 0.0) {
+        // each edge's area once: the upper edge of bin j is the lower of j + 1
+        // (the same values annulus_weight computes)
+        double lo = lens_area<double>(ze[0], k, c);
+        for (int j = 0; j < nz; ++j) {
+            const double hi = lens_area<double>(ze[j + 1], k, c);
+            acc += ((hi - lo) / tot) * lp[j];
+            lo = hi;
+        }
+    } else {
+        for (int j = 0; j < nz; ++j) acc += annulus_weight(ze, nz, j, k, c, tot) * lp[j];
+    }
     o[m] = R(acc);
     o[g.ng + m] = R(acc);
 }
@@ -369,13 +475,19 @@ hipError_t launch_pv_ld(const rr_tables* t, const double* prof, const double* pv
                        t->nmu, t->zm, t->nz, pv, npv, npar, g, ldp, istar, inv_istar, ikr, perm);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const dim3 grid(unsigned(nr * ((g.ng + kBlock - 1) / kBlock)));
-    if (precision == RR_FP64)
-        hipLaunchKernelGGL(k_pv_tables<double>, grid, dim3(kBlock), 0, s, t->W, ldp, ikr, perm,
-                           t->nz, g, static_cast<double*>(rows));
-    else
-        hipLaunchKernelGGL(k_pv_tables<float>, grid, dim3(kBlock), 0, s, t->W, ldp, ikr, perm,
-                           t->nz, g, static_cast<float*>(rows));
+    const dim3 grid(unsigned(((nr + 15) / 16) * ((g.ng + 63) / 64)));
+    const dim3 grid_rows(unsigned(nr * ((g.ng + kBlock - 1) / kBlock)));
+    if (precision == RR_FP64) {
+        hipLaunchKernelGGL(k_pv_tables_mfma<double>, grid, dim3(kBlock), 0, s, t->W, ldp, ikr,
+                           perm, nr, t->nz, g, static_cast<double*>(rows));
+        hipLaunchKernelGGL(k_pv_tables<double>, grid_rows, dim3(kBlock), 0, s, t->W, ldp, ikr,
+                           perm, t->nz, g, static_cast<double*>(rows));
+    } else {
+        hipLaunchKernelGGL(k_pv_tables_mfma<float>, grid, dim3(kBlock), 0, s, t->W, ldp, ikr,
+                           perm, nr, t->nz, g, static_cast<float*>(rows));
+        hipLaunchKernelGGL(k_pv_tables<float>, grid_rows, dim3(kBlock), 0, s, t->W, ldp, ikr,
+                           perm, t->nz, g, static_cast<float*>(rows));
+    }
     return hipGetLastError();
 }
 

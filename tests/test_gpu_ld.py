@@ -52,6 +52,25 @@ def test_population_ld_matches_oracle(rr, npt):
     check(ref, f64, f32)
 
 
+def test_clustered_radius_ratios(rr):
+    """Rows whose k fall on few k-rows (walkers): after sorting, 16-row tiles
+    with one or two k-rows run on the matrix cores and tiles spanning more
+    run per row; 45 rows give tiles of both kinds and a ragged last tile."""
+    w = wl.population_ld(npv=45, npt=3000)
+    w["times"] = np.linspace(0.0, 12.0, 3000)
+    pv = w["pv"].copy()
+    dk = (wl.TEST_GRID["k1"] - wl.TEST_GRID["k0"]) / (wl.TEST_GRID["nk"] - 1)
+    base = wl.TEST_GRID["k0"] + 8 * dk
+    pattern = [0.3] * 20 + [1.4] * 8 + [2.6, 3.5, 4.2, 5.1, 6.3, 7.7, 8.2, 9.9] + [11.3] * 9
+    pv[:, 6] = base + dk * np.asarray(pattern)
+    tab = rr.Tables(w["mu_s"], w["I_s"], wl.TEST_GRID)
+    otab = orr.Tables(w["mu_s"], w["I_s"], **wl.TEST_GRID)
+    ser = rr.TimeSeries(w["times"])
+    f64 = rr.evaluate_ld(tab, ser, pv, w["prof_pv"], "fp64").cpu().numpy()
+    f32 = rr.evaluate_ld(tab, ser, pv, w["prof_pv"], "mixed").cpu().numpy().astype(np.float64)
+    check(orr.evaluate_ld(otab, w["times"], pv, w["prof_pv"]), f64, f32)
+
+
 def test_heterogeneous_passbands_and_supersampling(rr):
     """Four passbands, each vector with four profiles of its own, chromatic k,
     nss 10 and 1 light curves."""
@@ -72,17 +91,17 @@ def test_heterogeneous_passbands_and_supersampling(rr):
 
 def test_own_profile_equals_shared_tables(rr):
     """Every vector given the tables' own profile: rr_evaluate_ld and
-    rr_evaluate agree bitwise (each vector's two table rows are summed over
-    the bins in the same order as the shared table, then interpolated in k
-    the same way)."""
+    rr_evaluate agree to rounding (each vector's two table rows are the
+    shared rows up to the order of the FP64 additions over bins, then
+    interpolated in k the same way)."""
     w = wl.population(npv=64, npt=6000)
     tab = rr.Tables(w["mu_s"], w["I_s"], wl.DEFAULT_GRID)
     ser = rr.TimeSeries(w["times"])
     prof = np.broadcast_to(w["I_s"], (64,) + w["I_s"].shape).copy()
-    for prec in ("fp64", "mixed"):
-        a = rr.evaluate_ld(tab, ser, w["pv"], prof, prec).cpu().numpy()
-        b = rr.evaluate(tab, ser, w["pv"], prec).cpu().numpy()
-        assert np.array_equal(a, b), (prec, np.abs(a.astype(float) - b).max())
+    for prec, tol in (("fp64", 1e-14), ("mixed", 1e-8)):
+        a = rr.evaluate_ld(tab, ser, w["pv"], prof, prec).cpu().numpy().astype(np.float64)
+        b = rr.evaluate(tab, ser, w["pv"], prec).cpu().numpy().astype(np.float64)
+        assert np.abs(a - b).max() <= tol, (prec, np.abs(a - b).max())
 
 
 def test_full_size_sampled_rows(rr):
