@@ -725,19 +725,24 @@ inline unsigned nblocks(int64_t n) { return unsigned((n + kBlock - 1) / kBlock);
 
 // Per-vector LD: dlogL/dldp_r[j] = sum_m (W[ik][j][m] (1 - ak) +
 // W[ik+1][j][m] ak) dlogL/dldw_r[m] for row r = (vector, passband): the
-// transpose of the row's k-interpolated T = W . l.  Workgroup (r, 16 bins):
-// each wave takes 4 bins; per bin, lane l sums m = l, l + 64, ... in order,
-// then a fixed butterfly across the lanes.
+// transpose of the row's k-interpolated T = W . l.  Workgroup (sorted row,
+// 16 bins): each wave takes 4 bins; per bin, lane l sums m = l, l + 64, ...
+// in order, then a fixed butterfly across the lanes.  Rows of tiles that go
+// to the matrix cores (k_pv_ldp_grad_mfma) are skipped.
 constexpr int kLdpBins = 16;
 __global__ __launch_bounds__(kBlock) void k_pv_ldp_grad(const double* __restrict__ W,
                                                         const double* __restrict__ gldw,
                                                         const double* __restrict__ pv,
-                                                        int32_t npar, int32_t nz, GridDev g,
+                                                        int32_t npar, const int32_t* __restrict__ ikr,
+                                                        const int32_t* __restrict__ perm,
+                                                        int64_t nr, int32_t nz, GridDev g,
                                                         double* __restrict__ gldp) {
     const int nchunk = (nz + kLdpBins - 1) / kLdpBins;
     const int64_t b = blockIdx.x;
-    const int64_t r = b / nchunk;
-    const int jc = int(b - r * nchunk);
+    const int64_t pos = b / nchunk;
+    const int jc = int(b - pos * nchunk);
+    if (tile_on_matrix_cores(ikr, perm, nr, pos / 16)) return;     // uniform
+    const int64_t r = perm[pos];
     const int64_t ipv = r / g.npb;
     const int pb = int(r - ipv * g.npb);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -835,13 +840,89 @@ hipError_t launch_adjoint(const AdjointArgs& A, int32_t precision, hipStream_t s
     return hipGetLastError();
 }
 
-hipError_t launch_pv_prof_grad(const rr_tables* t, const AdjointArgs& A, double* gldp,
-                               double* out, hipStream_t s) {
+// The same on the matrix cores for tiles of 16 sorted rows on at most
+// kMfmaMaxRuns k-rows: per wave a 16 (bins) x 16 (rows) tile of
+// D[j][q] = sum_m W[ik][j][m] (1 - ak_q) g_q[m] + W[ik+1][j][m] ak_q g_q[m]
+// (g_q = dlogL/dldw of row q, zero for rows on another k-row), two
+// v_mfma_f64_16x16x4f64 chains into one accumulator; lane layout as in
+// k_pv_tables_mfma.  Block = 4 waves = 64 bins x 16 rows.
+typedef double v4d __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(kBlock) void k_pv_ldp_grad_mfma(
+    const double* __restrict__ W, const double* __restrict__ gldw,
+    const double* __restrict__ pv, int32_t npar, const int32_t* __restrict__ ikr,
+    const int32_t* __restrict__ perm, int64_t nr, int32_t nz, GridDev g,
+    double* __restrict__ gldp) {
+    const int njb = (nz + 63) / 64;
+    const int64_t rt = int64_t(blockIdx.x) / njb;
+    const int jb = int(int64_t(blockIdx.x) - rt * njb);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int j0 = jb * 64 + wave * 16;
+    const int ka = lane >> 4, col = lane & 15;
+    const int64_t pos = rt * 16 + col;
+    const int64_t r = pos < nr ? perm[pos] : -1;
+    const int ik = r >= 0 ? ikr[r] : 0x7fffffff;
+    const int prev_ik = __shfl(ik, (lane & 48) | ((col + 15) & 15), 64);
+    const uint64_t starts = __ballot(lane < 16 && r >= 0 && (col == 0 || ik != prev_ik));
+    if (__popcll(starts) > kMfmaMaxRuns) return;                  // k_pv_ldp_grad's tile
+    double ak = 0.0;
+    if (r >= 0) {
+        const int64_t ipv = r / g.npb;
+        const int pb = int(r - ipv * g.npb);
+        ak = (pv[ipv * npar + 6 + pb] - g.k0) / g.dk - ik;
+        if (!(ak == ak)) ak = 0.0;                  // non-finite k: zero gldw anyway
+    }
+    const int jj = j0 + col;                          // A row of this lane
+    const bool jin = jj < nz;
+    v4d d = {0.0, 0.0, 0.0, 0.0};
+    int cur = ik;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) cur = min(cur, __shfl_xor(cur, off, 64));
+    while (cur != 0x7fffffff) {
+        const bool take = ik == cur;
+        const double* w0 = W + (int64_t(cur) * nz + (jin ? jj : 0)) * g.ng;
+        const double* w1 = w0 + int64_t(nz) * g.ng;
+        const double* gr = gldw + (take ? r : 0) * g.ng;
+        for (int m0 = 0; m0 < g.ng; m0 += 16) {
+            double a0[4], a1[4], b0[4], b1[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {               // four k-steps' loads in flight
+                const int m = m0 + 4 * u + ka;
+                const bool min_ = m < g.ng;
+                a0[u] = jin && min_ ? w0[m] : 0.0;
+                a1[u] = jin && min_ ? w1[m] : 0.0;
+                const double gq = take && min_ ? gr[m] : 0.0;
+                b0[u] = (1.0 - ak) * gq;
+                b1[u] = ak * gq;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                d = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[u], b0[u], d, 0, 0, 0);
+                d = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[u], b1[u], d, 0, 0, 0);
+            }
+        }
+        int nxt = ik > cur ? ik : 0x7fffffff;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) nxt = min(nxt, __shfl_xor(nxt, off, 64));
+        cur = nxt;
+    }
+    if (r < 0) return;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int j = j0 + 4 * i + ka;
+        if (j < nz) gldp[r * nz + j] = d[i];
+    }
+}
+
+hipError_t launch_pv_prof_grad(const rr_tables* t, const AdjointArgs& A, const int32_t* ikr,
+                               const int32_t* perm, double* gldp, double* out, hipStream_t s) {
     const GridDev g = A.g;
     const int64_t nr = int64_t(A.npv) * g.npb;
     const int64_t nchunk = (t->nz + kLdpBins - 1) / kLdpBins;
+    hipLaunchKernelGGL(k_pv_ldp_grad_mfma, dim3(unsigned(((nr + 15) / 16) * ((t->nz + 63) / 64))),
+                       dim3(kBlock), 0, s, t->W, A.gldw_pv, A.pv, A.npar, ikr, perm, nr, t->nz, g,
+                       gldp);
     hipLaunchKernelGGL(k_pv_ldp_grad, dim3(unsigned(nr * nchunk)), dim3(kBlock), 0, s, t->W,
-                       A.gldw_pv, A.pv, A.npar, t->nz, g, gldp);
+                       A.gldw_pv, A.pv, A.npar, ikr, perm, nr, t->nz, g, gldp);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     // the shared profile's last step with every (vector, passband) as one

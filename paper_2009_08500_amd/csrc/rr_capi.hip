@@ -495,8 +495,9 @@ static int loglik_impl(const rr_tables* t, const double* times_d,
                          reinterpret_cast<int32_t*>(base + o_perm), base + o_rows, stream);
     if (e == hipSuccess) e = launch_adjoint(A, precision, stream);
     if (e == hipSuccess && prof && per_row)
-        e = launch_pv_prof_grad(t, A, reinterpret_cast<double*>(base + o_gldpr), grad_prof_d,
-                                stream);
+        e = launch_pv_prof_grad(t, A, reinterpret_cast<const int32_t*>(base + o_ikr),
+                                reinterpret_cast<const int32_t*>(base + o_perm),
+                                reinterpret_cast<double*>(base + o_gldpr), grad_prof_d, stream);
     if (e == hipSuccess && shared_prof) {
         ProfGradScratch w;
         w.kidx = reinterpret_cast<int32_t*>(base + o_kidx);

@@ -381,4 +381,23 @@ __device__ inline bool in_phase_window(double u, const PvConst& p, double hw_pha
     return (g - floor(g)) < p.wn + 2.0 * hw_phase;
 }
 
+// Per-vector LD: a tile of 16 consecutive rows in k-row order goes to the
+// matrix cores when its rows span at most kMfmaMaxRuns k-rows (each W value
+// is then read once for the tile), else to the per-row kernels.  The
+// matrix-core and per-row kernels apply this same test to the sorted keys.
+constexpr int kMfmaMaxRuns = 2;
+// Wave-level: lanes 0..15 each read one key, so it must be called by whole
+// waves (the result is uniform).
+__device__ inline bool tile_on_matrix_cores(const int32_t* __restrict__ ikr,
+                                            const int32_t* __restrict__ perm, int64_t nr,
+                                            int64_t tile) {
+    const int lane = threadIdx.x & 63, q = lane & 15;
+    const int64_t pos = tile * 16 + q;
+    const bool in = pos < nr;
+    const int ik = in ? ikr[perm[pos]] : -1;
+    const int prev = __shfl(ik, (lane & 48) | ((q + 15) & 15), 64);
+    const uint64_t starts = __ballot(lane < 16 && in && (q == 0 || ik != prev));
+    return __popcll(starts) <= kMfmaMaxRuns;
+}
+
 }  // namespace rr

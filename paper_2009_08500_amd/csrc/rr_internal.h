@@ -199,9 +199,10 @@ struct ProfGradScratch {
     double* gist;         // [npb]
 };
 // Per-vector LD: d logL / d prof[ipv][pb][s] from the adjoint's per-vector
-// d logL / d ldw and d logL / d I_star; gldp is [npv][npb][nz] scratch.
-hipError_t launch_pv_prof_grad(const rr_tables* t, const AdjointArgs& A, double* gldp,
-                               double* out, hipStream_t s);
+// d logL / d ldw and d logL / d I_star; ikr and perm are launch_pv_ld's sort
+// of the rows by k-row, gldp is [npv][npb][nz] scratch.
+hipError_t launch_pv_prof_grad(const rr_tables* t, const AdjointArgs& A, const int32_t* ikr,
+                               const int32_t* perm, double* gldp, double* out, hipStream_t s);
 hipError_t launch_profile_grad(const rr_tables* t, const AdjointArgs& a,
                                const ProfGradScratch& w, double* out, hipStream_t s);
 hipError_t launch_fill(double* p, int64_t n, hipStream_t s);

@@ -258,21 +258,6 @@ __global__ __launch_bounds__(kBlock) void k_pv_prep(const double* __restrict__ m
 // a tile would need a pass per k-row) to k_pv_tables, one workgroup per
 // (row, 256 m).  Both kernels evaluate the same test on the sorted keys, so
 // every row is written by exactly one of them.
-constexpr int kMfmaMaxRuns = 2;
-__device__ inline bool tile_on_matrix_cores(const int32_t* __restrict__ ikr,
-                                            const int32_t* __restrict__ perm, int64_t nr,
-                                            int64_t tile) {
-    int runs = 0, prev = -1;
-    for (int q = 0; q < 16; ++q) {
-        const int64_t pos = tile * 16 + q;
-        if (pos >= nr) break;
-        const int ik = ikr[perm[pos]];
-        runs += ik != prev ? 1 : 0;
-        prev = ik;
-    }
-    return runs <= kMfmaMaxRuns;
-}
-
 // k_pv_tables: rows taken in sorted order, with an XCD-aware block order: blocks go round-robin to the eight XCDs, so block
 // p works on sorted item (p mod 8) * (blocks / 8) + p / 8 (rounded for a
 // remainder) and each XCD walks a contiguous stretch of the sorted rows,
