@@ -107,3 +107,29 @@ def test_autograd_through_per_row_coefficients(rr):
             cm[i, q] -= h
             fd = (loss(cp).item() - loss(cm).item()) / (2 * h)
             assert coef.grad[i, q].item() == pytest.approx(fd, rel=2e-5, abs=1e-3)
+
+
+def test_per_row_profiles_four_passbands(rr):
+    """Four passbands, supersampled light curves, each row with four
+    profiles of its own: logL, parameter gradients and every row's profile
+    gradient against the oracle (FP64)."""
+    w = wl.heterogeneous(npv=5, days=4.0)
+    kw = dict(lcids=w["lcids"], pbids=w["pbids"], nss=w["nss"], exptimes=w["exptimes"])
+    grid = wl.TEST_GRID
+    otab = orr.Tables(w["mu_s"], w["I_s"], **grid)
+    obs = orr.evaluate(otab, w["times"], w["pv"][:1], **kw)[0] + \
+        200e-6 * np.random.default_rng(8).standard_normal(w["times"].size)
+    rng = np.random.default_rng(9)
+    c = rng.uniform(0.3, 0.7, (5, 4))
+    al = rng.uniform(0.4, 0.8, (5, 4))
+    prof = 1.0 - c[..., None] * (1.0 - w["mu_s"][None, None, :] ** al[..., None])
+    tab = rr.Tables(w["mu_s"], w["I_s"], grid)
+    ser = rr.TimeSeries(w["times"], w["lcids"], w["pbids"], w["nss"], w["exptimes"])
+    ll, g, gp = [x.cpu().numpy() for x in rr.loglik_grad_ld(tab, ser, w["pv"], prof, obs, 2e-4,
+                                                            "fp64")]
+    for i in range(5):
+        oll, og, ogp = ogr.loglik_grad(orr.with_profile(otab, prof[i]), w["times"],
+                                       w["pv"][i:i + 1], obs, 2e-4, **kw)
+        np.testing.assert_allclose(ll[i], oll[0], rtol=1e-11)
+        rowwise_close(g[i:i + 1], og, 1e-7)
+        rowwise_close(gp[i], ogp, 1e-7)
