@@ -260,6 +260,42 @@ __device__ inline void forward_block(const FwdJob& job, const LcInfo& lc, int ip
     int pb_cached = -1;
     PbConst<R> c = {};
 
+    // Pass 2 when every flagged exposure of the wave has nss = 1: two
+    // exposures of the same passband at a time, as two independent chains
+    // the compiler interleaves (a lane with several exposures is
+    // latency-bound, above all in the kernel's tail where few waves are left
+    // to hide it).  Both kernel variants take this path for such waves, so
+    // a series gives the same bits whichever variant a launch uses.
+    auto pass2_pairs = [&]() {
+        while (todo) {
+            const int r1 = __builtin_ctz(todo);
+            todo &= todo - 1;
+            const int it1 = t_base + 64 * r1;
+            const int l1 = lcids ? lcids[it1] : 0;
+            const int pb1 = lc.pb[l1];
+            if (pb1 != pb_cached) {
+                pb_cached = pb1;
+                c = pb_const<R>(pv, ipv, npar, pb1, g, T, inv_istar, job);
+            }
+            int it2 = -1, l2 = 0;
+            if (todo) {
+                const int r2 = __builtin_ctz(todo);
+                const int cand = t_base + 64 * r2;
+                l2 = lcids ? lcids[cand] : 0;
+                if (lc.pb[l2] == pb1) {
+                    it2 = cand;
+                    todo &= todo - 1;
+                }
+            }
+            const R d1 = subsample_delta<R>(p, orb, c, times[it1], lc.exptime[l1], 1.0, 0, g);
+            if (it2 >= 0) {
+                const R d2 = subsample_delta<R>(p, orb, c, times[it2], lc.exptime[l2], 1.0, 0, g);
+                orow[it2] = R(1) - d2;
+            }
+            orow[it1] = R(1) - d1;
+        }
+    };
+
     if constexpr (kSubPar) {
         // Supersampled exposures: if every flagged exposure of the wave has
         // the same nss in [2, 32], spread the subsamples over the lanes --
@@ -282,6 +318,10 @@ __device__ inline void forward_block(const FwdJob& job, const LcInfo& lc, int ip
             nmax = b > nmax ? b : nmax;
         }
         const int N = nmax;
+        if (N == 1) {
+            pass2_pairs();
+            return;
+        }
         if (nmin == nmax && N >= 2 && N <= 32) {
             __shared__ uint16_t packed[kFwdBlock / 64][kSpan];
             uint16_t* pk = packed[threadIdx.x >> 6];
@@ -324,6 +364,10 @@ __device__ inline void forward_block(const FwdJob& job, const LcInfo& lc, int ip
     }
 
     // Pass 2 in the wave: the flagged exposures, one per lane and bit.
+    if constexpr (!kSubPar) {
+        pass2_pairs();
+        return;
+    }
     while (todo) {
         const int r = __builtin_ctz(todo);
         todo &= todo - 1;
