@@ -350,3 +350,73 @@ def evaluate_direct(tab, times, pv, lcids=None, pbids=None, nss=None, exptimes=N
             z, front, _ = _orbit.projected_separation(dt, P, a, b, e, w)
             out[ipv, sel] = 1.0 - occulted_with(tab, ldw, pb, k, z, front).mean(axis=1)
     return out
+
+
+# ---------------------------------------------------------------- Sect. 3.4.2
+def small_planet_ldw(tab, pb, k):
+    """Small-planet approximation (Sect. 3.4.2) as an LD vector over g: at
+    each g node the LD-weighted mean over the planet's disk is replaced by
+    the profile at the planet's centre, c = g (1 + k), i.e. the interpolant
+    of the samples at mu = sqrt(1 - c^2).  A centre off the disk (c > 1,
+    limb overlap only) takes the limb value I(mu = 0).  The g-interpolation
+    of ``occulted_with`` is then applied unchanged."""
+    g = np.arange(tab.ng) / (tab.ng - 1.0)
+    c = np.minimum(g * (1.0 + k), 1.0)
+    return np.interp(np.sqrt(1.0 - c * c), tab.mu_s, tab.I_s[pb])
+
+
+def pv_is_valid_small_planet(row, tab, k_small):
+    """Physical parameter vector where every k is either below the
+    small-planet threshold (and positive) or inside the table's [k0, k1]."""
+    ks = row[NPAR_ORBIT:]
+    if not np.all(np.isfinite(row)):
+        return False
+    t0, P, a, b, e, w = row[:NPAR_ORBIT]
+    if not (P > 0.0 and a > 0.0 and b >= 0.0 and 0.0 <= e < 1.0):
+        return False
+    for k in ks:
+        if k < k_small:
+            if not k > 0.0:
+                return False
+        elif k < tab.k0 or k > tab.k1:
+            return False
+    return abs(_orbit.cos_inclination(a, b, e, w)) <= 1.0
+
+
+def evaluate_small_planet(tab, times, pv, k_small, lcids=None, pbids=None, nss=None,
+                          exptimes=None):
+    """Fluxes as ``evaluate``, except that a passband whose radius ratio is
+    below ``k_small`` uses ``small_planet_ldw`` instead of the table
+    interpolated in k (Sect. 3.4.2); such a k may lie below the table's k0.
+    I_star is the same normaliser in both cases."""
+    times = np.asarray(times, float)
+    pv = np.atleast_2d(np.asarray(pv, float))
+    npt = times.size
+    lcids = np.zeros(npt, np.int64) if lcids is None else np.asarray(lcids)
+    if pbids is None:
+        nlc = int(lcids.max()) + 1 if npt else 1
+        pbids = np.zeros(nlc, np.int64)
+    else:
+        pbids = np.asarray(pbids)
+        nlc = pbids.size
+    nss = np.ones(nlc, np.int64) if nss is None else np.broadcast_to(nss, (nlc,))
+    exptimes = (np.zeros(nlc) if exptimes is None
+                else np.broadcast_to(np.asarray(exptimes, float), (nlc,)))
+    out = np.empty((pv.shape[0], npt))
+    for ipv, row in enumerate(pv):
+        if not pv_is_valid_small_planet(row, tab, k_small):
+            out[ipv] = np.nan
+            continue
+        t0, P, a, b, e, w = row[:NPAR_ORBIT]
+        for lc in range(nlc):
+            sel = np.nonzero(lcids == lc)[0]
+            if sel.size == 0:
+                continue
+            pb = int(pbids[lc])
+            k = row[NPAR_ORBIT + pb]
+            ldw = small_planet_ldw(tab, pb, k) if k < k_small else ldw_for_k(tab, pb, k)
+            ts = _orbit.subsample_times(times[sel], int(nss[lc]), exptimes[lc])
+            dt = _orbit.phase_offset(ts, t0, P)
+            z, front, _ = _orbit.projected_separation(dt, P, a, b, e, w)
+            out[ipv, sel] = 1.0 - occulted_with(tab, ldw, pb, k, z, front).mean(axis=1)
+    return out
