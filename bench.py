@@ -301,6 +301,58 @@ def direct_leg(rr, wl, steps, warmup):
     return res
 
 
+def small_planet_leg(rr, wl, steps, warmup):
+    """Small planets (512 x 20 000, nss 1, k ~ logU(0.003, 0.03)) through
+    the small-planet approximation with threshold 0.01
+    (rr_evaluate_small_planet): points/s and per-call latency for both
+    precisions, the same population through the interpolated model for
+    comparison (rows below the tables' k0 are NaN there, so it is timed with
+    k raised to 0.01), and the error of eight sampled rows against the
+    oracle."""
+    import numpy as np
+    import torch
+    from oracle import roadrunner as orr
+    w = wl.population_small()
+    grid = wl.DEFAULT_GRID
+    tab = rr.Tables(w["mu_s"], w["I_s"], grid)
+    ser = rr.TimeSeries(w["times"])
+    pv = torch.as_tensor(w["pv"], device="cuda")
+    pv_tab = pv.clone()
+    pv_tab[:, 6] = pv_tab[:, 6].clamp(min=grid["k0"])
+    npv, npt = pv.shape[0], int(w["times"].size)
+    nsmall = int((w["pv"][:, 6] < 0.01).sum())
+    res = dict(workload=f"small planets: npv={npv} npt={npt} nss=1, k ~ logU(0.003, 0.03), "
+                        f"threshold 0.01 ({nsmall} vectors below)", npv=npv, npt=npt)
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return 1e3 * (time.perf_counter() - t0) / steps
+
+    outs = {}
+    for prec in ("mixed", "fp64"):
+        dtype = torch.float64 if prec == "fp64" else torch.float32
+        out = torch.empty((npv, npt), dtype=dtype, device="cuda")
+        ms = timed(lambda: rr.evaluate_small_planet(tab, ser, pv, 0.01, prec, out=out))
+        outs[prec] = out.cpu().numpy().astype(np.float64)
+        ms_tab = timed(lambda: rr.evaluate(tab, ser, pv_tab, prec, out=out))
+        res[prec] = dict(points_per_s=npv * npt / (ms / 1e3), ms_per_step=ms,
+                         interpolated_model_ms=ms_tab)
+    rows = np.random.default_rng(11).choice(npv, 8, replace=False)
+    otab = orr.Tables(w["mu_s"], w["I_s"], **grid)
+    ref = orr.evaluate_small_planet(otab, w["times"], w["pv"][rows], 0.01)
+    res["accuracy_vs_oracle"] = dict(
+        rows_checked=len(rows),
+        max_abs_err_fp64=float(np.abs(outs["fp64"][rows] - ref).max()),
+        max_abs_err_mixed_ppm=float(np.abs(outs["mixed"][rows] - ref).max()) * 1e6)
+    return res
+
+
 def loglik_leg(rr, wl, steps, warmup):
     """Gaussian log-likelihood and its adjoint for 1024 walkers around a truth
     vector, 50 000 times at 2-min cadence with nss = 5 (data = the oracle's
@@ -550,6 +602,7 @@ def main():
         line["heterogeneous"] = heterogeneous_leg(rr, wl, min(args.steps, 50), 5, lib)
         line["per_vector_ld"] = per_vector_ld_leg(rr, wl, min(args.steps, 50), 5, lib)
         line["direct_model"] = direct_leg(rr, wl, min(args.steps, 20), 2)
+        line["small_planet"] = small_planet_leg(rr, wl, min(args.steps, 20), 2)
         line["loglik_grad"] = loglik_leg(rr, wl, 10, 2)
     if not args.no_cpu_baseline:
         cb, acc = cpu_baseline(w, grid, args.cpu_seconds, o64, o32)

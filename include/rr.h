@@ -19,6 +19,8 @@
  *                   vector (LD sampled with the orbit);
  *   rr_evaluate_direct  the direct model: weights for each vector's own k,
  *                   no k-interpolation and no k limits (Sect. 3.1.1);
+ *   rr_evaluate_small_planet  the small-planet approximation below a
+ *                   radius-ratio threshold (Sect. 3.4.2);
  *   rr_flux_at_z    Eq. 5 at given separations and radius ratios;
  *   rr_loglik_grad  Gaussian log-likelihood of observed fluxes and its
  *                   gradient with respect to every parameter and to the
@@ -169,6 +171,29 @@ RR_API int rr_evaluate_direct(const rr_tables* t, const double* times_d,
                               const double* exptimes, int32_t nlc,
                               const double* pv_d, int32_t npv, int32_t npar,
                               int32_t precision, void* out_d, hipStream_t stream);
+
+/* The small-planet approximation (Sect. 3.4.2): fluxes as rr_evaluate,
+ * except that a passband whose radius ratio k is below k_small replaces the
+ * LD-weighted mean over the planet's disk with the LD value at the planet's
+ * centre.  Per g node (centre distance c = g (1 + k), clamped to 1 off the
+ * disk) that value is the tables' piecewise-linear profile at
+ * mu = sqrt(1 - c^2); the g-interpolation, lens area and I_star of
+ * rr_evaluate are kept.  Such a k needs only k > 0, so planets smaller than
+ * the tables' k0 are evaluated without widening the tables; a k at or above
+ * k_small takes the interpolated model and must lie in [k0, k1] (results
+ * equal rr_evaluate's up to rounding).  k_small: host scalar in [0, 1]
+ * (0: no row uses the approximation), else RR_EINVAL.  Other arguments,
+ * errors and invalid rows as rr_evaluate.  Temporary device memory
+ * (144 + 2 npb ng sizeof(real) bytes per vector) is the per-stream buffer
+ * that rr_evaluate uses.  The profile gradient entry points do not take
+ * this approximation. */
+RR_API int rr_evaluate_small_planet(const rr_tables* t, const double* times_d,
+                                    const int32_t* lcids_d, int32_t npt,
+                                    const int32_t* pbids, const int32_t* nss,
+                                    const double* exptimes, int32_t nlc,
+                                    const double* pv_d, int32_t npv, int32_t npar,
+                                    double k_small, int32_t precision, void* out_d,
+                                    hipStream_t stream);
 
 /* The model as a function of the separation: out_d[i] = Eq. 5 for a planet
  * in front of the star at separation z_d[i] (in stellar radii) with radius

@@ -8,8 +8,8 @@ the library has not been built.
 
 from ._lib import (RR_FP64, RR_MIXED, RRError, lib)  # noqa: F401
 from .api import (DEFAULT_GRID, Evaluator, RRLogLik, RRLogLikLD, Tables,  # noqa: F401
-                  TimeSeries, evaluate, evaluate_direct, evaluate_ld, flux_at_z,
-                  loglik_grad, loglik_grad_ld, make_grid)
+                  TimeSeries, evaluate, evaluate_direct, evaluate_ld, evaluate_small_planet,
+                  flux_at_z, loglik_grad, loglik_grad_ld, make_grid)
 from . import ldlaws  # noqa: F401,E402
 from .tuning import tune_grid  # noqa: F401,E402
 

@@ -75,6 +75,10 @@ def _declare(L):
                                      c_void_p, i32, c_void_p, i32, i32, i32, c_void_p,
                                      c_void_p]
     L.rr_evaluate_direct.restype = ctypes.c_int
+    L.rr_evaluate_small_planet.argtypes = [c_void_p, c_void_p, c_void_p, i32, c_void_p,
+                                           c_void_p, c_void_p, i32, c_void_p, i32, i32, dbl,
+                                           i32, c_void_p, c_void_p]
+    L.rr_evaluate_small_planet.restype = ctypes.c_int
     L.rr_flux_at_z.argtypes = [c_void_p, c_void_p, c_void_p, dbl, i64, i32, i32, c_void_p,
                                c_void_p]
     L.rr_flux_at_z.restype = ctypes.c_int

@@ -201,6 +201,33 @@ def evaluate_direct(tables, series, pv, precision="fp64", out=None, stream=None)
     return out
 
 
+def evaluate_small_planet(tables, series, pv, k_small, precision="fp64", out=None,
+                          stream=None):
+    """Fluxes with the small-planet approximation (rr_evaluate_small_planet,
+    Sect. 3.4.2): a passband whose k is below ``k_small`` uses the LD value
+    at the planet's centre instead of the mean over its disk, and may lie
+    below the tables' k0; the others are evaluated as ``evaluate``.
+    Arguments and result as ``evaluate``."""
+    prec = PRECISIONS[precision]
+    if not isinstance(series, TimeSeries):
+        series = TimeSeries(series)
+    pv = _dev(pv, torch.float64)
+    if pv.dim() == 1:
+        pv = pv.unsqueeze(0)
+    npv, npar = pv.shape
+    dtype = torch.float64 if prec == RR_FP64 else torch.float32
+    if out is None:
+        out = torch.empty((npv, series.npt), dtype=dtype, device=pv.device)
+    elif out.dtype != dtype or not out.is_contiguous() or out.numel() != npv * series.npt:
+        raise ValueError("out has the wrong dtype, layout or size")
+    lc, npt, pb, nss, ex, nlc = series.lc_args()
+    check(_lib.lib().rr_evaluate_small_planet(
+        tables.handle, ctypes.c_void_p(series.times.data_ptr()), lc, npt, pb, nss, ex, nlc,
+        ctypes.c_void_p(pv.data_ptr()), npv, npar, float(k_small), prec,
+        ctypes.c_void_p(out.data_ptr()), _stream(stream)), "rr_evaluate_small_planet")
+    return out
+
+
 def flux_at_z(tables, z, k, pb=0, precision="fp64", stream=None):
     """Eq. 5 at separations ``z`` for radius ratio ``k`` (a scalar or one per
     separation), planet in front of the star (rr_flux_at_z).  Returns a

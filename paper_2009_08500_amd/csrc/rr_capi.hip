@@ -305,6 +305,45 @@ RR_API int rr_evaluate_direct(const rr_tables* t, const double* times_d,
     return RR_OK;
 }
 
+RR_API int rr_evaluate_small_planet(const rr_tables* t, const double* times_d,
+                                    const int32_t* lcids_d, int32_t npt,
+                                    const int32_t* pbids, const int32_t* nss,
+                                    const double* exptimes, int32_t nlc,
+                                    const double* pv_d, int32_t npv, int32_t npar,
+                                    double k_small, int32_t precision, void* out_d,
+                                    hipStream_t stream) {
+    LcInfo lc;
+    int rc = check_eval_args(t, times_d, lcids_d, npt, pbids, nss, exptimes, nlc,
+                             pv_d, npv, npar, precision, &lc);
+    if (rc) return rc;
+    if (!(k_small >= 0.0 && k_small <= 1.0)) return einval("k_small must lie in [0, 1]");
+    if (npt == 0 || npv == 0) return RR_OK;
+    if (!out_d) return einval("out is NULL");
+    const int64_t nr = int64_t(npv) * t->npb;
+    if (nr * t->grid.ng >= (int64_t(1) << 36)) return elimit("npv * npb too large");
+    rc = check_device(t);
+    if (rc) return rc;
+    const size_t elt = precision == RR_FP64 ? sizeof(double) : sizeof(float);
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off += (bytes + 255) / 256 * 256; return o; };
+    const size_t o_pvc = take(sizeof(PvConst) * size_t(npv));
+    const size_t o_rows = take(elt * size_t(nr) * 2 * t->grid.ng);
+    void* ws = nullptr;
+    hipError_t e = stream_workspace(const_cast<rr_tables*>(t), stream, off, &ws);
+    if (e != hipSuccess) return e == hipErrorOutOfMemory ? RR_ENOMEM : hip_fail(e, "workspace");
+    char* base = static_cast<char*>(ws);
+    PvConst* pvc = reinterpret_cast<PvConst*>(base + o_pvc);
+    void* rows = base + o_rows;
+    e = launch_pv_setup_k(pv_d, npv, npar, t->grid.k0, t->grid.k1, pvc, stream, k_small);
+    if (e == hipSuccess)
+        e = launch_small_planet_rows(t, pv_d, npv, npar, k_small, precision, rows, stream);
+    if (e == hipSuccess)
+        e = launch_forward(t, times_d, lcids_d, npt, lc, pv_d, npv, npar, pvc, precision,
+                           out_d, stream, rows, nullptr, 1);
+    if (e != hipSuccess) return hip_fail(e, "small-planet kernels");
+    return RR_OK;
+}
+
 RR_API int rr_flux_at_z(const rr_tables* t, const double* z_d, const double* k_d,
                         double k, int64_t n, int32_t pb, int32_t precision, void* out_d,
                         hipStream_t stream) {

@@ -277,8 +277,10 @@ __host__ __device__ inline bool is_finite(double x) { return (x - x) == 0.0; }
 // [t0, P, a, b, e, w, k_0 .. k_{npb-1}] (FP64).  The row is invalid (NaN
 // output) if any value is non-finite, P <= 0, a <= 0, b < 0, e outside
 // [0, 1), a k outside [k0, k1] or |cos i| > 1.
+// A radius ratio below k_small (small-planet rows, Sect. 3.4.2) only has to
+// be positive; any other must lie in [k0, k1].
 __host__ __device__ inline PvConst make_pv_const(const double* row, int npb, double k0,
-                                                 double k1) {
+                                                 double k1, double k_small = 0.0) {
     PvConst c = {};
     const double t0 = row[0], P = row[1], a = row[2], b = row[3], e = row[4],
                  w = row[5];
@@ -288,7 +290,7 @@ __host__ __device__ inline PvConst make_pv_const(const double* row, int npb, dou
     double kmax = 0.0;
     for (int pb = 0; pb < npb; ++pb) {
         const double k = row[6 + pb];
-        ok = ok && is_finite(k) && k >= k0 && k <= k1;
+        ok = ok && is_finite(k) && (k < k_small ? k > 0.0 : (k >= k0 && k <= k1));
         kmax = k > kmax ? k : kmax;
     }
     double sw = 0.0, cw = 1.0;

@@ -33,11 +33,11 @@ static_assert(kTimesPerThread % 4 == 0 && kTimesPerThread <= 32,
               "pass 1 packs 4 float or 2 double outputs per 16-B store");
 
 __global__ void k_pv_setup(const double* __restrict__ pv, int32_t npv,
-                           int32_t npar, double k0, double k1,
+                           int32_t npar, double k0, double k1, double k_small,
                            PvConst* __restrict__ out) {
     const int ipv = blockIdx.x * blockDim.x + threadIdx.x;
     if (ipv >= npv) return;
-    out[ipv] = make_pv_const(pv + int64_t(ipv) * npar, npar - 6, k0, k1);
+    out[ipv] = make_pv_const(pv + int64_t(ipv) * npar, npar - 6, k0, k1, k_small);
 }
 
 // Per-row, per-passband constants of pass 2: the two k-rows of T that
@@ -461,9 +461,9 @@ hipError_t launch_pv_setup(const rr_tables* t, const double* pv, int32_t npv,
 }
 
 hipError_t launch_pv_setup_k(const double* pv, int32_t npv, int32_t npar, double k_lo,
-                             double k_hi, PvConst* pvc, hipStream_t s) {
+                             double k_hi, PvConst* pvc, hipStream_t s, double k_small) {
     hipLaunchKernelGGL(k_pv_setup, dim3(nblocks(npv)), dim3(kBlock), 0, s, pv, npv,
-                       npar, k_lo, k_hi, pvc);
+                       npar, k_lo, k_hi, k_small, pvc);
     return hipGetLastError();
 }
 

@@ -178,11 +178,12 @@ rr::GridDev grid_dev(const rr_tables* t);
 hipError_t launch_prepare_grid_weights(rr_tables* t, hipStream_t s);
 hipError_t launch_prepare_profile(rr_tables* t, hipStream_t s);
 // Per-row constants; k must lie in [k_lo, k_hi] (the tables' k range by
-// default; the direct model takes (0, 1]).
+// default; the direct model takes (0, 1]), or in (0, k_small) for
+// small-planet rows.
 hipError_t launch_pv_setup(const rr_tables* t, const double* pv, int32_t npv,
                            int32_t npar, PvConst* pvc, hipStream_t s);
 hipError_t launch_pv_setup_k(const double* pv, int32_t npv, int32_t npar, double k_lo,
-                             double k_hi, PvConst* pvc, hipStream_t s);
+                             double k_hi, PvConst* pvc, hipStream_t s, double k_small = 0.0);
 size_t adjoint_lds_bytes(int32_t precision, int32_t npb, int32_t ng);
 hipError_t launch_adjoint(const AdjointArgs& a, int32_t precision, hipStream_t s);
 // Temporaries of the profile gradient.
@@ -220,6 +221,13 @@ hipError_t launch_forward(const rr_tables* t, const double* times,
 // LD-weighted vector for its own k, rows [npv][npb][2][ng] by precision.
 hipError_t launch_direct_rows(const rr_tables* t, const double* pv, int32_t npv, int32_t npar,
                               int32_t precision, void* rows, hipStream_t s);
+// Small-planet approximation (rr_evaluate_small_planet): rows
+// [npv][npb][2][ng] by precision; a row whose k is below k_small holds the
+// profile at the planet's centre for each g node, any other the tables' two
+// k-rows already interpolated at its k (read with zero k-weight).
+hipError_t launch_small_planet_rows(const rr_tables* t, const double* pv, int32_t npv,
+                                    int32_t npar, double k_small, int32_t precision,
+                                    void* rows, hipStream_t s);
 // Eq. 5 at separations z[n] (rr_flux_at_z); kv[n] or, if NULL, kconst.
 hipError_t launch_flux_at_z(const rr_tables* t, const double* z, const double* kv,
                            double kconst, int64_t n, int32_t pb, int32_t precision, void* out,

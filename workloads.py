@@ -131,6 +131,18 @@ def population_ld(npv=512, npt=20000, seed_extra=0):
     return w
 
 
+def population_small(npv=512, npt=20000, seed_extra=0, k_lo=0.003, k_hi=0.03):
+    """Population with small planets: the orbits, profile and times of
+    ``population`` with k ~ logU(k_lo, k_hi), so that about half the vectors
+    fall below a small-planet threshold of 0.01 (Earth- to Neptune-size
+    planets around a Sun-like star)."""
+    w = population(npv, npt, seed_extra)
+    rng = rng_for(7, seed_extra)
+    w["pv"][:, 6] = np.exp(rng.uniform(np.log(k_lo), np.log(k_hi), npv))
+    w["name"] = f"population_small_npv{npv}_npt{npt}"
+    return w
+
+
 def heterogeneous(npv=256, days=27.0, seed_extra=0):
     """Four passbands with their own profiles and chromatic k; two 30-min
     light curves with nss = 10 and two 2-min light curves with nss = 1, all
