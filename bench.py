@@ -353,6 +353,31 @@ def small_planet_leg(rr, wl, steps, warmup):
     return res
 
 
+def variant_leg(rr, wl):
+    """Trial-run selection of the forward-kernel variant (rr_select_variant)
+    on three workloads: the population, a small problem (32 x 2000) and the
+    heterogeneous four-passband series; the mean time per forward launch of
+    each variant (4/8/16 exposures per lane; subsamples spread or one lane
+    per exposure) and the one chosen."""
+    import torch
+    res = {}
+    w = wl.population()
+    cases = [("population 512 x 20000", w, rr.TimeSeries(w["times"]), w["pv"]),
+             ("small 32 x 2000", w, rr.TimeSeries(w["times"][:2000]), w["pv"][:32])]
+    wh = wl.heterogeneous()
+    cases.append(("heterogeneous 256 x 41472 (nss 10/1)", wh,
+                  rr.TimeSeries(wh["times"], wh["lcids"], wh["pbids"], wh["nss"],
+                                wh["exptimes"]), wh["pv"]))
+    for name, wk, ser, pv in cases:
+        tab = rr.Tables(wk["mu_s"], wk["I_s"], wl.DEFAULT_GRID)
+        pvd = torch.as_tensor(pv, device="cuda")
+        res[name] = {}
+        for prec in ("mixed", "fp64"):
+            best, ms = rr.select_variant(tab, ser, pvd, prec, reps=20)
+            res[name][prec] = dict(best=best, us_per_variant=[round(1e3 * m, 2) for m in ms])
+    return res
+
+
 def loglik_leg(rr, wl, steps, warmup):
     """Gaussian log-likelihood and its adjoint for 1024 walkers around a truth
     vector, 50 000 times at 2-min cadence with nss = 5 (data = the oracle's
@@ -564,13 +589,13 @@ def main():
     m = summary("mixed", 4)
     d = summary("fp64", 8)
     achieved = m["alg_bytes"] / (m["kernel_ms"]["mean"] / 1e3) / 1e9
-    kc = profile_counters("k_forward<float, false>")
+    kc = profile_counters("k_forward<float, false, 8>")
     traffic = kc.get("hbm_bytes_per_launch") if kc else None
     roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=achieved / HBM_PEAK_GBS, traffic=traffic,
-                kernel="k_forward<float, false>", alg_bytes_per_launch=m["alg_bytes"],
+                kernel="k_forward<float, false, 8>", alg_bytes_per_launch=m["alg_bytes"],
                 kernel_ms=m["kernel_ms"]["mean"],
-                valu=valu_view("k_forward<float, false>", m["kernel_ms"]["mean"]))
+                valu=valu_view("k_forward<float, false, 8>", m["kernel_ms"]["mean"]))
     achieved64 = d["alg_bytes"] / (d["kernel_ms"]["mean"] / 1e3) / 1e9
 
     line = dict(
@@ -587,7 +612,7 @@ def main():
                                              peak=HBM_PEAK_GBS, unit="GB/s",
                                              frac=achieved64 / HBM_PEAK_GBS,
                                              kernel_ms=d["kernel_ms"]["mean"],
-                                             valu=valu_view("k_forward<double, false>",
+                                             valu=valu_view("k_forward<double, false, 8>",
                                                             d["kernel_ms"]["mean"]))),
         roofline=roof,
         in_transit_fraction=None,
@@ -603,6 +628,7 @@ def main():
         line["per_vector_ld"] = per_vector_ld_leg(rr, wl, min(args.steps, 50), 5, lib)
         line["direct_model"] = direct_leg(rr, wl, min(args.steps, 20), 2)
         line["small_planet"] = small_planet_leg(rr, wl, min(args.steps, 20), 2)
+        line["variant_selection"] = variant_leg(rr, wl)
         line["loglik_grad"] = loglik_leg(rr, wl, 10, 2)
     if not args.no_cpu_baseline:
         cb, acc = cpu_baseline(w, grid, args.cpu_seconds, o64, o32)

@@ -17,6 +17,9 @@
  *                   g-interpolation x lens area -> supersample mean;
  *   rr_evaluate_ld  the same with a limb-darkening profile per parameter
  *                   vector (LD sampled with the orbit);
+ *   rr_evaluate_variant / rr_select_variant  one forward-kernel variant,
+ *                   and the trial run that picks the fastest for given
+ *                   inputs (Sect. 3.4.1);
  *   rr_evaluate_direct  the direct model: weights for each vector's own k,
  *                   no k-interpolation and no k limits (Sect. 3.1.1);
  *   rr_evaluate_small_planet  the small-planet approximation below a
@@ -75,6 +78,7 @@ extern "C" {
 #define RR_MAX_PB    16   /* passbands per table set                        */
 #define RR_MAX_LC    64   /* light curves per rr_evaluate call              */
 #define RR_MAX_NSS   1024 /* subsamples per exposure                        */
+#define RR_NUM_VARIANTS 6 /* forward-kernel variants (rr_evaluate_variant)  */
 
 /* Precision policies for rr_evaluate / rr_loglik_grad. */
 #define RR_FP64  0  /* every step in FP64; output double                  */
@@ -153,6 +157,50 @@ RR_API int rr_evaluate(const rr_tables* t, const double* times_d,
                        const double* exptimes, int32_t nlc,
                        const double* pv_d, int32_t npv, int32_t npar,
                        int32_t precision, void* out_d, hipStream_t stream);
+
+/* rr_evaluate with a chosen forward-kernel variant.  The variants differ
+ * only in how work maps onto the GPU, never in the arithmetic of an
+ * exposure, so every variant writes the values of rr_evaluate (bit for bit
+ * in FP64 and without supersampling; for supersampled series in RR_MIXED
+ * the float code of the two subsample paths may round differently, within
+ * the mixed path's accuracy):
+ *   variant 0, 1, 2   each lane owns 4, 8, 16 exposures (a workgroup, one
+ *                     wave64, owns 256, 512, 1024 consecutive times); the
+ *                     subsamples of supersampled exposures are spread over
+ *                     the lanes where a wave's flagged exposures share nss;
+ *   variant 3, 4, 5   the same tiles with every exposure's subsamples
+ *                     summed by one lane.
+ * rr_evaluate is variant 1.  Smaller tiles give more waves for small
+ * problems; larger ones amortise the per-tile work of long series.
+ * variant outside [0, RR_NUM_VARIANTS) is RR_EINVAL; other arguments,
+ * errors and memory as rr_evaluate. */
+RR_API int rr_evaluate_variant(const rr_tables* t, const double* times_d,
+                               const int32_t* lcids_d, int32_t npt,
+                               const int32_t* pbids, const int32_t* nss,
+                               const double* exptimes, int32_t nlc,
+                               const double* pv_d, int32_t npv, int32_t npar,
+                               int32_t precision, int32_t variant, void* out_d,
+                               hipStream_t stream);
+
+/* Trial-run selection of the implementation (Sect. 3.4.1, where the model
+ * times each implementation once after set-up and keeps the fastest): runs
+ * the per-vector set-up once, then for every variant one untimed forward
+ * launch and `reps` timed ones between two HIP events on `stream`, and
+ * writes the variant with the smallest mean time to *best (host int32) and,
+ * if ms is not NULL, the mean milliseconds per launch of each variant to
+ * ms[RR_NUM_VARIANTS] (host).  Without supersampling variants 3-5 launch
+ * the same kernels as 0-2, so only 0-2 run and ms[v + 3] = ms[v].  out_d
+ * (as rr_evaluate's) receives the fluxes.  Waits for `stream` to finish the
+ * trial before returning.  reps outside [1, 1000] or best == NULL is
+ * RR_EINVAL; other arguments, errors and memory as rr_evaluate; with
+ * npt == 0 or npv == 0 nothing runs, *best = 1 and ms is zeroed. */
+RR_API int rr_select_variant(const rr_tables* t, const double* times_d,
+                             const int32_t* lcids_d, int32_t npt,
+                             const int32_t* pbids, const int32_t* nss,
+                             const double* exptimes, int32_t nlc,
+                             const double* pv_d, int32_t npv, int32_t npar,
+                             int32_t precision, void* out_d, int32_t reps,
+                             int32_t* best, float* ms, hipStream_t stream);
 
 /* The direct model (Sect. 3.1.1): fluxes as rr_evaluate, but every
  * (vector, passband) gets the LD-weighted vector built from annulus weights

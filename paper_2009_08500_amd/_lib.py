@@ -75,6 +75,14 @@ def _declare(L):
                                      c_void_p, i32, c_void_p, i32, i32, i32, c_void_p,
                                      c_void_p]
     L.rr_evaluate_direct.restype = ctypes.c_int
+    L.rr_evaluate_variant.argtypes = [c_void_p, c_void_p, c_void_p, i32, c_void_p, c_void_p,
+                                      c_void_p, i32, c_void_p, i32, i32, i32, i32, c_void_p,
+                                      c_void_p]
+    L.rr_evaluate_variant.restype = ctypes.c_int
+    L.rr_select_variant.argtypes = [c_void_p, c_void_p, c_void_p, i32, c_void_p, c_void_p,
+                                    c_void_p, i32, c_void_p, i32, i32, i32, c_void_p, i32,
+                                    c_void_p, c_void_p, c_void_p]
+    L.rr_select_variant.restype = ctypes.c_int
     L.rr_evaluate_small_planet.argtypes = [c_void_p, c_void_p, c_void_p, i32, c_void_p,
                                            c_void_p, c_void_p, i32, c_void_p, i32, i32, dbl,
                                            i32, c_void_p, c_void_p]

@@ -151,10 +151,16 @@ class TimeSeries:
         return (lc, self.npt, _ptr(self.pbids), _ptr(self.nss), _ptr(self.exptimes), self.nlc)
 
 
-def evaluate(tables, series, pv, precision="fp64", out=None, stream=None):
+NUM_VARIANTS = 6
+
+
+def evaluate(tables, series, pv, precision="fp64", out=None, stream=None, variant=None):
     """Fluxes (npv, npt) for parameter rows ``pv`` (npv, 6 + npb):
     [t0, P, a, b, e, w, k_0 .. k_{npb-1}] (rr_evaluate).  Returns a device
-    tensor, float64 for "fp64" and float32 for "mixed"."""
+    tensor, float64 for "fp64" and float32 for "mixed".  ``variant`` (0-5,
+    see ``select_variant``) picks a forward-kernel variant
+    (rr_evaluate_variant); every variant gives the same values (to float
+    rounding for supersampled series in mixed precision)."""
     prec = PRECISIONS[precision]
     if not isinstance(series, TimeSeries):
         series = TimeSeries(series)
@@ -168,12 +174,46 @@ def evaluate(tables, series, pv, precision="fp64", out=None, stream=None):
     elif out.dtype != dtype or not out.is_contiguous() or out.numel() != npv * series.npt:
         raise ValueError("out has the wrong dtype, layout or size")
     lc, npt, pb, nss, ex, nlc = series.lc_args()
+    if variant is not None:
+        check(_lib.lib().rr_evaluate_variant(
+            tables.handle, ctypes.c_void_p(series.times.data_ptr()), lc, npt, pb, nss, ex, nlc,
+            ctypes.c_void_p(pv.data_ptr()), npv, npar, prec, int(variant),
+            ctypes.c_void_p(out.data_ptr()), _stream(stream)), "rr_evaluate_variant")
+        return out
     check(_lib.lib().rr_evaluate(tables.handle, ctypes.c_void_p(series.times.data_ptr()),
                                  lc, npt, pb, nss, ex, nlc,
                                  ctypes.c_void_p(pv.data_ptr()), npv, npar, prec,
                                  ctypes.c_void_p(out.data_ptr()), _stream(stream)),
           "rr_evaluate")
     return out
+
+
+def select_variant(tables, series, pv, precision="mixed", reps=20, stream=None):
+    """Trial-run selection of the forward-kernel variant (rr_select_variant,
+    the GPU form of Sect. 3.4.1's choice among implementations): times
+    every variant on these inputs (``reps`` launches each, after one
+    untimed) and returns (best, ms) with ms[v] the mean milliseconds per
+    forward launch of variant v.  Variants 0, 1, 2 give each lane 4, 8, 16
+    exposures (1 is rr_evaluate's); 3, 4, 5 are the same with supersampled
+    exposures evaluated one per lane instead of spread over lanes.  Waits
+    for the stream."""
+    prec = PRECISIONS[precision]
+    if not isinstance(series, TimeSeries):
+        series = TimeSeries(series)
+    pv = _dev(pv, torch.float64)
+    if pv.dim() == 1:
+        pv = pv.unsqueeze(0)
+    npv, npar = pv.shape
+    dtype = torch.float64 if prec == RR_FP64 else torch.float32
+    out = torch.empty((npv, series.npt), dtype=dtype, device=pv.device)
+    lc, npt, pb, nss, ex, nlc = series.lc_args()
+    best = ctypes.c_int32(-1)
+    ms = (ctypes.c_float * NUM_VARIANTS)()
+    check(_lib.lib().rr_select_variant(
+        tables.handle, ctypes.c_void_p(series.times.data_ptr()), lc, npt, pb, nss, ex, nlc,
+        ctypes.c_void_p(pv.data_ptr()), npv, npar, prec, ctypes.c_void_p(out.data_ptr()),
+        int(reps), ctypes.byref(best), ms, _stream(stream)), "rr_select_variant")
+    return best.value, [float(x) for x in ms]
 
 
 def evaluate_direct(tables, series, pv, precision="fp64", out=None, stream=None):
@@ -287,9 +327,11 @@ class Evaluator:
     """rr_evaluate for repeated calls with populations of one size over one
     time series (the MCMC pattern): every argument except the parameter
     rows is marshalled once, and the output buffer is reused.  Calls enqueue
-    on the stream current at construction (or ``stream``)."""
+    on the stream current at construction (or ``stream``).  ``variant``
+    fixes a forward-kernel variant (``select_variant``); ``select(pv)``
+    chooses it by a trial run on the given rows."""
 
-    def __init__(self, tables, series, npv, precision="mixed", stream=None):
+    def __init__(self, tables, series, npv, precision="mixed", stream=None, variant=None):
         if not isinstance(series, TimeSeries):
             series = TimeSeries(series)
         self.tables, self.series, self.npv = tables, series, int(npv)
@@ -299,9 +341,31 @@ class Evaluator:
         self.out = torch.empty((self.npv, series.npt), dtype=dtype, device="cuda")
         lc, npt, pb, nss, ex, nlc = series.lc_args()
         s = torch.cuda.current_stream() if stream is None else stream
-        self._fn = _lib.lib().rr_evaluate
-        self._args = [tables.handle, series.times.data_ptr(), lc, npt, pb, nss, ex, nlc,
-                      None, self.npv, self.npar, self.prec, self.out.data_ptr(), s.cuda_stream]
+        self._stream = s
+        self._base = [tables.handle, series.times.data_ptr(), lc, npt, pb, nss, ex, nlc,
+                      None, self.npv, self.npar, self.prec]
+        self._set_variant(variant)
+
+    def _set_variant(self, variant):
+        self.variant = variant
+        if variant is None:
+            self._fn = _lib.lib().rr_evaluate
+            self._args = self._base + [self.out.data_ptr(), self._stream.cuda_stream]
+        else:
+            if not 0 <= int(variant) < NUM_VARIANTS:
+                raise ValueError("variant must lie in [0, 6)")
+            self._fn = _lib.lib().rr_evaluate_variant
+            self._args = self._base + [int(variant), self.out.data_ptr(),
+                                       self._stream.cuda_stream]
+
+    def select(self, pv, reps=20):
+        """Trial run of every variant on rows ``pv`` (``select_variant``);
+        later calls use the fastest.  Returns (best, ms)."""
+        with torch.cuda.stream(self._stream):
+            best, ms = select_variant(self.tables, self.series, pv,
+                                      "fp64" if self.prec == RR_FP64 else "mixed", reps)
+        self._set_variant(best)
+        return best, ms
 
     def __call__(self, pv):
         """Fluxes (npv, npt) for a contiguous float64 device tensor of rows."""

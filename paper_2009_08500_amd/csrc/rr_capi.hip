@@ -121,7 +121,8 @@ int check_eval_args(const rr_tables* t, const double* times_d,
     }
     const int64_t ntiles = (int64_t(npt) + kAdjTile - 1) / kAdjTile;   // the larger tiles
     if (ntiles * npv * kAdjBlock >= (int64_t(1) << 32) ||
-        ((int64_t(npt) + kFwdTile - 1) / kFwdTile) * npv * kFwdBlock >= (int64_t(1) << 32))
+        ((int64_t(npt) + 4 * kFwdBlock - 1) / (4 * kFwdBlock)) * npv * kFwdBlock >=
+            (int64_t(1) << 32))                  // the smallest forward tile (J = 4)
         return elimit("npv * npt too large for one launch");
     return RR_OK;
 }
@@ -264,6 +265,100 @@ RR_API int rr_evaluate(const rr_tables* t, const double* times_d,
         e = launch_forward(t, times_d, lcids_d, npt, lc, pv_d, npv, npar, pvc,
                            precision, out_d, stream);
     if (e != hipSuccess) return hip_fail(e, "forward kernels");
+    return RR_OK;
+}
+
+RR_API int rr_evaluate_variant(const rr_tables* t, const double* times_d,
+                               const int32_t* lcids_d, int32_t npt,
+                               const int32_t* pbids, const int32_t* nss,
+                               const double* exptimes, int32_t nlc,
+                               const double* pv_d, int32_t npv, int32_t npar,
+                               int32_t precision, int32_t variant, void* out_d,
+                               hipStream_t stream) {
+    if (variant < 0 || variant >= RR_NUM_VARIANTS) return einval("unknown variant");
+    LcInfo lc;
+    int rc = check_eval_args(t, times_d, lcids_d, npt, pbids, nss, exptimes, nlc,
+                             pv_d, npv, npar, precision, &lc);
+    if (rc) return rc;
+    if (npt == 0 || npv == 0) return RR_OK;
+    if (!out_d) return einval("out is NULL");
+    rc = check_device(t);
+    if (rc) return rc;
+    void* ws = nullptr;
+    hipError_t e = stream_workspace(const_cast<rr_tables*>(t), stream,
+                                    sizeof(PvConst) * size_t(npv), &ws);
+    if (e != hipSuccess) return e == hipErrorOutOfMemory ? RR_ENOMEM : hip_fail(e, "workspace");
+    PvConst* pvc = static_cast<PvConst*>(ws);
+    e = launch_pv_setup(t, pv_d, npv, npar, pvc, stream);
+    if (e == hipSuccess)
+        e = launch_forward(t, times_d, lcids_d, npt, lc, pv_d, npv, npar, pvc, precision,
+                           out_d, stream, nullptr, nullptr, 0, variant);
+    if (e != hipSuccess) return hip_fail(e, "forward kernels");
+    return RR_OK;
+}
+
+RR_API int rr_select_variant(const rr_tables* t, const double* times_d,
+                             const int32_t* lcids_d, int32_t npt,
+                             const int32_t* pbids, const int32_t* nss,
+                             const double* exptimes, int32_t nlc,
+                             const double* pv_d, int32_t npv, int32_t npar,
+                             int32_t precision, void* out_d, int32_t reps,
+                             int32_t* best, float* ms, hipStream_t stream) {
+    if (!best) return einval("best is NULL");
+    if (reps < 1 || reps > 1000) return einval("reps must lie in [1, 1000]");
+    LcInfo lc;
+    int rc = check_eval_args(t, times_d, lcids_d, npt, pbids, nss, exptimes, nlc,
+                             pv_d, npv, npar, precision, &lc);
+    if (rc) return rc;
+    *best = kDefaultFwdVariant;
+    if (ms)
+        for (int v = 0; v < RR_NUM_VARIANTS; ++v) ms[v] = 0.0f;
+    if (npt == 0 || npv == 0) return RR_OK;
+    if (!out_d) return einval("out is NULL");
+    rc = check_device(t);
+    if (rc) return rc;
+    void* ws = nullptr;
+    hipError_t e = stream_workspace(const_cast<rr_tables*>(t), stream,
+                                    sizeof(PvConst) * size_t(npv), &ws);
+    if (e != hipSuccess) return e == hipErrorOutOfMemory ? RR_ENOMEM : hip_fail(e, "workspace");
+    PvConst* pvc = static_cast<PvConst*>(ws);
+    e = launch_pv_setup(t, pv_d, npv, npar, pvc, stream);
+    if (e != hipSuccess) return hip_fail(e, "setup kernel");
+    // without supersampling the one-lane-per-exposure variants launch the
+    // same kernels as the others: only J is tried
+    bool sub = false;
+    for (int l = 0; l < lc.nlc; ++l) sub = sub || lc.nss[l] > 1;
+    const int nv = sub ? RR_NUM_VARIANTS : 3;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    float tbest = 0.0f;
+    for (int v = 0; v < nv && e == hipSuccess; ++v) {
+        // one untimed launch, then reps launches between two events
+        e = launch_forward(t, times_d, lcids_d, npt, lc, pv_d, npv, npar, pvc, precision,
+                           out_d, stream, nullptr, nullptr, 0, v);
+        if (e == hipSuccess) e = hipEventRecord(e0, stream);
+        for (int r = 0; r < reps && e == hipSuccess; ++r)
+            e = launch_forward(t, times_d, lcids_d, npt, lc, pv_d, npv, npar, pvc, precision,
+                               out_d, stream, nullptr, nullptr, 0, v);
+        if (e == hipSuccess) e = hipEventRecord(e1, stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float el = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&el, e0, e1);
+        if (e != hipSuccess) break;
+        el /= float(reps);
+        if (ms) {
+            ms[v] = el;
+            if (!sub) ms[v + 3] = el;
+        }
+        if (v == 0 || el < tbest) {
+            tbest = el;
+            *best = v;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return hip_fail(e, "variant trial");
     return RR_OK;
 }
 

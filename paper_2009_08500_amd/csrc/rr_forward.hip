@@ -29,6 +29,11 @@
 namespace rr {
 namespace {
 
+// Exposures per lane (J) of the forward kernel's variants: the tile of a
+// workgroup is 64 J consecutive times.  J is a multiple of 4 (pass 1 packs
+// 4 float or 2 double outputs per 16-B store) and at most 32 (a lane's
+// flags fit one 32-bit mask).
+constexpr int kFwdJ[3] = {4, 8, 16};
 static_assert(kTimesPerThread % 4 == 0 && kTimesPerThread <= 32,
               "pass 1 packs 4 float or 2 double outputs per 16-B store");
 
@@ -135,28 +140,28 @@ __device__ inline R exposure_flux(const PvConst& p, const OrbitR<R>& orb, const 
 }
 
 // The work of one workgroup: population row ipv, time tile `tile`.  Each
-// wave64 owns 64 kTimesPerThread consecutive exposures of the tile and works
+// wave64 owns 64 J consecutive exposures of the tile and works
 // on its own, with no workgroup barrier: a wave whose exposures all lie
 // outside the transit window stores ones and ends.
-template <typename R, bool kSubPar>
+template <typename R, bool kSubPar, int J>
 __device__ inline void forward_block(const FwdJob& job, const LcInfo& lc, int ipv,
                                      int tile, const GridDev& g,
                                      const R* __restrict__ T,
                                      const double* __restrict__ inv_istar) {
-    constexpr int kSpan = 64 * kTimesPerThread;           // exposures per wave
+    constexpr int kSpan = 64 * J;           // exposures per wave
     const int lane = threadIdx.x & 63;
     const int npt = job.npt, npar = job.npar;
     const double* __restrict__ times = job.times;
     const int32_t* __restrict__ lcids = job.lcids;
     const double* __restrict__ pv = job.pv;
     // exposure r of this lane (pass 2 order, and pass 1 off the fast path)
-    const int w0 = tile * kFwdTile + (threadIdx.x >> 6) * kSpan;
+    const int w0 = tile * (kFwdBlock * J) + (threadIdx.x >> 6) * kSpan;
     const int t_base = w0 + lane;
     R* __restrict__ orow = static_cast<R*>(job.out) + int64_t(ipv) * npt;
     const PvConst p = job.pvc[ipv];
 
     if (!(p.flags & kValid)) {
-        for (int r = 0; r < kTimesPerThread; ++r) {
+        for (int r = 0; r < J; ++r) {
             const int it = t_base + 64 * r;
             if (it < npt) orow[it] = R(NAN);
         }
@@ -167,7 +172,7 @@ __device__ inline void forward_block(const FwdJob& job, const LcInfo& lc, int ip
     // of `todo` marks exposure t_base + 64 r as one that may overlap it.
     uint32_t todo = 0;
     constexpr int kVec = 16 / int(sizeof(R));            // outputs per 16-B store
-    constexpr int kGroups = kTimesPerThread / kVec;
+    constexpr int kGroups = J / kVec;
     bool vec = w0 + kSpan <= npt &&
                ((reinterpret_cast<uintptr_t>(orow + w0) | reinterpret_cast<uintptr_t>(times) |
                  reinterpret_cast<uintptr_t>(lcids)) & 15) == 0;
@@ -198,7 +203,7 @@ __device__ inline void forward_block(const FwdJob& job, const LcInfo& lc, int ip
         // no bounds or light-curve checks.  Phase g = t/P + c0 with
         // c0 = -t0/P - (window start) by one FMA.
         typedef R RV __attribute__((ext_vector_type(kVec)));
-        double tv[kTimesPerThread];
+        double tv[J];
 #pragma unroll
         for (int q = 0; q < kGroups; ++q) {
             const double* tp = times + w0 + q * (64 * kVec) + lane * kVec;
@@ -234,17 +239,17 @@ __device__ inline void forward_block(const FwdJob& job, const LcInfo& lc, int ip
                 todo |= ((x >> (q * kVec + lane % kVec)) & 1u) << (q * kVec + sidx);
         }
     } else {
-        double tv[kTimesPerThread];
-        int lv[kTimesPerThread];
+        double tv[J];
+        int lv[J];
 #pragma unroll
-        for (int r = 0; r < kTimesPerThread; ++r) {
+        for (int r = 0; r < J; ++r) {
             const int it = t_base + 64 * r;
             tv[r] = it < npt ? times[it] : 0.0;
             lv[r] = (lcids && it < npt) ? lcids[it] : 0;
         }
         const double hw0 = 0.5 * lc.exptime[0] * p.invP;
 #pragma unroll
-        for (int r = 0; r < kTimesPerThread; ++r) {
+        for (int r = 0; r < J; ++r) {
             const int it = t_base + 64 * r;
             if (it >= npt) continue;
             const int l = lv[r];
@@ -322,13 +327,13 @@ __device__ inline void forward_block(const FwdJob& job, const LcInfo& lc, int ip
             pass2_pairs();
             return;
         }
-        if (nmin == nmax && N >= 2 && N <= 32) {
+        if (job.spread && nmin == nmax && N >= 2 && N <= 32) {
             __shared__ uint16_t packed[kFwdBlock / 64][kSpan];
             uint16_t* pk = packed[threadIdx.x >> 6];
             const uint64_t below = __lanemask_lt();
             int total = 0;
 #pragma unroll
-            for (int r = 0; r < kTimesPerThread; ++r) {
+            for (int r = 0; r < J; ++r) {
                 const uint64_t m = __ballot((todo >> r) & 1u);
                 if ((todo >> r) & 1u) pk[total + __popcll(m & below)] = uint16_t(64 * r + lane);
                 total += __popcll(m);
@@ -382,15 +387,15 @@ __device__ inline void forward_block(const FwdJob& job, const LcInfo& lc, int ip
     }
 }
 
-// One population (rr_evaluate): workgroup (x, y) -> row pv0 + y, tile x.
-// kSubPar: some light curve has nss > 1.
-template <typename R, bool kSubPar>
+// One population (rr_evaluate): workgroup (x, y) -> row pv0 + y, tile x of
+// 64 J times.  kSubPar: some light curve has nss > 1.
+template <typename R, bool kSubPar, int J>
 __global__ __launch_bounds__(kFwdBlock) void k_forward(FwdJob job, LcInfo lc, GridDev g,
                                                     const R* __restrict__ T,
                                                     const double* __restrict__ inv_istar) {
     const int ipv = job.pv0 + blockIdx.y;
     const int tile = blockIdx.x;
-    forward_block<R, kSubPar>(job, lc, ipv, tile, g, T, inv_istar);
+    forward_block<R, kSubPar, J>(job, lc, ipv, tile, g, T, inv_istar);
 }
 
 // Grouped launch (serving): workgroup b belongs to the last job whose
@@ -407,7 +412,7 @@ __global__ __launch_bounds__(kFwdBlock) void k_forward_jobs(JobTable jt, GridDev
     const int local = b - job.block0;
     const int ipv = job.pv0 + local / job.ntiles;
     const int tile = local - (local / job.ntiles) * job.ntiles;
-    forward_block<R, kSubPar>(job, *job.lc, ipv, tile, g, T, inv_istar);
+    forward_block<R, kSubPar, kTimesPerThread>(job, *job.lc, ipv, tile, g, T, inv_istar);
 }
 
 // Eq. 5 at given separations (the model as a function of z and k, the
@@ -467,18 +472,40 @@ hipError_t launch_pv_setup_k(const double* pv, int32_t npv, int32_t npar, double
     return hipGetLastError();
 }
 
+// One launch of k_forward for J exposures per lane.
+template <typename R>
+hipError_t launch_forward_j(int J, bool sub, dim3 grid, dim3 block, hipStream_t s,
+                            hipEvent_t st, hipEvent_t sp, const FwdJob& job, const LcInfo& lc,
+                            const GridDev& g, const R* T, const double* inv_istar) {
+    switch (J * 2 + (sub ? 1 : 0)) {
+        case 8: launch_timed(k_forward<R, false, 4>, grid, block, 0, s, st, sp, job, lc, g, T, inv_istar); break;
+        case 9: launch_timed(k_forward<R, true, 4>, grid, block, 0, s, st, sp, job, lc, g, T, inv_istar); break;
+        case 16: launch_timed(k_forward<R, false, 8>, grid, block, 0, s, st, sp, job, lc, g, T, inv_istar); break;
+        case 17: launch_timed(k_forward<R, true, 8>, grid, block, 0, s, st, sp, job, lc, g, T, inv_istar); break;
+        case 32: launch_timed(k_forward<R, false, 16>, grid, block, 0, s, st, sp, job, lc, g, T, inv_istar); break;
+        case 33: launch_timed(k_forward<R, true, 16>, grid, block, 0, s, st, sp, job, lc, g, T, inv_istar); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_forward(const rr_tables* t, const double* times,
                           const int32_t* lcids, int32_t npt, const LcInfo& lc,
                           const double* pv, int32_t npv, int32_t npar,
                           const PvConst* pvc, int32_t precision, void* out,
                           hipStream_t s, const void* ldw_pv, const double* inv_istar_pv,
-                          int32_t ldw_exact_k) {
+                          int32_t ldw_exact_k, int32_t variant) {
     const GridDev g = grid_dev(t);
+    // variant (rr_evaluate_variant): J = kFwdJ[v % 3]; v >= 3 evaluates
+    // supersampled exposures one per lane instead of spreading subsamples
+    if (variant < 0 || variant >= kNumFwdVariants) variant = kDefaultFwdVariant;
+    const int J = kFwdJ[variant % 3];
     FwdJob job;
     job.ldw_pv = ldw_pv; job.inv_istar_pv = inv_istar_pv; job.ldw_exact_k = ldw_exact_k;
+    job.spread = variant < 3 ? 1 : 0;
     job.times = times; job.lcids = lcids; job.lc = nullptr; job.pv = pv; job.pvc = pvc;
     job.out = out; job.npt = npt; job.npar = npar; job.pv0 = 0; job.npv = npv;
-    job.ntiles = (npt + kFwdTile - 1) / kFwdTile; job.block0 = 0; job.max_nss = 1;
+    job.ntiles = (npt + kFwdBlock * J - 1) / (kFwdBlock * J); job.block0 = 0; job.max_nss = 1;
     for (int l = 0; l < lc.nlc; ++l) job.max_nss = lc.nss[l] > job.max_nss ? lc.nss[l] : job.max_nss;
     const KernelEvents ev = kernel_events();
     const bool sub = job.max_nss > 1;
@@ -489,21 +516,13 @@ hipError_t launch_forward(const rr_tables* t, const double* times,
         const dim3 block(kFwdBlock);
         hipEvent_t st = r0 == 0 ? ev.before : nullptr;
         hipEvent_t sp = npv - r0 <= 65535 ? ev.after : nullptr;
-        if (precision == RR_FP64) {
-            if (sub)
-                launch_timed(k_forward<double, true>, grid, block, 0, s, st, sp, job, lc, g,
-                             t->T64, t->inv_istar);
-            else
-                launch_timed(k_forward<double, false>, grid, block, 0, s, st, sp, job, lc, g,
-                             t->T64, t->inv_istar);
-        } else {
-            if (sub)
-                launch_timed(k_forward<float, true>, grid, block, 0, s, st, sp, job, lc, g,
-                             t->T32, t->inv_istar);
-            else
-                launch_timed(k_forward<float, false>, grid, block, 0, s, st, sp, job, lc, g,
-                             t->T32, t->inv_istar);
-        }
+        const hipError_t e =
+            precision == RR_FP64
+                ? launch_forward_j<double>(J, sub, grid, block, s, st, sp, job, lc, g, t->T64,
+                                           t->inv_istar)
+                : launch_forward_j<float>(J, sub, grid, block, s, st, sp, job, lc, g, t->T32,
+                                          t->inv_istar);
+        if (e != hipSuccess) return e;
     }
     return hipGetLastError();
 }

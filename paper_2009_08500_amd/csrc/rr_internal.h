@@ -73,7 +73,16 @@ struct FwdJob {
     const void* ldw_pv;
     const double* inv_istar_pv;   // NULL: the tables' 1/I_star
     int32_t ldw_exact_k;          // 1: ldw_pv rows are for the row's exact k (direct model)
+    int32_t spread;               // 1: supersampled exposures may spread over lanes
 };
+// Forward-kernel variants (rr_evaluate_variant): exposures per lane
+// J = 4, 8, 16 for v = 0, 1, 2 with subsamples spread over lanes where
+// possible, the same J with one lane per exposure for v = 3, 4, 5.
+constexpr int kNumFwdVariants = 6;
+static_assert(kTimesPerThread == 4 || kTimesPerThread == 8 || kTimesPerThread == 16,
+              "the default forward variant has J = kTimesPerThread");
+constexpr int kDefaultFwdVariant =        // rr_evaluate: J = kTimesPerThread, spreading
+    kTimesPerThread == 4 ? 0 : (kTimesPerThread == 8 ? 1 : 2);
 constexpr int kMaxJobs = 24;   // jobs per grouped launch (kernel arguments)
 struct JobTable {
     int32_t njobs;
@@ -216,7 +225,8 @@ hipError_t launch_forward(const rr_tables* t, const double* times,
                           const double* pv, int32_t npv, int32_t npar,
                           const PvConst* pvc, int32_t precision, void* out,
                           hipStream_t s, const void* ldw_pv = nullptr,
-                          const double* inv_istar_pv = nullptr, int32_t ldw_exact_k = 0);
+                          const double* inv_istar_pv = nullptr, int32_t ldw_exact_k = 0,
+                          int32_t variant = kDefaultFwdVariant);
 // Direct model (rr_evaluate_direct): each (vector, passband) row's
 // LD-weighted vector for its own k, rows [npv][npb][2][ng] by precision.
 hipError_t launch_direct_rows(const rr_tables* t, const double* pv, int32_t npv, int32_t npar,

@@ -271,7 +271,7 @@ bool rr_server::step() {
                 j.pvc = r->pvc_dev; j.out = r->out_dev; j.npt = se.npt; j.npar = r->npar;
                 j.pv0 = r->next_row; j.npv = rows; j.ntiles = se.ntiles; j.block0 = nb[p];
                 j.max_nss = se.max_nss;
-                j.ldw_pv = nullptr; j.inv_istar_pv = nullptr; j.ldw_exact_k = 0;
+                j.ldw_pv = nullptr; j.inv_istar_pv = nullptr; j.ldw_exact_k = 0; j.spread = 1;
                 nb[p] += rows * se.ntiles;
                 left -= rows * se.ntiles;
                 r->next_row += rows;

@@ -1,0 +1,100 @@
+"""Forward-kernel variants and their trial-run selection (Sect. 3.4.1)
+through the C ABI: every variant (4, 8 or 16 exposures per lane;
+subsamples spread over lanes or summed by one lane) writes the values of
+rr_evaluate -- bit for bit without supersampling and in FP64, to float
+rounding for supersampled series in mixed precision -- and meets the
+oracle's tolerances; the trial run reports a time for every variant and
+picks the fastest."""
+
+import numpy as np
+import pytest
+
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rr():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2009_08500_amd as rr
+    return rr
+
+
+@pytest.mark.parametrize("npt", [700, 2049, 20000])
+def test_variants_equal_evaluate(rr, npt):
+    w = wl.population(npv=24, npt=npt)
+    tab = rr.Tables(w["mu_s"], w["I_s"], wl.DEFAULT_GRID)
+    ser = rr.TimeSeries(w["times"])
+    pv = w["pv"].copy()
+    pv[3, 6] = 0.5                                    # an invalid row (k > k1)
+    for prec in ("fp64", "mixed"):
+        ref = rr.evaluate(tab, ser, pv, prec).cpu().numpy()
+        assert np.isnan(ref[3]).all() and (ref < 1.0).any()
+        for v in range(rr.NUM_VARIANTS):
+            out = rr.evaluate(tab, ser, pv, prec, variant=v).cpu().numpy()
+            assert np.array_equal(out, ref, equal_nan=True), (prec, v)
+
+
+def test_supersampled_variants(rr):
+    """Four passbands, nss 10 and 1.  In FP64 spreading subsamples over
+    lanes and one lane per exposure give the same bits (the same terms
+    summed in the same order).  In mixed precision the float arithmetic of
+    the two code paths may be contracted differently by the compiler, and
+    the tile size decides which path an exposure near a light-curve
+    boundary takes, so the variants agree to float rounding; every variant
+    is held to the oracle as rr_evaluate is."""
+    from oracle import roadrunner as orr
+    w = wl.heterogeneous(npv=8, days=3.0)
+    kw = dict(lcids=w["lcids"], pbids=w["pbids"], nss=w["nss"], exptimes=w["exptimes"])
+    tab = rr.Tables(w["mu_s"], w["I_s"], wl.TEST_GRID)
+    otab = orr.Tables(w["mu_s"], w["I_s"], **wl.TEST_GRID)
+    ser = rr.TimeSeries(w["times"], w["lcids"], w["pbids"], w["nss"], w["exptimes"])
+    oref = orr.evaluate(otab, w["times"], w["pv"], **kw)
+    assert (oref < 1.0).any()
+    ref64 = rr.evaluate(tab, ser, w["pv"], "fp64").cpu().numpy()
+    ref32 = rr.evaluate(tab, ser, w["pv"], "mixed").cpu().numpy().astype(np.float64)
+    for v in range(rr.NUM_VARIANTS):
+        o64 = rr.evaluate(tab, ser, w["pv"], "fp64", variant=v).cpu().numpy()
+        o32 = rr.evaluate(tab, ser, w["pv"], "mixed", variant=v).cpu().numpy().astype(np.float64)
+        assert np.array_equal(o64, ref64), v
+        assert np.abs(o32 - ref32).max() <= 1e-6, (v, np.abs(o32 - ref32).max())
+        assert np.abs(o64 - oref).max() <= 1e-9
+        assert np.abs(o32 - oref).max() <= 1e-6
+        out = oref == 1.0
+        assert np.all(o64[out] == 1.0) and np.all(o32[out] == 1.0)
+
+
+def test_select_variant_and_evaluator(rr):
+    import torch
+    w = wl.population(npv=64, npt=5000)
+    tab = rr.Tables(w["mu_s"], w["I_s"], wl.DEFAULT_GRID)
+    ser = rr.TimeSeries(w["times"])
+    pv = torch.as_tensor(w["pv"], device="cuda")
+    best, ms = rr.select_variant(tab, ser, pv, "mixed", reps=5)
+    assert 0 <= best < 3                        # no supersampling: variants 0-2
+    assert all(m > 0.0 for m in ms) and ms[3:] == ms[:3]
+    assert ms[best] == min(ms)
+    ev = rr.Evaluator(tab, ser, 64, "mixed")
+    ref = ev(pv).clone()
+    b2, _ = ev.select(pv, reps=3)
+    assert ev.variant == b2
+    assert torch.equal(ev(pv), ref)
+    wh = wl.heterogeneous(npv=8, days=3.0)
+    tabh = rr.Tables(wh["mu_s"], wh["I_s"], wl.DEFAULT_GRID)
+    serh = rr.TimeSeries(wh["times"], wh["lcids"], wh["pbids"], wh["nss"], wh["exptimes"])
+    best, ms = rr.select_variant(tabh, serh, wh["pv"], "fp64", reps=2)
+    assert 0 <= best < rr.NUM_VARIANTS and all(m > 0.0 for m in ms)
+
+
+def test_bad_variant_arguments(rr):
+    w = wl.population(npv=2, npt=100)
+    tab = rr.Tables(w["mu_s"], w["I_s"], wl.TEST_GRID)
+    ser = rr.TimeSeries(w["times"])
+    for v in (-1, rr.NUM_VARIANTS):
+        with pytest.raises(rr.RRError):
+            rr.evaluate(tab, ser, w["pv"], "fp64", variant=v)
+    with pytest.raises(rr.RRError):
+        rr.select_variant(tab, ser, w["pv"], "fp64", reps=0)
