@@ -329,9 +329,12 @@ class Evaluator:
     rows is marshalled once, and the output buffer is reused.  Calls enqueue
     on the stream current at construction (or ``stream``).  ``variant``
     fixes a forward-kernel variant (``select_variant``); ``select(pv)``
-    chooses it by a trial run on the given rows."""
+    chooses it by a trial run on the given rows, and ``auto_select=True``
+    runs that trial on the first call's rows, as the paper's model does
+    after set-up (Sect. 3.4.1)."""
 
-    def __init__(self, tables, series, npv, precision="mixed", stream=None, variant=None):
+    def __init__(self, tables, series, npv, precision="mixed", stream=None, variant=None,
+                 auto_select=False):
         if not isinstance(series, TimeSeries):
             series = TimeSeries(series)
         self.tables, self.series, self.npv = tables, series, int(npv)
@@ -345,6 +348,7 @@ class Evaluator:
         self._base = [tables.handle, series.times.data_ptr(), lc, npt, pb, nss, ex, nlc,
                       None, self.npv, self.npar, self.prec]
         self._set_variant(variant)
+        self._auto = bool(auto_select) and variant is None
 
     def _set_variant(self, variant):
         self.variant = variant
@@ -372,6 +376,9 @@ class Evaluator:
         if (pv.dtype is not torch.float64 or not pv.is_cuda or not pv.is_contiguous()
                 or pv.numel() != self.npv * self.npar):
             raise ValueError("pv must be a float64 device tensor of shape (npv, npar)")
+        if self._auto:
+            self._auto = False
+            self.select(pv)
         a = self._args
         a[8] = pv.data_ptr()
         rc = self._fn(*a)

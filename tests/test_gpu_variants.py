@@ -82,6 +82,9 @@ def test_select_variant_and_evaluator(rr):
     b2, _ = ev.select(pv, reps=3)
     assert ev.variant == b2
     assert torch.equal(ev(pv), ref)
+    ev2 = rr.Evaluator(tab, ser, 64, "mixed", auto_select=True)
+    assert ev2.variant is None
+    assert torch.equal(ev2(pv), ref) and ev2.variant in (0, 1, 2)
     wh = wl.heterogeneous(npv=8, days=3.0)
     tabh = rr.Tables(wh["mu_s"], wh["I_s"], wl.DEFAULT_GRID)
     serh = rr.TimeSeries(wh["times"], wh["lcids"], wh["pbids"], wh["nss"], wh["exptimes"])
