@@ -9,8 +9,9 @@
 //               the planet is either behind the star or farther than 1 + k
 //               from its centre, so the flux is exactly 1 (kept in phase
 //               units, so the test is frac(phase - lo) < width);
-//   k_forward   one wave64 workgroup per (parameter vector, tile of 512
-//               consecutive times), lanes along time so loads of the shared
+//   k_forward   one wave64 workgroup per (parameter vector, tile of 64 J
+//               consecutive times; J = 8 by default, 4 or 16 in the variants
+//               of rr_evaluate_variant), lanes along time so loads of the shared
 //               time array and the stores of out[pv][t] are coalesced; each
 //               wave runs alone (no LDS, no barrier).  Pass 1 reduces each
 //               mid-exposure time to an offset from conjunction (FP64),
