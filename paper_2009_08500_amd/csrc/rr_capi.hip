@@ -415,7 +415,7 @@ RR_API int rr_evaluate_small_planet(const rr_tables* t, const double* times_d,
     if (npt == 0 || npv == 0) return RR_OK;
     if (!out_d) return einval("out is NULL");
     const int64_t nr = int64_t(npv) * t->npb;
-    if (nr * t->grid.ng >= (int64_t(1) << 36)) return elimit("npv * npb too large");
+    if (nr >= (int64_t(1) << 31)) return elimit("npv * npb too large");
     rc = check_device(t);
     if (rc) return rc;
     const size_t elt = precision == RR_FP64 ? sizeof(double) : sizeof(float);

@@ -442,28 +442,42 @@ __global__ __launch_bounds__(kBlock) void k_direct_rows(const double* __restrict
 // c = g_m (1 + k) clamped to the limb (mu = sqrt(1 - c^2) on the tables'
 // piecewise-linear profile); any other row gets the shared table's two
 // k-rows around its k combined with its k-weight, in the evaluation
-// precision and in the order the forward kernel combines them.  Thread per
-// (row, m); stored twice ([2][ng]), read with zero k-weight.
+// precision and in the order the forward kernel combines them.  Workgroup
+// (row, kBlock nodes): a small-planet row stages the mu samples and its
+// passband's profile in LDS (when they fit) for the binary searches.
+// Stored twice ([2][ng]), read with zero k-weight.
+constexpr int kSpLds = 1024;
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_small_planet_rows(
     const double* __restrict__ mu_s, const double* __restrict__ prof, int32_t nmu,
     const R* __restrict__ T, const double* __restrict__ pv, int32_t npar, double k_small,
-    double k1, int64_t nrows, GridDev g, R* __restrict__ out) {
-    const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-    if (i >= nrows * g.ng) return;
-    const int64_t r = i / g.ng;
-    const int m = int(i - r * g.ng);
+    double k1, GridDev g, R* __restrict__ out) {
+    __shared__ double smu[kSpLds], sf[kSpLds];
+    const int64_t r = blockIdx.x;
+    const int m = int(blockIdx.y) * kBlock + int(threadIdx.x);
     const int64_t ipv = r / g.npb;
     const int pb = int(r - ipv * g.npb);
-    const double k = pv[ipv * npar + 6 + pb];
-    R v = R(0);                              // invalid rows: the forward writes NaN
+    const double k = pv[ipv * npar + 6 + pb];          // uniform in the workgroup
+    R* o = out + r * 2 * g.ng;
+    R v = R(0);                                        // invalid rows: the forward writes NaN
     if (k < k_small) {
         if (k > 0.0) {
+            const double* f = prof + int64_t(pb) * nmu;
+            const bool staged = nmu <= kSpLds;
+            if (staged) {
+                for (int j = threadIdx.x; j < nmu; j += kBlock) {
+                    smu[j] = mu_s[j];
+                    sf[j] = f[j];
+                }
+                __syncthreads();
+            }
+            if (m >= g.ng) return;
             double c = (double(m) / double(g.ng - 1)) * (1.0 + k);
             c = c < 1.0 ? c : 1.0;
-            v = R(profile_at_bin(mu_s, prof + int64_t(pb) * nmu, nmu, c));
+            v = R(staged ? profile_at_bin(smu, sf, nmu, c) : profile_at_bin(mu_s, f, nmu, c));
         }
     } else if (k >= g.k0 && k <= k1) {
+        if (m >= g.ng) return;
         const double u = (k - g.k0) / g.dk;
         int ik = int(floor(u));
         ik = ik < 0 ? 0 : (ik > g.nk - 2 ? g.nk - 2 : ik);
@@ -471,7 +485,7 @@ __global__ __launch_bounds__(kBlock) void k_small_planet_rows(
         const R* t0r = T + (int64_t(pb) * g.nk + ik) * g.ng;
         v = (R(1) - ak) * t0r[m] + ak * t0r[g.ng + m];
     }
-    R* o = out + r * 2 * g.ng;
+    if (m >= g.ng) return;
     o[m] = v;
     o[g.ng + m] = v;
 }
@@ -495,14 +509,14 @@ hipError_t launch_small_planet_rows(const rr_tables* t, const double* pv, int32_
                                     void* rows, hipStream_t s) {
     const GridDev g = grid_dev(t);
     const int64_t nr = int64_t(npv) * t->npb;
-    const dim3 grid(nblocks(nr * g.ng));
+    const dim3 grid(unsigned(nr), unsigned((g.ng + kBlock - 1) / kBlock));
     if (precision == RR_FP64)
         hipLaunchKernelGGL(k_small_planet_rows<double>, grid, dim3(kBlock), 0, s, t->mu_s,
-                           t->prof, t->nmu, t->T64, pv, npar, k_small, t->grid.k1, nr, g,
+                           t->prof, t->nmu, t->T64, pv, npar, k_small, t->grid.k1, g,
                            static_cast<double*>(rows));
     else
         hipLaunchKernelGGL(k_small_planet_rows<float>, grid, dim3(kBlock), 0, s, t->mu_s,
-                           t->prof, t->nmu, t->T32, pv, npar, k_small, t->grid.k1, nr, g,
+                           t->prof, t->nmu, t->T32, pv, npar, k_small, t->grid.k1, g,
                            static_cast<float*>(rows));
     return hipGetLastError();
 }
