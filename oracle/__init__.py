@@ -12,7 +12,9 @@ Modules
 roadrunner  Oracle-A: the method step by step, in the order of Sects. 2-3
             (z-grid, annulus weights over (k, g), LD tables, k- and
             g-interpolation, Eq. 5), plus the orbit and supersampling that
-            Sect. 4 describes.  This is the GPU parity target.
+            Sect. 4 describes; also the per-row LD, direct-model
+            (Sect. 3.1.1) and small-planet (Sect. 3.4.2) forms.  This is the
+            GPU parity target.
 exact       Oracle-B: the plain definition of the transit signal (Eq. 1-2)
             integrated with adaptive quadrature, and a 2-D brute-force
             integral over the planet disk for tiny inputs.  It pins Oracle-A's

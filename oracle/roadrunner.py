@@ -21,6 +21,11 @@ Follows the paper's method in its own order:
 8. orbit and supersampling for populations of parameter vectors and
    heterogeneous light curves (Sect. 4.1, Sect. 4.2).
 
+Also the per-row LD form (each row's own profile through steps 2-5), the
+direct model (weights for a row's own k, Sect. 3.1.1) and the small-planet
+approximation (the LD value at the planet's centre below a radius-ratio
+threshold, Sect. 3.4.2).
+
 Readings of points the paper leaves open (listed with reasons in the design
 notes): n_g and n_k count grid points including both ends; the g index is
 clamped to n_g - 2 and the k index to n_k - 2; the weight vector at g = 1
