@@ -75,3 +75,28 @@ def test_heterogeneous_direct(rr):
     f64 = rr.evaluate_direct(tab, ser, w["pv"], "fp64").cpu().numpy()
     f32 = rr.evaluate_direct(tab, ser, w["pv"], "mixed").cpu().numpy().astype(np.float64)
     check(orr.evaluate_direct(otab, w["times"], w["pv"], **kw), f64, f32)
+
+
+@pytest.mark.parametrize("k", [0.005, 0.1, 0.5])
+def test_direct_model_against_analytic_model(rr, k):
+    """The direct model on the single light curve's orbit with quadratic LD
+    (2001 mu samples), at k below, inside and above the tables' k range:
+    within 5 ppm of the analytic quadratic-LD model (Mandel & Agol 2002) in
+    both precisions, as the paper's accuracy figure shows for the direct
+    model up to k = 0.5."""
+    from oracle import analytic as an
+    from oracle import orbit
+    w = wl.single_light_curve()
+    mu = np.linspace(0.0, 1.0, 2001)
+    tab = rr.Tables(mu, wl.profile_quadratic(mu, 0.4, 0.25), wl.DEFAULT_GRID)
+    pv = w["pv"].copy()
+    pv[0, 6] = k
+    ser = rr.TimeSeries(w["times"])
+    f64 = rr.evaluate_direct(tab, ser, pv, "fp64").cpu().numpy()[0]
+    f32 = rr.evaluate_direct(tab, ser, pv, "mixed").cpu().numpy()[0]
+    row = pv[0]
+    z, front, _ = orbit.projected_separation(w["times"] - row[0], *row[1:6])
+    fm = np.where(front, an.quadratic_flux(z, k, 0.4, 0.25), 1.0)
+    assert (fm < 1.0).sum() > 100
+    assert np.abs(f64 - fm).max() <= 5e-6
+    assert np.abs(f32.astype(np.float64) - fm).max() <= 6e-6
