@@ -105,13 +105,21 @@ def test_full_size_sampled_rows(rr):
     check(ref, f64[rows], f32[rows].astype(np.float64))
 
 
-def test_rejects_bad_threshold(rr):
+def test_rejects_bad_threshold_and_empty_sizes(rr):
+    import torch
     w = wl.population(npv=2, npt=100)
     tab = rr.Tables(w["mu_s"], w["I_s"], wl.TEST_GRID)
     ser = rr.TimeSeries(w["times"])
     for ks in (-0.1, 1.5, float("nan")):
         with pytest.raises(rr.RRError):
             rr.evaluate_small_planet(tab, ser, w["pv"], ks, "fp64")
+    with pytest.raises(rr.RRError):                         # npar mismatch
+        rr.evaluate_small_planet(tab, ser, np.zeros((2, 8)), 0.01, "fp64")
+    out = rr.evaluate_small_planet(tab, rr.TimeSeries(np.zeros(0)), w["pv"], 0.01, "fp64")
+    assert out.shape == (2, 0)
+    out = rr.evaluate_small_planet(tab, ser, np.zeros((0, 7)), 0.01, "mixed")
+    assert out.shape == (0, 100)
+    torch.cuda.synchronize()
 
 
 def test_small_planet_against_analytic_model(rr):

@@ -101,3 +101,8 @@ def test_bad_variant_arguments(rr):
             rr.evaluate(tab, ser, w["pv"], "fp64", variant=v)
     with pytest.raises(rr.RRError):
         rr.select_variant(tab, ser, w["pv"], "fp64", reps=0)
+    # empty sizes: nothing runs, the default variant is reported
+    best, ms = rr.select_variant(tab, rr.TimeSeries(np.zeros(0)), w["pv"], "fp64")
+    assert best == 1 and ms == [0.0] * rr.NUM_VARIANTS
+    out = rr.evaluate(tab, ser, np.zeros((0, 7)), "mixed", variant=2)
+    assert out.shape == (0, 100)
