@@ -23,7 +23,9 @@
  *   rr_evaluate_direct  the direct model: weights for each vector's own k,
  *                   no k-interpolation and no k limits (Sect. 3.1.1);
  *   rr_evaluate_small_planet  the small-planet approximation below a
- *                   radius-ratio threshold (Sect. 3.4.2);
+ *                   radius-ratio threshold (Sect. 3.4.2), and
+ *                   rr_loglik_grad_small_planet its log-likelihood and
+ *                   parameter gradient;
  *   rr_flux_at_z    Eq. 5 at given separations and radius ratios;
  *   rr_loglik_grad  Gaussian log-likelihood of observed fluxes and its
  *                   gradient with respect to every parameter and to the
@@ -242,6 +244,25 @@ RR_API int rr_evaluate_small_planet(const rr_tables* t, const double* times_d,
                                     const double* pv_d, int32_t npv, int32_t npar,
                                     double k_small, int32_t precision, void* out_d,
                                     hipStream_t stream);
+
+/* rr_loglik_grad with the small-planet approximation of
+ * rr_evaluate_small_planet (Sect. 3.4.2): logl_d[npv] and, if grad_d is not
+ * NULL, grad_d[npv][npar] for the same data arguments, obs_d and sigma as
+ * rr_loglik_grad.  A passband whose k is below k_small (host scalar in
+ * [0, 1], else RR_EINVAL) contributes the derivative of the centre values
+ * with respect to k (the piecewise-linear profile's slope at each g node's
+ * centre distance); the others are as rr_loglik_grad.  There is no
+ * LD-profile gradient here.  Invalid rows give NaN.  Errors and memory as
+ * rr_loglik_grad (its temporaries plus 2 npb ng sizeof(real) + 8 npb bytes
+ * per vector). */
+RR_API int rr_loglik_grad_small_planet(const rr_tables* t, const double* times_d,
+                                       const int32_t* lcids_d, int32_t npt,
+                                       const int32_t* pbids, const int32_t* nss,
+                                       const double* exptimes, int32_t nlc,
+                                       const double* pv_d, int32_t npv, int32_t npar,
+                                       double k_small, int32_t precision, const void* obs_d,
+                                       double sigma, double* logl_d, double* grad_d,
+                                       hipStream_t stream);
 
 /* The model as a function of the separation: out_d[i] = Eq. 5 for a planet
  * in front of the star at separation z_d[i] (in stellar radii) with radius

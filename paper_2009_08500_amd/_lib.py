@@ -83,6 +83,11 @@ def _declare(L):
                                     c_void_p, i32, c_void_p, i32, i32, i32, c_void_p, i32,
                                     c_void_p, c_void_p, c_void_p]
     L.rr_select_variant.restype = ctypes.c_int
+    L.rr_loglik_grad_small_planet.argtypes = [c_void_p, c_void_p, c_void_p, i32, c_void_p,
+                                              c_void_p, c_void_p, i32, c_void_p, i32, i32,
+                                              dbl, i32, c_void_p, dbl, c_void_p, c_void_p,
+                                              c_void_p]
+    L.rr_loglik_grad_small_planet.restype = ctypes.c_int
     L.rr_evaluate_small_planet.argtypes = [c_void_p, c_void_p, c_void_p, i32, c_void_p,
                                            c_void_p, c_void_p, i32, c_void_p, i32, i32, dbl,
                                            i32, c_void_p, c_void_p]

@@ -421,6 +421,36 @@ def loglik_grad(tables, series, pv, obs, sigma, precision="fp64", grad=True, pro
     return logl, g, gp
 
 
+def loglik_grad_small_planet(tables, series, pv, obs, sigma, k_small, precision="fp64",
+                             grad=True, stream=None):
+    """rr_loglik_grad_small_planet: the log-likelihood of ``obs`` under the
+    small-planet approximation below ``k_small`` (Sect. 3.4.2) and its
+    parameter gradient.  Returns (logl[npv], grad[npv, npar] or None),
+    float64 device tensors."""
+    prec = PRECISIONS[precision]
+    if not isinstance(series, TimeSeries):
+        series = TimeSeries(series)
+    pv = _dev(pv, torch.float64)
+    if pv.dim() == 1:
+        pv = pv.unsqueeze(0)
+    npv, npar = pv.shape
+    obs = _dev(obs, torch.float64 if prec == RR_FP64 else torch.float32)
+    if obs.numel() != series.npt:
+        raise ValueError("obs must have one value per time")
+    logl = torch.empty(npv, dtype=torch.float64, device=pv.device)
+    g = torch.empty((npv, npar), dtype=torch.float64, device=pv.device) if grad else None
+
+    def p(t):
+        return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+    lc, npt, pb, nss, ex, nlc = series.lc_args()
+    check(_lib.lib().rr_loglik_grad_small_planet(
+        tables.handle, p(series.times), lc, npt, pb, nss, ex, nlc, p(pv), npv, npar,
+        float(k_small), prec, p(obs), float(sigma), p(logl), p(g), _stream(stream)),
+        "rr_loglik_grad_small_planet")
+    return logl, g
+
+
 def loglik_grad_ld(tables, series, pv, prof, obs, sigma, precision="fp64", grad=True,
                    profile=True, stream=None):
     """rr_loglik_grad_ld: the log-likelihood with a profile per parameter row

@@ -519,7 +519,7 @@ static int loglik_impl(const rr_tables* t, const double* times_d,
                        int32_t precision, const void* obs_d, double sigma,
                        const double* wprof_d, double* logl_d, double* grad_d,
                        double* grad_prof_d, bool per_row, const double* prof_pv_d,
-                       hipStream_t stream) {
+                       hipStream_t stream, double k_small = -1.0) {
     LcInfo lc;
     int rc = check_eval_args(t, times_d, lcids_d, npt, pbids, nss, exptimes, nlc,
                              pv_d, npv, npar, precision, &lc);
@@ -572,10 +572,14 @@ static int loglik_impl(const rr_tables* t, const double* times_d,
     const size_t elt = precision == RR_FP64 ? sizeof(double) : sizeof(float);
     const size_t o_ldp = per_row ? take(sizeof(double) * size_t(nr) * t->nz) : 0;
     const size_t o_isr = per_row ? take(sizeof(double) * size_t(nr)) : 0;
-    const size_t o_iisr = per_row ? take(sizeof(double) * size_t(nr)) : 0;
+    // small-planet rows (k_small >= 0): own row pairs and 1/I_star per row
+    const bool sp = k_small >= 0.0;
+    if (sp && nr >= (int64_t(1) << 31)) return elimit("npv * npb too large");
+    const bool own_rows = per_row || sp;
+    const size_t o_iisr = own_rows ? take(sizeof(double) * size_t(nr)) : 0;
     const size_t o_ikr = per_row ? take(sizeof(int32_t) * size_t(nr)) : 0;
     const size_t o_perm = per_row ? take(sizeof(int32_t) * size_t(nr)) : 0;
-    const size_t o_rows = per_row ? take(elt * size_t(nr) * 2 * g.ng) : 0;
+    const size_t o_rows = own_rows ? take(elt * size_t(nr) * 2 * g.ng) : 0;
     const size_t o_gldpr = per_row && prof ? take(sizeof(double) * size_t(nr) * t->nz) : 0;
     const size_t o_gt = shared_prof ? take(sizeof(double) * size_t(t->npb) * g.nk * g.ng) : 0;
     const size_t o_gldp = shared_prof ? take(sizeof(double) * size_t(t->npb) * t->nz) : 0;
@@ -604,8 +608,8 @@ static int loglik_impl(const rr_tables* t, const double* times_d,
     A.npv = npv; A.npar = npar; A.pvc = reinterpret_cast<PvConst*>(base + o_pvc); A.g = g;
     A.T = precision == RR_FP64 ? static_cast<const void*>(t->T64) : static_cast<const void*>(t->T32);
     A.inv_istar = t->inv_istar; A.obs = obs_d; A.inv_sig2 = 1.0 / (sigma * sigma);
-    A.rows_per_vector = per_row ? 1 : 0;
-    if (per_row) {
+    A.rows_per_vector = own_rows ? 1 : 0;
+    if (own_rows) {
         A.T = base + o_rows;
         A.inv_istar = reinterpret_cast<double*>(base + o_iisr);
     }
@@ -619,7 +623,12 @@ static int loglik_impl(const rr_tables* t, const double* times_d,
     A.seg_gi = segs ? reinterpret_cast<double*>(base + o_sgi) : nullptr;
     A.seg_flag = segs ? reinterpret_cast<int32_t*>(base + o_sfl) : nullptr;
     A.logl = logl_d; A.grad = grad_d;
-    e = launch_pv_setup(t, pv_d, npv, npar, const_cast<PvConst*>(A.pvc), stream);
+    e = sp ? launch_pv_setup_k(pv_d, npv, npar, t->grid.k0, t->grid.k1,
+                               const_cast<PvConst*>(A.pvc), stream, k_small)
+           : launch_pv_setup(t, pv_d, npv, npar, const_cast<PvConst*>(A.pvc), stream);
+    if (e == hipSuccess && sp)
+        e = launch_small_planet_adj_rows(t, pv_d, npv, npar, k_small, precision, base + o_rows,
+                                         reinterpret_cast<double*>(base + o_iisr), stream);
     if (e == hipSuccess && per_row)
         e = launch_pv_ld(t, prof_pv_d, pv_d, npv, npar, precision,
                          reinterpret_cast<double*>(base + o_ldp),
@@ -677,6 +686,20 @@ RR_API int rr_loglik_grad_ld(const rr_tables* t, const double* times_d,
     return loglik_impl(t, times_d, lcids_d, npt, pbids, nss, exptimes, nlc, pv_d, npv, npar,
                        precision, obs_d, sigma, nullptr, logl_d, grad_d, grad_prof_d, true,
                        prof_d, stream);
+}
+
+RR_API int rr_loglik_grad_small_planet(const rr_tables* t, const double* times_d,
+                                       const int32_t* lcids_d, int32_t npt,
+                                       const int32_t* pbids, const int32_t* nss,
+                                       const double* exptimes, int32_t nlc,
+                                       const double* pv_d, int32_t npv, int32_t npar,
+                                       double k_small, int32_t precision, const void* obs_d,
+                                       double sigma, double* logl_d, double* grad_d,
+                                       hipStream_t stream) {
+    if (!(k_small >= 0.0 && k_small <= 1.0)) return einval("k_small must lie in [0, 1]");
+    return loglik_impl(t, times_d, lcids_d, npt, pbids, nss, exptimes, nlc, pv_d, npv, npar,
+                       precision, obs_d, sigma, nullptr, logl_d, grad_d, nullptr, false,
+                       nullptr, stream, k_small);
 }
 
 RR_API void rr_free_tables(rr_tables* t) { free_tables(t); }

@@ -238,6 +238,12 @@ hipError_t launch_direct_rows(const rr_tables* t, const double* pv, int32_t npv,
 hipError_t launch_small_planet_rows(const rr_tables* t, const double* pv, int32_t npv,
                                     int32_t npar, double k_small, int32_t precision,
                                     void* rows, hipStream_t s);
+// The same for the log-likelihood's adjoint: row pairs whose k-lerp gives
+// the centre values and whose difference over dk their k-derivative, and
+// 1/I_star per row ([npv][npb]).
+hipError_t launch_small_planet_adj_rows(const rr_tables* t, const double* pv, int32_t npv,
+                                        int32_t npar, double k_small, int32_t precision,
+                                        void* rows, double* inv_istar_rows, hipStream_t s);
 // Eq. 5 at separations z[n] (rr_flux_at_z); kv[n] or, if NULL, kconst.
 hipError_t launch_flux_at_z(const rr_tables* t, const double* z, const double* kv,
                            double kconst, int64_t n, int32_t pb, int32_t precision, void* out,

@@ -504,6 +504,95 @@ hipError_t launch_direct_rows(const rr_tables* t, const double* pv, int32_t npv,
     return hipGetLastError();
 }
 
+// The small-planet rows for the log-likelihood's adjoint, which reads a
+// row pair (row0, row1) per (vector, passband) with the k-weight ak of the
+// row's k on the tables' k-grid: ldw = (1 - ak) row0 + ak row1 and
+// dldw/dk = (row1 - row0) / dk.  Below k_small the pair is built so that
+// these give the centre values v[m] = I(mu(c_m)), c_m = g_m (1 + k), and
+// their k-derivative D[m] = I'(mu) (-c_m / mu) g_m (zero where c_m is
+// clamped to the limb or the profile is constant beyond its samples):
+// row0 = v - ak dk D, row1 = row0 + dk D.  Other rows copy the shared
+// table's two k-rows.  Also writes 1/I_star per row (the tables' value).
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_small_planet_adj_rows(
+    const double* __restrict__ mu_s, const double* __restrict__ prof, int32_t nmu,
+    const R* __restrict__ T, const double* __restrict__ inv_istar, const double* __restrict__ pv,
+    int32_t npar, double k_small, GridDev g, R* __restrict__ out,
+    double* __restrict__ inv_istar_rows) {
+    __shared__ double smu[kSpLds], sf[kSpLds];
+    const int64_t r = blockIdx.x;
+    const int m = int(blockIdx.y) * kBlock + int(threadIdx.x);
+    const int64_t ipv = r / g.npb;
+    const int pb = int(r - ipv * g.npb);
+    const double k = pv[ipv * npar + 6 + pb];          // uniform in the workgroup
+    R* o = out + r * 2 * g.ng;
+    const double u = (k - g.k0) / g.dk;
+    int ik = int(floor(u));
+    ik = ik < 0 ? 0 : (ik > g.nk - 2 ? g.nk - 2 : ik);
+    R r0 = R(0), r1 = R(0);                           // invalid rows: NaN from the setup
+    if (k < k_small) {
+        if (k > 0.0) {
+            const double* f = prof + int64_t(pb) * nmu;
+            const bool staged = nmu <= kSpLds;
+            if (staged) {
+                for (int j = threadIdx.x; j < nmu; j += kBlock) {
+                    smu[j] = mu_s[j];
+                    sf[j] = f[j];
+                }
+                __syncthreads();
+            }
+            if (m >= g.ng) return;
+            const double* ms = staged ? smu : mu_s;
+            const double* fs = staged ? sf : f;
+            const double gm = double(m) / double(g.ng - 1);
+            const double craw = gm * (1.0 + k);
+            const double c = craw < 1.0 ? craw : 1.0;
+            const double v = profile_at_bin(ms, fs, nmu, c);
+            double D = 0.0;
+            const double mu = sqrt(1.0 - c * c);
+            if (craw < 1.0 && mu > ms[0] && mu < ms[nmu - 1]) {
+                int lo = 0, hi = nmu - 1;                  // ms[lo] <= mu < ms[hi]
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (ms[mid] <= mu) lo = mid; else hi = mid;
+                }
+                const double slope = (fs[lo + 1] - fs[lo]) / (ms[lo + 1] - ms[lo]);
+                D = slope * (-c / mu) * gm;
+            }
+            const double ak = u - ik;
+            const double b0 = v - ak * g.dk * D;
+            r0 = R(b0);
+            r1 = R(b0 + g.dk * D);
+        }
+    } else {
+        if (m >= g.ng) return;
+        const R* t0r = T + (int64_t(pb) * g.nk + ik) * g.ng;
+        r0 = t0r[m];
+        r1 = t0r[g.ng + m];
+    }
+    if (m >= g.ng) return;
+    o[m] = r0;
+    o[g.ng + m] = r1;
+    if (m == 0) inv_istar_rows[r] = inv_istar[pb];
+}
+
+hipError_t launch_small_planet_adj_rows(const rr_tables* t, const double* pv, int32_t npv,
+                                        int32_t npar, double k_small, int32_t precision,
+                                        void* rows, double* inv_istar_rows, hipStream_t s) {
+    const GridDev g = grid_dev(t);
+    const int64_t nr = int64_t(npv) * t->npb;
+    const dim3 grid(unsigned(nr), unsigned((g.ng + kBlock - 1) / kBlock));
+    if (precision == RR_FP64)
+        hipLaunchKernelGGL(k_small_planet_adj_rows<double>, grid, dim3(kBlock), 0, s, t->mu_s,
+                           t->prof, t->nmu, t->T64, t->inv_istar, pv, npar, k_small, g,
+                           static_cast<double*>(rows), inv_istar_rows);
+    else
+        hipLaunchKernelGGL(k_small_planet_adj_rows<float>, grid, dim3(kBlock), 0, s, t->mu_s,
+                           t->prof, t->nmu, t->T32, t->inv_istar, pv, npar, k_small, g,
+                           static_cast<float*>(rows), inv_istar_rows);
+    return hipGetLastError();
+}
+
 hipError_t launch_small_planet_rows(const rr_tables* t, const double* pv, int32_t npv,
                                     int32_t npar, double k_small, int32_t precision,
                                     void* rows, hipStream_t s) {

@@ -126,8 +126,8 @@ def test_server_rejects_bad_arguments_on_host(lib):
 
 def test_newer_entry_points_reject_null_handle(lib):
     """rr_evaluate_ld, rr_evaluate_direct, rr_evaluate_small_planet,
-    rr_evaluate_variant, rr_select_variant, rr_loglik_grad_ld and
-    rr_flux_at_z check their arguments on the host and return RR_EINVAL for a NULL
+    rr_evaluate_variant, rr_select_variant, rr_loglik_grad_ld,
+    rr_loglik_grad_small_planet and rr_flux_at_z check their arguments on the host and return RR_EINVAL for a NULL
     tables handle without touching the device."""
     from paper_2009_08500_amd import _lib
     one = np.ones(1, np.int32)
@@ -151,5 +151,9 @@ def test_newer_entry_points_reject_null_handle(lib):
                                  ctypes.byref(best), None, None) == _lib.RR_EINVAL
     assert lib.rr_select_variant(None, None, None, 0, p1, p1, pz, 1, None, 0, 7, 0, None, 5,
                                  None, None, None) == _lib.RR_EINVAL
+    assert lib.rr_loglik_grad_small_planet(None, None, None, 0, p1, p1, pz, 1, None, 0, 7, 0.01,
+                                           0, None, 1.0, None, None, None) == _lib.RR_EINVAL
+    assert lib.rr_loglik_grad_small_planet(None, None, None, 0, p1, p1, pz, 1, None, 0, 7, 2.0,
+                                           0, None, 1.0, None, None, None) == _lib.RR_EINVAL
     assert lib.rr_flux_at_z(None, None, None, 0.1, 0, 0, 0, None, None) == _lib.RR_EINVAL
     assert "NULL" in _lib.last_error()
