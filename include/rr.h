@@ -235,8 +235,8 @@ RR_API int rr_evaluate_direct(const rr_tables* t, const double* times_d,
  * (0: no row uses the approximation), else RR_EINVAL.  Other arguments,
  * errors and invalid rows as rr_evaluate.  Temporary device memory
  * (144 + 2 npb ng sizeof(real) bytes per vector) is the per-stream buffer
- * that rr_evaluate uses.  The profile gradient entry points do not take
- * this approximation. */
+ * that rr_evaluate uses.  rr_loglik_grad_small_planet gives its
+ * log-likelihood and parameter gradient (no LD-profile gradient). */
 RR_API int rr_evaluate_small_planet(const rr_tables* t, const double* times_d,
                                     const int32_t* lcids_d, int32_t npt,
                                     const int32_t* pbids, const int32_t* nss,
