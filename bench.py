@@ -307,8 +307,9 @@ def small_planet_leg(rr, wl, steps, warmup):
     (rr_evaluate_small_planet): points/s and per-call latency for both
     precisions, the same population through the interpolated model for
     comparison (rows below the tables' k0 are NaN there, so it is timed with
-    k raised to 0.01), and the error of eight sampled rows against the
-    oracle."""
+    k raised to 0.01), the log-likelihood with its parameter gradient
+    (rr_loglik_grad_small_planet), and the error of eight sampled rows
+    against the oracle."""
     import numpy as np
     import torch
     from oracle import roadrunner as orr
@@ -341,8 +342,13 @@ def small_planet_leg(rr, wl, steps, warmup):
         ms = timed(lambda: rr.evaluate_small_planet(tab, ser, pv, 0.01, prec, out=out))
         outs[prec] = out.cpu().numpy().astype(np.float64)
         ms_tab = timed(lambda: rr.evaluate(tab, ser, pv_tab, prec, out=out))
+        # log-likelihood and parameter gradient of the same rows against the
+        # first row's light curve plus 200 ppm of seeded noise
+        noise = torch.as_tensor(np.random.default_rng(12).normal(0.0, 2e-4, npt), device="cuda")
+        obs = (torch.as_tensor(outs[prec][0], device="cuda") + noise).to(out.dtype)
+        ms_ll = timed(lambda: rr.loglik_grad_small_planet(tab, ser, pv, obs, 2e-4, 0.01, prec))
         res[prec] = dict(points_per_s=npv * npt / (ms / 1e3), ms_per_step=ms,
-                         interpolated_model_ms=ms_tab)
+                         interpolated_model_ms=ms_tab, loglik_grad_ms=ms_ll)
     rows = np.random.default_rng(11).choice(npv, 8, replace=False)
     otab = orr.Tables(w["mu_s"], w["I_s"], **grid)
     ref = orr.evaluate_small_planet(otab, w["times"], w["pv"][rows], 0.01)
