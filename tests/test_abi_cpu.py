@@ -157,3 +157,24 @@ def test_newer_entry_points_reject_null_handle(lib):
                                            0, None, 1.0, None, None, None) == _lib.RR_EINVAL
     assert lib.rr_flux_at_z(None, None, None, 0.1, 0, 0, 0, None, None) == _lib.RR_EINVAL
     assert "NULL" in _lib.last_error()
+
+
+def test_variant_count_matches_header():
+    """The binding's variant count is the header's RR_NUM_VARIANTS."""
+    txt = open(os.path.join(ROOT, "include", "rr.h")).read()
+    n = int(re.search(r"#define RR_NUM_VARIANTS\s+(\d+)", txt).group(1))
+    from paper_2009_08500_amd import api
+    assert api.NUM_VARIANTS == n == 6
+
+
+def test_small_planet_workload_recipe():
+    """Seeded and reproducible; k ~ logU(0.003, 0.03), about half of the
+    vectors below the 0.01 threshold; orbits and times as the population."""
+    import workloads as wl
+    a, b = wl.population_small(npv=512, npt=100), wl.population_small(npv=512, npt=100)
+    assert np.array_equal(a["pv"], b["pv"])
+    k = a["pv"][:, 6]
+    assert k.min() >= 0.003 and k.max() <= 0.03
+    assert 0.35 < np.mean(k < 0.01) < 0.65
+    p = wl.population(npv=512, npt=100)
+    assert np.array_equal(a["pv"][:, :6], p["pv"][:, :6]) and np.array_equal(a["times"], p["times"])
