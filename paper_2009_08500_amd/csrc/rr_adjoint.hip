@@ -192,6 +192,8 @@ __global__ __launch_bounds__(kAdjBlock) void k_adjoint(
     double* __restrict__ seg_gw, double* __restrict__ seg_gi, int32_t* __restrict__ seg_flag,
     int32_t rows_per_vector) {
     extern __shared__ unsigned char smem_raw[];
+    constexpr int kJ = adj_times_per_thread(kProf);   // times per thread
+    constexpr int kTile = kAdjBlock * kJ;
     const int npb = g.npb, ng = g.ng;
     R* ldw = reinterpret_cast<R*>(smem_raw);                    // [npb][ng]
     R* dTk = ldw + npb * ng;                                    // [npb][ng]
@@ -234,15 +236,15 @@ __global__ __launch_bounds__(kAdjBlock) void k_adjoint(
     const int tile0 = kProf ? c * tpp : c;
     const int tile_end = kProf ? min(ntiles, (c + 1) * tpp) : c + 1;
     for (int tile = tile0; tile < tile_end; ++tile) {
-        const int t_base = tile * kAdjTile + tid;
+        const int t_base = tile * kTile + tid;
         // Pass 1: residuals of exposures that cannot overlap the star.
         uint32_t todo = 0;
-        const int tfirst = tile * kAdjTile;
-        if (!lcids && tfirst + kAdjTile <= npt) {
+        const int tfirst = tile * kTile;
+        if (!lcids && tfirst + kTile <= npt) {
             // whole tile in range, one light curve (see forward_block)
-            double tv[kTimesPerThread], ov[kTimesPerThread];
+            double tv[kJ], ov[kJ];
 #pragma unroll
-            for (int j = 0; j < kTimesPerThread; ++j) {
+            for (int j = 0; j < kJ; ++j) {
                 tv[j] = times[tfirst + tid + j * kAdjBlock];
                 ov[j] = double(obs[tfirst + tid + j * kAdjBlock]);
             }
@@ -250,7 +252,7 @@ __global__ __launch_bounds__(kAdjBlock) void k_adjoint(
             const double c0 = -p.t0 * p.invP - (p.flo - hw);
             const double wn = p.wn + 2.0 * hw;
 #pragma unroll
-            for (int j = 0; j < kTimesPerThread; ++j) {
+            for (int j = 0; j < kJ; ++j) {
                 const double gph = fma(tv[j], p.invP, c0);
                 if (gph - floor(gph) < wn) {
                     todo |= 1u << j;
@@ -260,7 +262,7 @@ __global__ __launch_bounds__(kAdjBlock) void k_adjoint(
                 }
             }
         } else {
-            for (int j = 0; j < kTimesPerThread; ++j) {
+            for (int j = 0; j < kJ; ++j) {
                 const int it = t_base + j * kAdjBlock;
                 if (it >= npt) continue;
                 const int l = lcids ? lcids[it] : 0;

@@ -27,8 +27,11 @@ constexpr int kTimesPerThread = RR_TIMES_PER_THREAD;   // times per thread
 constexpr int kFwdBlock = 64;
 constexpr int kFwdTile = kFwdBlock * kTimesPerThread;
 // Log-likelihood kernel: two wave64 per workgroup share the LDS tables.
+// Times per thread: 16 for logL and the parameter gradients, 8 with the
+// LD-profile gradient (measured fastest for each).
 constexpr int kAdjBlock = 128;
-constexpr int kAdjTile = kAdjBlock * kTimesPerThread;
+constexpr int adj_times_per_thread(bool prof) { return prof ? 8 : 16; }
+constexpr int adj_tile(bool prof) { return kAdjBlock * adj_times_per_thread(prof); }
 constexpr int kMaxLdsBytes = 64 * 1024;   // LDS budget for the adjoint's
                                           // per-workgroup tables
 
