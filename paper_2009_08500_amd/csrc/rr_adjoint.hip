@@ -192,7 +192,7 @@ __global__ __launch_bounds__(kAdjBlock) void k_adjoint(
     double* __restrict__ seg_gw, double* __restrict__ seg_gi, int32_t* __restrict__ seg_flag,
     int32_t rows_per_vector) {
     extern __shared__ unsigned char smem_raw[];
-    constexpr int kJ = adj_times_per_thread(kProf);   // times per thread
+    constexpr int kJ = adj_times_per_thread(kProf, sizeof(R) == 8);   // times per thread
     constexpr int kTile = kAdjBlock * kJ;
     const int npb = g.npb, ng = g.ng;
     R* ldw = reinterpret_cast<R*>(smem_raw);                    // [npb][ng]

@@ -119,7 +119,8 @@ int check_eval_args(const rr_tables* t, const double* times_d,
         if (!times_d) return einval("times is NULL");
         if (!pv_d) return einval("pv is NULL");
     }
-    const int64_t ntiles = (int64_t(npt) + adj_tile(true) - 1) / adj_tile(true);   // the smaller tiles
+    const int64_t ntiles = (int64_t(npt) + adj_tile(true, false) - 1) /
+                           adj_tile(true, false);            // the smaller tiles
     if (ntiles * npv * kAdjBlock >= (int64_t(1) << 32) ||
         ((int64_t(npt) + 4 * kFwdBlock - 1) / (4 * kFwdBlock)) * npv * kFwdBlock >=
             (int64_t(1) << 32))                  // the smallest forward tile (J = 4)
@@ -544,7 +545,8 @@ static int loglik_impl(const rr_tables* t, const double* times_d,
         return RR_OK;
     }
     const bool prof = grad_prof_d != nullptr;
-    const int32_t ntiles = npt > 0 ? (npt + adj_tile(prof) - 1) / adj_tile(prof) : 1;
+    const int32_t tile = adj_tile(prof, precision == RR_FP64);
+    const int32_t ntiles = npt > 0 ? (npt + tile - 1) / tile : 1;
     const int32_t nq = 7 + t->npb;
     const GridDev g = grid_dev(t);
     // With the profile gradient each workgroup runs tpp consecutive tiles of

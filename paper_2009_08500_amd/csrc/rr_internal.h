@@ -27,11 +27,11 @@ constexpr int kTimesPerThread = RR_TIMES_PER_THREAD;   // times per thread
 constexpr int kFwdBlock = 64;
 constexpr int kFwdTile = kFwdBlock * kTimesPerThread;
 // Log-likelihood kernel: two wave64 per workgroup share the LDS tables.
-// Times per thread: 16 for logL and the parameter gradients, 8 with the
-// LD-profile gradient (measured fastest for each).
+// Times per thread: 16, except 8 with the LD-profile gradient in mixed
+// precision (measured fastest for each).
 constexpr int kAdjBlock = 128;
-constexpr int adj_times_per_thread(bool prof) { return prof ? 8 : 16; }
-constexpr int adj_tile(bool prof) { return kAdjBlock * adj_times_per_thread(prof); }
+constexpr int adj_times_per_thread(bool prof, bool f64) { return prof && !f64 ? 8 : 16; }
+constexpr int adj_tile(bool prof, bool f64) { return kAdjBlock * adj_times_per_thread(prof, f64); }
 constexpr int kMaxLdsBytes = 64 * 1024;   // LDS budget for the adjoint's
                                           // per-workgroup tables
 
