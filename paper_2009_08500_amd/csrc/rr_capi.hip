@@ -75,7 +75,7 @@ static void free_tables(rr_tables* t) {
     (void)hipGetDevice(&cur);
     (void)hipSetDevice(t->device);
     void* bufs[] = {t->mu_s, t->prof, t->ze, t->zm, t->ldp, t->istar,
-                    t->W, t->T64, t->T32, t->inv_istar};
+                    t->W, t->W32, t->T64, t->T32, t->inv_istar};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     for (auto& kv : t->ws)
@@ -194,6 +194,7 @@ RR_API int rr_prepare_ld(const double* mu, const double* prof, int32_t nmu,
         {(void**)&t->istar, sizeof(double) * npb},
         {(void**)&t->inv_istar, sizeof(double) * npb},
         {(void**)&t->W, sizeof(double) * nk * nz * ng},
+        {(void**)&t->W32, sizeof(float) * nk * nz * ng},
         {(void**)&t->T64, sizeof(double) * npb * nk * ng},
         {(void**)&t->T32, sizeof(float) * npb * nk * ng},
     };
@@ -501,7 +502,8 @@ RR_API int rr_evaluate_ld(const rr_tables* t, const double* times_d,
                          reinterpret_cast<double*>(base + o_ldp),
                          reinterpret_cast<double*>(base + o_is), inv_is,
                          reinterpret_cast<int32_t*>(base + o_ikr),
-                         reinterpret_cast<int32_t*>(base + o_perm), ldw, stream);
+                         reinterpret_cast<int32_t*>(base + o_perm), ldw, stream,
+                         precision == RR_MIXED);
     if (e == hipSuccess)
         e = launch_forward(t, times_d, lcids_d, npt, lc, pv_d, npv, npar, pvc, precision,
                            out_d, stream, ldw, inv_is);

@@ -154,6 +154,7 @@ struct rr_tables {
     double* ldp = nullptr;       // [npb][nz]
     double* istar = nullptr;     // [npb]
     double* W = nullptr;         // [nk][nz][ng]
+    float* W32 = nullptr;        // [nk][nz][ng], FP32 copy (mixed per-vector tables)
     double* T64 = nullptr;       // [npb][nk][ng]
     float* T32 = nullptr;        // [npb][nk][ng]
     double* inv_istar = nullptr; // [npb]
@@ -256,9 +257,10 @@ hipError_t launch_flux_at_z(const rr_tables* t, const double* z, const double* k
 // 1/I_star ([npv][npb]) and the vector's own two table rows around its k
 // (rows, [npv][npb][2][ng], double or float by precision); ikr and perm are
 // [npv npb] int32 scratch.
+// w32: the per-row kernel reads the FP32 copy of W (mixed precision only).
 hipError_t launch_pv_ld(const rr_tables* t, const double* prof, const double* pv,
                         int32_t npv, int32_t npar, int32_t precision, double* ldp,
                         double* istar, double* inv_istar, int32_t* ikr, int32_t* perm,
-                        void* rows, hipStream_t s);
+                        void* rows, hipStream_t s, bool w32 = false);
 
 }  // namespace rr

@@ -159,6 +159,12 @@ GridDev grid_dev(const rr_tables* t) {
     return g;
 }
 
+// FP32 copy of the weights for the mixed-precision per-vector tables.
+__global__ void k_weights_f32(const double* __restrict__ W, int64_t n, float* __restrict__ W32) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) W32[i] = float(W[i]);
+}
+
 hipError_t launch_prepare_grid_weights(rr_tables* t, hipStream_t s) {
     const GridDev g = grid_dev(t);
     hipLaunchKernelGGL(k_zgrid, dim3(nblocks(t->nz + 1)), dim3(kBlock), 0, s,
@@ -167,6 +173,7 @@ hipError_t launch_prepare_grid_weights(rr_tables* t, hipStream_t s) {
     if (e != hipSuccess) return e;
     const int64_t nw = int64_t(g.nk) * g.nz * g.ng;
     hipLaunchKernelGGL(k_weights, dim3(nblocks(nw)), dim3(kBlock), 0, s, t->ze, g, t->W);
+    hipLaunchKernelGGL(k_weights_f32, dim3(nblocks(nw)), dim3(kBlock), 0, s, t->W, nw, t->W32);
     return hipGetLastError();
 }
 
@@ -263,8 +270,8 @@ __global__ __launch_bounds__(kBlock) void k_pv_prep(const double* __restrict__ m
 // remainder) and each XCD walks a contiguous stretch of the sorted rows,
 // whose W rows its L2 then serves to the following rows of equal ik.
 constexpr int kXcds = 8;
-template <typename R>
-__global__ __launch_bounds__(kBlock) void k_pv_tables(const double* __restrict__ W,
+template <typename R, typename WT>
+__global__ __launch_bounds__(kBlock) void k_pv_tables(const WT* __restrict__ W,
                                                       const double* __restrict__ ldp,
                                                       const int32_t* __restrict__ ikr,
                                                       const int32_t* __restrict__ perm,
@@ -285,12 +292,12 @@ __global__ __launch_bounds__(kBlock) void k_pv_tables(const double* __restrict__
     __syncthreads();
     const int m = mb * kBlock + int(threadIdx.x);
     if (m >= g.ng) return;
-    const double* w0 = W + int64_t(ik) * nz * g.ng + m;
-    const double* w1 = w0 + int64_t(nz) * g.ng;
+    const WT* w0 = W + int64_t(ik) * nz * g.ng + m;
+    const WT* w1 = w0 + int64_t(nz) * g.ng;
     double a0 = 0.0, a1 = 0.0;
     int j = 0;
     for (; j + 8 <= nz; j += 8) {                 // sixteen loads in flight
-        double x0[8], x1[8];
+        WT x0[8], x1[8];
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
             x0[b] = w0[int64_t(j + b) * g.ng];
@@ -298,13 +305,13 @@ __global__ __launch_bounds__(kBlock) void k_pv_tables(const double* __restrict__
         }
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
-            a0 += x0[b] * lp[j + b];
-            a1 += x1[b] * lp[j + b];
+            a0 += double(x0[b]) * lp[j + b];
+            a1 += double(x1[b]) * lp[j + b];
         }
     }
     for (; j < nz; ++j) {
-        a0 += w0[int64_t(j) * g.ng] * lp[j];
-        a1 += w1[int64_t(j) * g.ng] * lp[j];
+        a0 += double(w0[int64_t(j) * g.ng]) * lp[j];
+        a1 += double(w1[int64_t(j) * g.ng]) * lp[j];
     }
     R* o = out + r * 2 * g.ng;
     o[m] = R(a0);
@@ -613,7 +620,7 @@ hipError_t launch_small_planet_rows(const rr_tables* t, const double* pv, int32_
 hipError_t launch_pv_ld(const rr_tables* t, const double* prof, const double* pv,
                         int32_t npv, int32_t npar, int32_t precision, double* ldp,
                         double* istar, double* inv_istar, int32_t* ikr, int32_t* perm,
-                        void* rows, hipStream_t s) {
+                        void* rows, hipStream_t s, bool w32) {
     const GridDev g = grid_dev(t);
     const int64_t nr = int64_t(npv) * t->npb;     // (vector, passband) rows
     hipLaunchKernelGGL(k_pv_prep, dim3(unsigned(nr + 1)), dim3(kBlock), 0, s, t->mu_s, prof,
@@ -625,13 +632,17 @@ hipError_t launch_pv_ld(const rr_tables* t, const double* prof, const double* pv
     if (precision == RR_FP64) {
         hipLaunchKernelGGL(k_pv_tables_mfma<double>, grid, dim3(kBlock), 0, s, t->W, ldp, ikr,
                            perm, nr, t->nz, g, static_cast<double*>(rows));
-        hipLaunchKernelGGL(k_pv_tables<double>, grid_rows, dim3(kBlock), 0, s, t->W, ldp, ikr,
-                           perm, t->nz, g, static_cast<double*>(rows));
+        hipLaunchKernelGGL((k_pv_tables<double, double>), grid_rows, dim3(kBlock), 0, s, t->W,
+                           ldp, ikr, perm, t->nz, g, static_cast<double*>(rows));
     } else {
         hipLaunchKernelGGL(k_pv_tables_mfma<float>, grid, dim3(kBlock), 0, s, t->W, ldp, ikr,
                            perm, nr, t->nz, g, static_cast<float*>(rows));
-        hipLaunchKernelGGL(k_pv_tables<float>, grid_rows, dim3(kBlock), 0, s, t->W, ldp, ikr,
-                           perm, t->nz, g, static_cast<float*>(rows));
+        if (w32)
+            hipLaunchKernelGGL((k_pv_tables<float, float>), grid_rows, dim3(kBlock), 0, s,
+                               t->W32, ldp, ikr, perm, t->nz, g, static_cast<float*>(rows));
+        else
+            hipLaunchKernelGGL((k_pv_tables<float, double>), grid_rows, dim3(kBlock), 0, s,
+                               t->W, ldp, ikr, perm, t->nz, g, static_cast<float*>(rows));
     }
     return hipGetLastError();
 }

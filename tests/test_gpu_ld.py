@@ -93,12 +93,14 @@ def test_own_profile_equals_shared_tables(rr):
     """Every vector given the tables' own profile: rr_evaluate_ld and
     rr_evaluate agree to rounding (each vector's two table rows are the
     shared rows up to the order of the FP64 additions over bins, then
-    interpolated in k the same way)."""
+    interpolated in k the same way; in mixed precision the rows are summed
+    from the FP32 copy of the weights, so the float outputs may differ by
+    an ulp)."""
     w = wl.population(npv=64, npt=6000)
     tab = rr.Tables(w["mu_s"], w["I_s"], wl.DEFAULT_GRID)
     ser = rr.TimeSeries(w["times"])
     prof = np.broadcast_to(w["I_s"], (64,) + w["I_s"].shape).copy()
-    for prec, tol in (("fp64", 1e-14), ("mixed", 1e-8)):
+    for prec, tol in (("fp64", 1e-14), ("mixed", 1.2e-7)):
         a = rr.evaluate_ld(tab, ser, w["pv"], prof, prec).cpu().numpy().astype(np.float64)
         b = rr.evaluate(tab, ser, w["pv"], prec).cpu().numpy().astype(np.float64)
         assert np.abs(a - b).max() <= tol, (prec, np.abs(a - b).max())
