@@ -117,7 +117,8 @@ typedef struct rr_tables rr_tables;   /* opaque, owned by the library */
  * W[nk][nz][ng] (area of annulus j occluded by a planet of radius k_i at
  * grazing value g_m over the total occluded area, Sect. 2), the profile at
  * the bin means, I_star and the LD-weighted tables T[npb][nk][ng] in FP64
- * and FP32.  Device memory ~ 8 nk nz ng + 12 npb nk ng bytes.
+ * and FP32.  Device memory ~ 12 nk nz ng + 12 npb nk ng bytes (W in FP64
+ * and an FP32 copy for the mixed per-vector tables).
  * Synchronous: returns when the tables are ready for use on any stream.
  * 2 <= nmu <= 65536, 1 <= npb <= RR_MAX_PB.  On success *out receives a new
  * handle; release it with rr_free_tables. */
