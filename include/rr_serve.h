@@ -57,8 +57,21 @@ RR_API int rr_server_submit(rr_server* s, int32_t series_id, const double* pv,
                             int32_t npv, int32_t npar, int32_t precision,
                             void* out_host, int64_t* request_id);
 
+/* The same with the output written straight to out_dev[npv][npt] (double
+ * or float by precision), a device buffer of the server's device that the
+ * caller owns and must not read or free until the request is done; the
+ * request's arena footprint then excludes the output (about npv (8 npar +
+ * 160) bytes).  Done means the kernels that wrote out_dev have completed,
+ * so any stream may read it afterwards.  This form measures the GPU side of
+ * serving without the device-to-host copy of every result. */
+RR_API int rr_server_submit_device(rr_server* s, int32_t series_id,
+                                   const double* pv, int32_t npv, int32_t npar,
+                                   int32_t precision, void* out_dev,
+                                   int64_t* request_id);
+
 /* Status (RR_REQ_*, or a negative error) and, once done, the latency in
- * seconds (submission to the output being in out_host); -1 before. */
+ * seconds (submission to the output being in out_host, or to the kernels
+ * that wrote out_dev having completed); -1 before. */
 RR_API int rr_server_poll(rr_server* s, int64_t request_id, int32_t* status,
                           double* latency_s);
 
@@ -73,6 +86,12 @@ RR_API int rr_server_release(rr_server* s, int64_t request_id);
  * (npv x sum over times of nss), grouped launches issued, requests not yet
  * seen by the worker, last device error (0 if none). */
 RR_API int rr_server_stats(rr_server* s, int64_t* stats);
+
+/* Test instrumentation of the failure path: the next grouped launch is
+ * not made and is treated as failed on the host (no kernel is involved);
+ * the requests it covered finish with RR_EDEVICE and the server keeps
+ * serving the others. */
+RR_API int rr_server_fail_next_tick(rr_server* s);
 
 /* Finish all queued and running requests, then free the server. */
 RR_API void rr_server_destroy(rr_server* s);

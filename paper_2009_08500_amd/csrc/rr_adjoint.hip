@@ -19,10 +19,13 @@
 //               then waves in order) to one partial per workgroup.  With the
 //               profile gradient requested each workgroup runs several
 //               consecutive tiles, and a second subsample loop scatters
-//               psi-weighted lerp weights into the workgroup's LDS copy of
-//               d logL / d ldw and d logL / d I_star, stored once per
-//               workgroup; k_prof_seg_sum adds a vector's workgroups in order
-//               (no accumulation across workgroups).
+//               psi-weighted lerp weights into its wave's own LDS copy of
+//               d logL / d ldw and d logL / d I_star (no two waves share an
+//               address, and one wave's LDS additions complete in program
+//               order); the copies are added in wave order and stored once
+//               per workgroup, and k_prof_seg_sum adds a vector's workgroups
+//               in order.  Every sum therefore has an order fixed by the
+//               inputs alone: the gradient is bitwise reproducible.
 //   k_adjoint_reduce   per parameter vector, the workgroup partials in a
 //               fixed order (lanes over tiles, then a butterfly) -> logL and
 //               the gradient row.
@@ -194,19 +197,26 @@ __global__ __launch_bounds__(kAdjBlock) void k_adjoint(
     extern __shared__ unsigned char smem_raw[];
     constexpr int kJ = adj_times_per_thread(kProf, sizeof(R) == 8);   // times per thread
     constexpr int kTile = kAdjBlock * kJ;
+    constexpr int kWaves = kAdjBlock / 64;
     const int npb = g.npb, ng = g.ng;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     R* ldw = reinterpret_cast<R*>(smem_raw);                    // [npb][ng]
     R* dTk = ldw + npb * ng;                                    // [npb][ng]
-    double* gw = reinterpret_cast<double*>(                     // [npb][ng]
+    // per-wave copies of d logL / d ldw [kWaves][npb][ng] and
+    // d logL / d I_star [kWaves][npb] (profile instantiation only)
+    double* gw_all = reinterpret_cast<double*>(
         smem_raw + ((2 * sizeof(R) * npb * ng + 7) / 8) * 8);
-    double* gi = gw + npb * ng;                                 // [npb]
-    __shared__ double red[kAdjBlock / 64][kNq + NPBT];
-    __shared__ int wave_any[2][kAdjBlock / 64];                 // by tile parity
+    double* gi_all = gw_all + kWaves * npb * ng;
+    double* gw = gw_all + wave * npb * ng;                      // this wave's copy
+    double* gi = gi_all + wave * npb;
+    __shared__ double red[kWaves][kNq + NPBT];
+    __shared__ int wave_any[2][kWaves];                         // by tile parity
+    static_assert(sizeof(red) + sizeof(wave_any) <= kAdjStaticLds,
+                  "static LDS must fit the reserve the host budget assumes");
 
     const int64_t slot = blockIdx.x;
     const int ipv = int(slot / nparts);
     const int c = int(slot - int64_t(ipv) * nparts);
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int nq = kNq + npb;
     double* part = partials + slot * nq;
     const PvConst p = pvc[ipv];
@@ -298,9 +308,11 @@ __global__ __launch_bounds__(kAdjBlock) void k_adjoint(
                                                : T + (int64_t(pb) * g.nk + ik) * ng;
                 ldw[idx] = (R(1) - ak) * t0r[m] + ak * t0r[ng + m];
                 dTk[idx] = (t0r[ng + m] - t0r[m]) * R(g.inv_dk);
-                if (kProf) gw[idx] = 0.0;
             }
-            if (kProf && tid < npb) gi[tid] = 0.0;
+            if (kProf) {
+                for (int idx = tid; idx < kWaves * npb * ng; idx += kAdjBlock) gw_all[idx] = 0.0;
+                if (tid < kWaves * npb) gi_all[tid] = 0.0;
+            }
             __syncthreads();
             ready = true;
         }
@@ -397,16 +409,25 @@ __global__ __launch_bounds__(kAdjBlock) void k_adjoint(
 
     if (kProf) {
         __syncthreads();                 // every wave's LDS additions done
+        // the waves' copies added in wave order
+        auto wsum = [&](const double* base, int stride, int idx) {
+            double v = base[idx];
+#pragma unroll
+            for (int w = 1; w < kWaves; ++w) v += base[w * stride + idx];
+            return v;
+        };
         double* out = seg_gw + slot * npb * ng;
         if (seg_flag) {
             if (tid == 0) seg_flag[slot] = ready ? 1 : 0;
             if (ready) {
-                for (int idx = tid; idx < npb * ng; idx += kAdjBlock) out[idx] = gw[idx];
-                if (tid < npb) seg_gi[slot * npb + tid] = gi[tid];
+                for (int idx = tid; idx < npb * ng; idx += kAdjBlock)
+                    out[idx] = wsum(gw_all, npb * ng, idx);
+                if (tid < npb) seg_gi[slot * npb + tid] = wsum(gi_all, npb, tid);
             }
         } else {
-            for (int idx = tid; idx < npb * ng; idx += kAdjBlock) out[idx] = ready ? gw[idx] : 0.0;
-            if (tid < npb) seg_gi[slot * npb + tid] = ready ? gi[tid] : 0.0;
+            for (int idx = tid; idx < npb * ng; idx += kAdjBlock)
+                out[idx] = ready ? wsum(gw_all, npb * ng, idx) : 0.0;
+            if (tid < npb) seg_gi[slot * npb + tid] = ready ? wsum(gi_all, npb, tid) : 0.0;
         }
     }
 
@@ -732,7 +753,8 @@ inline unsigned nblocks(int64_t n) { return unsigned((n + kBlock - 1) / kBlock);
 // in order, then a fixed butterfly across the lanes.  Rows of tiles that go
 // to the matrix cores (k_pv_ldp_grad_mfma) are skipped.
 constexpr int kLdpBins = 16;
-__global__ __launch_bounds__(kBlock) void k_pv_ldp_grad(const double* __restrict__ W,
+template <typename WT>
+__global__ __launch_bounds__(kBlock) void k_pv_ldp_grad(const WT* __restrict__ W,
                                                         const double* __restrict__ gldw,
                                                         const double* __restrict__ pv,
                                                         int32_t npar, const int32_t* __restrict__ ikr,
@@ -761,8 +783,8 @@ __global__ __launch_bounds__(kBlock) void k_pv_ldp_grad(const double* __restrict
     for (int q = 0; q < kPerWave; ++q) {
         const int j = jc * kLdpBins + wave * kPerWave + q;
         if (j >= nz) break;                      // uniform per wave
-        const double* w0 = W + (int64_t(ik) * nz + j) * g.ng;
-        const double* w1 = w0 + int64_t(nz) * g.ng;
+        const WT* w0 = W + (int64_t(ik) * nz + j) * g.ng;
+        const WT* w1 = w0 + int64_t(nz) * g.ng;
         // eight columns' loads in flight, added in column order
         double s = 0.0;
         for (int m0 = lane; m0 < g.ng; m0 += 8 * 64) {
@@ -771,8 +793,8 @@ __global__ __launch_bounds__(kBlock) void k_pv_ldp_grad(const double* __restrict
             for (int b = 0; b < 8; ++b) {
                 const int m = m0 + 64 * b;
                 const bool in = m < g.ng;
-                x0[b] = in ? w0[m] : 0.0;
-                x1[b] = in ? w1[m] : 0.0;
+                x0[b] = in ? double(w0[m]) : 0.0;
+                x1[b] = in ? double(w1[m]) : 0.0;
                 gv[b] = in ? gr[m] : 0.0;
             }
 #pragma unroll
@@ -816,15 +838,15 @@ hipError_t launch_fill(double* p, int64_t n, hipStream_t s) {
     return hipGetLastError();
 }
 
-size_t adjoint_lds_bytes(int32_t precision, int32_t npb, int32_t ng) {
+size_t adjoint_lds_bytes(int32_t precision, int32_t npb, int32_t ng, bool prof) {
     const size_t elt = precision == RR_FP64 ? sizeof(double) : sizeof(float);
-    return ((2 * elt * size_t(npb) * ng + 7) / 8) * 8 + sizeof(double) * (size_t(npb) * ng + npb);
+    const size_t tables = ((2 * elt * size_t(npb) * ng + 7) / 8) * 8;
+    if (!prof) return tables;
+    return tables + sizeof(double) * (kAdjBlock / 64) * (size_t(npb) * ng + npb);
 }
 
 hipError_t launch_adjoint(const AdjointArgs& A, int32_t precision, hipStream_t s) {
-    const size_t lds = A.want_prof ? adjoint_lds_bytes(precision, A.g.npb, A.g.ng)
-                                   : 2 * (precision == RR_FP64 ? sizeof(double) : sizeof(float)) *
-                                         size_t(A.g.npb) * A.g.ng;
+    const size_t lds = adjoint_lds_bytes(precision, A.g.npb, A.g.ng, A.want_prof != 0);
     const KernelEvents ev = kernel_events();
     if (precision == RR_FP64) launch_adjoint_r<double>(A, lds, s, ev);
     else launch_adjoint_r<float>(A, lds, s, ev);
@@ -849,8 +871,9 @@ hipError_t launch_adjoint(const AdjointArgs& A, int32_t precision, hipStream_t s
 // v_mfma_f64_16x16x4f64 chains into one accumulator; lane layout as in
 // k_pv_tables_mfma.  Block = 4 waves = 64 bins x 16 rows.
 typedef double v4d __attribute__((ext_vector_type(4)));
+template <typename WT>
 __global__ __launch_bounds__(kBlock) void k_pv_ldp_grad_mfma(
-    const double* __restrict__ W, const double* __restrict__ gldw,
+    const WT* __restrict__ W, const double* __restrict__ gldw,
     const double* __restrict__ pv, int32_t npar, const int32_t* __restrict__ ikr,
     const int32_t* __restrict__ perm, int64_t nr, int32_t nz, GridDev g,
     double* __restrict__ gldp) {
@@ -881,8 +904,8 @@ __global__ __launch_bounds__(kBlock) void k_pv_ldp_grad_mfma(
     for (int off = 32; off > 0; off >>= 1) cur = min(cur, __shfl_xor(cur, off, 64));
     while (cur != 0x7fffffff) {
         const bool take = ik == cur;
-        const double* w0 = W + (int64_t(cur) * nz + (jin ? jj : 0)) * g.ng;
-        const double* w1 = w0 + int64_t(nz) * g.ng;
+        const WT* w0 = W + (int64_t(cur) * nz + (jin ? jj : 0)) * g.ng;
+        const WT* w1 = w0 + int64_t(nz) * g.ng;
         const double* gr = gldw + (take ? r : 0) * g.ng;
         for (int m0 = 0; m0 < g.ng; m0 += 16) {
             double a0[4], a1[4], b0[4], b1[4];
@@ -890,8 +913,8 @@ __global__ __launch_bounds__(kBlock) void k_pv_ldp_grad_mfma(
             for (int u = 0; u < 4; ++u) {               // four k-steps' loads in flight
                 const int m = m0 + 4 * u + ka;
                 const bool min_ = m < g.ng;
-                a0[u] = jin && min_ ? w0[m] : 0.0;
-                a1[u] = jin && min_ ? w1[m] : 0.0;
+                a0[u] = jin && min_ ? double(w0[m]) : 0.0;
+                a1[u] = jin && min_ ? double(w1[m]) : 0.0;
                 const double gq = take && min_ ? gr[m] : 0.0;
                 b0[u] = (1.0 - ak) * gq;
                 b1[u] = ak * gq;
@@ -916,15 +939,25 @@ __global__ __launch_bounds__(kBlock) void k_pv_ldp_grad_mfma(
 }
 
 hipError_t launch_pv_prof_grad(const rr_tables* t, const AdjointArgs& A, const int32_t* ikr,
-                               const int32_t* perm, double* gldp, double* out, hipStream_t s) {
+                               const int32_t* perm, double* gldp, double* out, hipStream_t s,
+                               bool w32) {
     const GridDev g = A.g;
     const int64_t nr = int64_t(A.npv) * g.npb;
     const int64_t nchunk = (t->nz + kLdpBins - 1) / kLdpBins;
-    hipLaunchKernelGGL(k_pv_ldp_grad_mfma, dim3(unsigned(((nr + 15) / 16) * ((t->nz + 63) / 64))),
-                       dim3(kBlock), 0, s, t->W, A.gldw_pv, A.pv, A.npar, ikr, perm, nr, t->nz, g,
-                       gldp);
-    hipLaunchKernelGGL(k_pv_ldp_grad, dim3(unsigned(nr * nchunk)), dim3(kBlock), 0, s, t->W,
-                       A.gldw_pv, A.pv, A.npar, ikr, perm, nr, t->nz, g, gldp);
+    const dim3 gm(unsigned(((nr + 15) / 16) * ((t->nz + 63) / 64)));
+    const dim3 gr(unsigned(nr * nchunk));
+    // the transpose of the contraction that built the rows, with its weights
+    if (w32) {
+        hipLaunchKernelGGL(k_pv_ldp_grad_mfma<float>, gm, dim3(kBlock), 0, s, t->W32, A.gldw_pv,
+                           A.pv, A.npar, ikr, perm, nr, t->nz, g, gldp);
+        hipLaunchKernelGGL(k_pv_ldp_grad<float>, gr, dim3(kBlock), 0, s, t->W32, A.gldw_pv, A.pv,
+                           A.npar, ikr, perm, nr, t->nz, g, gldp);
+    } else {
+        hipLaunchKernelGGL(k_pv_ldp_grad_mfma<double>, gm, dim3(kBlock), 0, s, t->W, A.gldw_pv,
+                           A.pv, A.npar, ikr, perm, nr, t->nz, g, gldp);
+        hipLaunchKernelGGL(k_pv_ldp_grad<double>, gr, dim3(kBlock), 0, s, t->W, A.gldw_pv, A.pv,
+                           A.npar, ikr, perm, nr, t->nz, g, gldp);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     // the shared profile's last step with every (vector, passband) as one

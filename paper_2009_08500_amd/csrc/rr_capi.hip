@@ -183,6 +183,11 @@ RR_API int rr_prepare_ld(const double* mu, const double* prof, int32_t nmu,
     t->dk = (grid->k1 - grid->k0) / (grid->nk - 1);
     hipError_t e = hipGetDevice(&t->device);
     if (e != hipSuccess) { delete t; return hip_fail(e, "hipGetDevice"); }
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, t->device) !=
+            hipSuccess || lds < kMinLdsBytes)
+        lds = kMinLdsBytes;
+    t->lds_max = size_t(lds);
 
     const int64_t nz = t->nz, ng = grid->ng, nk = grid->nk;
     struct { void** p; size_t bytes; } allocs[] = {
@@ -530,8 +535,9 @@ static int loglik_impl(const rr_tables* t, const double* times_d,
     if (!(sigma > 0.0) || !isfinite(sigma)) return einval("sigma must be finite and > 0");
     if (npt > 0 && npv > 0 && !obs_d) return einval("obs is NULL");
     if (npv > 0 && !logl_d && !grad_d && !grad_prof_d) return einval("no output requested");
-    if (adjoint_lds_bytes(precision, t->npb, t->grid.ng) > size_t(kMaxLdsBytes))
-        return elimit("npb * ng adjoint LDS tables exceed the 64 KiB budget");
+    if (adjoint_lds_bytes(precision, t->npb, t->grid.ng, grad_prof_d != nullptr) +
+            kAdjStaticLds > t->lds_max)
+        return elimit("npb * ng adjoint LDS tables exceed the device's LDS per workgroup");
     rc = check_device(t);
     if (rc) return rc;
     hipError_t e;
@@ -639,12 +645,14 @@ static int loglik_impl(const rr_tables* t, const double* times_d,
                          reinterpret_cast<double*>(base + o_isr),
                          reinterpret_cast<double*>(base + o_iisr),
                          reinterpret_cast<int32_t*>(base + o_ikr),
-                         reinterpret_cast<int32_t*>(base + o_perm), base + o_rows, stream);
+                         reinterpret_cast<int32_t*>(base + o_perm), base + o_rows, stream,
+                         precision == RR_MIXED);     // the rows rr_evaluate_ld evaluates
     if (e == hipSuccess) e = launch_adjoint(A, precision, stream);
     if (e == hipSuccess && prof && per_row)
         e = launch_pv_prof_grad(t, A, reinterpret_cast<const int32_t*>(base + o_ikr),
                                 reinterpret_cast<const int32_t*>(base + o_perm),
-                                reinterpret_cast<double*>(base + o_gldpr), grad_prof_d, stream);
+                                reinterpret_cast<double*>(base + o_gldpr), grad_prof_d, stream,
+                                precision == RR_MIXED);
     if (e == hipSuccess && shared_prof) {
         ProfGradScratch w;
         w.kidx = reinterpret_cast<int32_t*>(base + o_kidx);

@@ -32,8 +32,9 @@ constexpr int kFwdTile = kFwdBlock * kTimesPerThread;
 constexpr int kAdjBlock = 128;
 constexpr int adj_times_per_thread(bool prof, bool f64) { return prof && !f64 ? 8 : 16; }
 constexpr int adj_tile(bool prof, bool f64) { return kAdjBlock * adj_times_per_thread(prof, f64); }
-constexpr int kMaxLdsBytes = 64 * 1024;   // LDS budget for the adjoint's
-                                          // per-workgroup tables
+constexpr int kMinLdsBytes = 64 * 1024;   // LDS a workgroup may use on any
+                                          // device (the budget used if the
+                                          // device does not report its own)
 
 // Per-parameter-vector orbit constants, computed once per call (FP64).
 struct PvConst {
@@ -145,6 +146,7 @@ struct rr_tables {
     rr_grid grid;
     int32_t nz, npb, nmu;
     int device;
+    size_t lds_max = 0;          // LDS one workgroup may allocate on `device`
     double dk;
     // device buffers
     double* mu_s = nullptr;      // [nmu]
@@ -197,7 +199,13 @@ hipError_t launch_pv_setup(const rr_tables* t, const double* pv, int32_t npv,
                            int32_t npar, PvConst* pvc, hipStream_t s);
 hipError_t launch_pv_setup_k(const double* pv, int32_t npv, int32_t npar, double k_lo,
                              double k_hi, PvConst* pvc, hipStream_t s, double k_small = 0.0);
-size_t adjoint_lds_bytes(int32_t precision, int32_t npb, int32_t ng);
+// Dynamic LDS of one log-likelihood workgroup: the k-interpolated LD
+// vectors and their k-derivatives, plus (prof) each wave's copy of
+// d logL / d ldw and d logL / d I_star.
+size_t adjoint_lds_bytes(int32_t precision, int32_t npb, int32_t ng, bool prof);
+// What the log-likelihood kernel declares in LDS statically (an upper
+// bound): the dynamic part must fit in lds_max less this.
+constexpr size_t kAdjStaticLds = 512;
 hipError_t launch_adjoint(const AdjointArgs& a, int32_t precision, hipStream_t s);
 // Temporaries of the profile gradient.
 struct ProfGradScratch {
@@ -215,8 +223,10 @@ struct ProfGradScratch {
 // Per-vector LD: d logL / d prof[ipv][pb][s] from the adjoint's per-vector
 // d logL / d ldw and d logL / d I_star; ikr and perm are launch_pv_ld's sort
 // of the rows by k-row, gldp is [npv][npb][nz] scratch.
+// w32: the weights are the FP32 copy (the mixed per-vector rows' own).
 hipError_t launch_pv_prof_grad(const rr_tables* t, const AdjointArgs& A, const int32_t* ikr,
-                               const int32_t* perm, double* gldp, double* out, hipStream_t s);
+                               const int32_t* perm, double* gldp, double* out, hipStream_t s,
+                               bool w32);
 hipError_t launch_profile_grad(const rr_tables* t, const AdjointArgs& a,
                                const ProfGradScratch& w, double* out, hipStream_t s);
 hipError_t launch_fill(double* p, int64_t n, hipStream_t s);

@@ -180,12 +180,14 @@ hipError_t launch_prepare_grid_weights(rr_tables* t, hipStream_t s) {
 // Per-vector LD rows.  Row r = (vector, passband) needs the two table rows
 // T_r[s][m] = sum_j W[ik_r + s][j][m] ldp[r][j], s = 0, 1, around its k
 // (Sect. 3.1.2: T = W . l, then the k-interpolation in the forward kernel).
-// k_pv_prep sorts the rows by ik (counting sort in one workgroup; the order
-// within a bin is arbitrary and does not affect any result), so that rows
-// with equal ik share the W reads of one matrix-core tile
-// (k_pv_tables_mfma, k_pv_tables below).
-// Counting sort of the rows by ik, by one workgroup of kBlock threads
-// (thread t owns bins 16 t .. 16 t + 15 of at most 4096).
+// k_pv_prep sorts the rows by ik, so that rows with equal ik share the W
+// reads of one matrix-core tile (k_pv_tables_mfma, k_pv_tables below).
+// Stable counting sort of the rows by ik, by one workgroup of kBlock
+// threads (thread t owns bins 16 t .. 16 t + 15 of at most 4096): the
+// histogram and its scan by all waves, then one wave places the rows in
+// row order, 64 at a time -- a lane's rank among the lanes with its key
+// comes from a ballot per key bit -- so equal keys keep their row order
+// and the tiles (and which kernel takes each) depend on the inputs only.
 __device__ inline void sort_rows(const double* __restrict__ pv, int32_t npv, int32_t npar,
                                  const GridDev& g, int32_t* __restrict__ ikr,
                                  int32_t* __restrict__ perm) {
@@ -232,7 +234,30 @@ __device__ inline void sort_rows(const double* __restrict__ pv, int32_t npv, int
         excl += v[q];
     }
     __syncthreads();
-    for (int64_t r = tid; r < n; r += kBlock) perm[atomicAdd(&cnt[ikr[r]], 1)] = int32_t(r);
+    if (wave != 0) return;
+    for (int64_t r0 = 0; r0 < n; r0 += 64) {
+        const int64_t r = r0 + lane;
+        const bool in = r < n;
+        const int key = in ? ikr[r] : 0;
+        uint64_t same = __ballot(in);            // lanes with this lane's key
+#pragma unroll
+        for (int b = 0; b < 12; ++b) {           // keys < nk <= 4096
+            const bool bit = (key >> b) & 1;
+            const uint64_t ones = __ballot(in && bit);
+            same &= bit ? ones : ~ones;
+        }
+        const int base = in ? cnt[key] : 0;
+        if (in) perm[base + __popcll(same & __lanemask_lt())] = int32_t(r);
+        // every lane has read its key's offset before the first lane of each
+        // key group (the only writer of that key) advances it
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (in && (same & __lanemask_lt()) == 0) cnt[key] = base + __popcll(same);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
 }
 
 // One launch for the per-vector preparation: workgroup r < nr interpolates
@@ -327,8 +352,8 @@ __global__ __launch_bounds__(kBlock) void k_pv_tables(const WT* __restrict__ W,
 // Lane l holds A[l & 15][l >> 4], B[l >> 4][l & 15] and D[4 i + (l >> 4)][l & 15]
 // (checked on the device).  Block = 4 waves = 64 m x 16 rows.
 typedef double v4d __attribute__((ext_vector_type(4)));
-template <typename R>
-__global__ __launch_bounds__(kBlock) void k_pv_tables_mfma(const double* __restrict__ W,
+template <typename R, typename WT>
+__global__ __launch_bounds__(kBlock) void k_pv_tables_mfma(const WT* __restrict__ W,
                                                            const double* __restrict__ ldp,
                                                            const int32_t* __restrict__ ikr,
                                                            const int32_t* __restrict__ perm,
@@ -356,8 +381,8 @@ __global__ __launch_bounds__(kBlock) void k_pv_tables_mfma(const double* __restr
     for (int off = 32; off > 0; off >>= 1) cur = min(cur, __shfl_xor(cur, off, 64));
     while (cur != 0x7fffffff) {
         const bool take = ik == cur;
-        const double* w0 = W + int64_t(cur) * nz * g.ng + (mok ? mm : 0);
-        const double* w1 = w0 + int64_t(nz) * g.ng;
+        const WT* w0 = W + int64_t(cur) * nz * g.ng + (mok ? mm : 0);
+        const WT* w1 = w0 + int64_t(nz) * g.ng;
         const double* lr = ldp + (take ? r : 0) * nz;
         for (int j0 = 0; j0 < nz; j0 += 16) {
             double a0[4], a1[4], b[4];
@@ -365,8 +390,8 @@ __global__ __launch_bounds__(kBlock) void k_pv_tables_mfma(const double* __restr
             for (int u = 0; u < 4; ++u) {               // four k-steps' loads in flight
                 const int j = j0 + 4 * u + ka;
                 const bool jin = j < nz;
-                a0[u] = jin && mok ? w0[int64_t(j) * g.ng] : 0.0;
-                a1[u] = jin && mok ? w1[int64_t(j) * g.ng] : 0.0;
+                a0[u] = jin && mok ? double(w0[int64_t(j) * g.ng]) : 0.0;
+                a1[u] = jin && mok ? double(w1[int64_t(j) * g.ng]) : 0.0;
                 b[u] = jin && take ? lr[j] : 0.0;
             }
 #pragma unroll
@@ -629,20 +654,23 @@ hipError_t launch_pv_ld(const rr_tables* t, const double* prof, const double* pv
     if (e != hipSuccess) return e;
     const dim3 grid(unsigned(((nr + 15) / 16) * ((g.ng + 63) / 64)));
     const dim3 grid_rows(unsigned(nr * ((g.ng + kBlock - 1) / kBlock)));
+    // both kernels read the same weights (FP64, or the FP32 copy with w32),
+    // so a row's values do not depend on which kernel its tile went to
     if (precision == RR_FP64) {
-        hipLaunchKernelGGL(k_pv_tables_mfma<double>, grid, dim3(kBlock), 0, s, t->W, ldp, ikr,
-                           perm, nr, t->nz, g, static_cast<double*>(rows));
+        hipLaunchKernelGGL((k_pv_tables_mfma<double, double>), grid, dim3(kBlock), 0, s, t->W,
+                           ldp, ikr, perm, nr, t->nz, g, static_cast<double*>(rows));
         hipLaunchKernelGGL((k_pv_tables<double, double>), grid_rows, dim3(kBlock), 0, s, t->W,
                            ldp, ikr, perm, t->nz, g, static_cast<double*>(rows));
+    } else if (w32) {
+        hipLaunchKernelGGL((k_pv_tables_mfma<float, float>), grid, dim3(kBlock), 0, s, t->W32,
+                           ldp, ikr, perm, nr, t->nz, g, static_cast<float*>(rows));
+        hipLaunchKernelGGL((k_pv_tables<float, float>), grid_rows, dim3(kBlock), 0, s,
+                           t->W32, ldp, ikr, perm, t->nz, g, static_cast<float*>(rows));
     } else {
-        hipLaunchKernelGGL(k_pv_tables_mfma<float>, grid, dim3(kBlock), 0, s, t->W, ldp, ikr,
-                           perm, nr, t->nz, g, static_cast<float*>(rows));
-        if (w32)
-            hipLaunchKernelGGL((k_pv_tables<float, float>), grid_rows, dim3(kBlock), 0, s,
-                               t->W32, ldp, ikr, perm, t->nz, g, static_cast<float*>(rows));
-        else
-            hipLaunchKernelGGL((k_pv_tables<float, double>), grid_rows, dim3(kBlock), 0, s,
-                               t->W, ldp, ikr, perm, t->nz, g, static_cast<float*>(rows));
+        hipLaunchKernelGGL((k_pv_tables_mfma<float, double>), grid, dim3(kBlock), 0, s, t->W,
+                           ldp, ikr, perm, nr, t->nz, g, static_cast<float*>(rows));
+        hipLaunchKernelGGL((k_pv_tables<float, double>), grid_rows, dim3(kBlock), 0, s,
+                           t->W, ldp, ikr, perm, t->nz, g, static_cast<float*>(rows));
     }
     return hipGetLastError();
 }

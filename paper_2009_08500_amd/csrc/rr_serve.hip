@@ -2,9 +2,10 @@
 //
 // Time series are registered once and stay on the device with the LD
 // tables.  A request is a population of parameter rows against one series;
-// its footprint (rows, per-row constants, output) is carved from a device
-// arena sized at creation, and requests are admitted in arrival order as
-// arena space frees up.  A worker thread cuts every admitted request into
+// its footprint (rows, per-row constants, and the output unless the caller
+// gives a device buffer for it) is carved from a device arena sized at
+// creation, and requests are admitted in arrival order as arena space
+// frees up.  A worker thread cuts every admitted request into
 // (row x time-tile) workgroups and packs workgroups of all admitted requests
 // into "ticks": one grouped forward launch per precision, at most
 // max_tick_blocks workgroups, each active request first getting a fair
@@ -12,8 +13,12 @@
 // alternate over two streams, so a tick's kernels overlap the next one's
 // and requests that arrive while others run join the next tick.  When all
 // rows of a request are done its output is copied to the caller's host
-// buffer and its arena space is released; latency is completion minus
-// submission, on the host's steady clock.
+// buffer (host-output requests) or is already in the caller's device
+// buffer (device-output requests), and its arena space is released;
+// latency is completion minus submission, on the host's steady clock.
+// A request keeps its own copy of its series' description, taken at
+// submission under the lock, so the worker never reads the series list
+// that rr_server_add_series may grow concurrently.
 //
 // Every request runs the same forward_block() code as rr_evaluate, so its
 // results do not depend on what it was batched with.
@@ -55,8 +60,10 @@ enum ReqState { kQueued = 0, kRunning = 1, kDone = 2 };
 struct Request {
     int64_t id = 0;
     int32_t series = 0, npv = 0, npar = 0, precision = 0;
+    Series se;                 // the series' description, copied at submission
     std::vector<double> pv;
-    void* out_host = nullptr;
+    void* out_host = nullptr;  // host output, or
+    void* out_user = nullptr;  // the caller's device output buffer
     size_t out_bytes = 0, off = 0, bytes = 0;
     double* pv_dev = nullptr;
     PvConst* pvc_dev = nullptr;
@@ -69,6 +76,9 @@ struct Request {
     std::atomic<int> err{RR_OK};
 };
 
+// A grouped launch and the request rows it covers.  ev == nullptr marks a
+// tick whose launch failed: its stream was synchronised instead, so it
+// counts as complete (its requests carry RR_EDEVICE).
 struct Tick {
     hipEvent_t ev = nullptr;
     std::vector<std::pair<Request*, int32_t>> parts;
@@ -141,20 +151,37 @@ struct rr_server {
     std::vector<Request*> copying;
     std::deque<Tick> ticks;
     int tick_stream = 0;
+    std::atomic<int> fail_next_tick{0};   // test hook: fail the next tick's launch
     // statistics (guarded by mu)
     int64_t completed = 0, points = 0, nticks = 0;
     int last_error = RR_OK;
 
-    size_t footprint(int32_t npv, int32_t npar, int32_t npt, int32_t precision) const {
+    size_t footprint(int32_t npv, int32_t npar, int32_t npt, int32_t precision,
+                     bool device_out) const {
         const size_t elt = precision == RR_FP64 ? 8 : 4;
         auto r = [](size_t b) { return (b + 255) / 256 * 256; };
         return r(size_t(npv) * npar * 8) + r(size_t(npv) * sizeof(PvConst)) +
-               r(size_t(npv) * npt * elt);
+               (device_out ? 0 : r(size_t(npv) * npt * elt));
     }
 
     void run();
     bool step();
+    void finish(Request* r);
 };
+
+// Release a request's arena space and mark it done (worker thread).
+void rr_server::finish(Request* r) {
+    const double t = now_s();
+    arena.release(r->off, r->bytes);
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        r->t_done = t;
+        r->state = kDone;
+        completed += 1;
+        points += int64_t(r->npv) * r->se.nsub;
+    }
+    cv_done.notify_all();
+}
 
 bool rr_server::step() {
     bool did = false;
@@ -166,21 +193,30 @@ bool rr_server::step() {
         }
     }
     // 1. completed ticks (in order)
-    while (!ticks.empty() && hipEventQuery(ticks.front().ev) == hipSuccess) {
+    while (!ticks.empty() &&
+           (!ticks.front().ev || hipEventQuery(ticks.front().ev) == hipSuccess)) {
         Tick& tk = ticks.front();
         for (auto& pr : tk.parts) {
             Request* r = pr.first;
             r->rows_done += pr.second;
             if (r->rows_done == r->npv && !r->copying) {
                 r->copying = true;
+                if (r->out_user || r->err != RR_OK) {
+                    // the rows are in the caller's device buffer (or failed)
+                    finish(r);
+                    continue;
+                }
                 hipError_t e = hipMemcpyAsync(r->out_host, r->out_dev, r->out_bytes,
                                               hipMemcpyDeviceToHost, copy_stream);
                 if (e == hipSuccess) e = hipEventRecord(r->done_ev, copy_stream);
-                if (e != hipSuccess) r->err = RR_EDEVICE;
+                if (e != hipSuccess) {
+                    (void)hipStreamSynchronize(copy_stream);
+                    r->err = RR_EDEVICE;
+                }
                 copying.push_back(r);
             }
         }
-        (void)hipEventDestroy(tk.ev);
+        if (tk.ev) (void)hipEventDestroy(tk.ev);
         ticks.pop_front();
         did = true;
     }
@@ -188,16 +224,7 @@ bool rr_server::step() {
     for (size_t i = 0; i < copying.size();) {
         Request* r = copying[i];
         if (r->err != RR_OK || hipEventQuery(r->done_ev) == hipSuccess) {
-            const double t = now_s();
-            arena.release(r->off, r->bytes);
-            {
-                std::lock_guard<std::mutex> lk(mu);
-                r->t_done = t;
-                r->state = kDone;
-                completed += 1;
-                points += int64_t(r->npv) * series[r->series].nsub;
-            }
-            cv_done.notify_all();
+            finish(r);
             copying[i] = copying.back();
             copying.pop_back();
             did = true;
@@ -220,7 +247,7 @@ bool rr_server::step() {
         const size_t pcb = (size_t(r->npv) * sizeof(PvConst) + 255) / 256 * 256;
         r->pv_dev = reinterpret_cast<double*>(base);
         r->pvc_dev = reinterpret_cast<PvConst*>(base + pvb);
-        r->out_dev = base + pvb + pcb;
+        r->out_dev = r->out_user ? r->out_user : base + pvb + pcb;
         hipError_t e = hipMemcpyAsync(r->pv_dev, r->pv.data(), size_t(r->npv) * r->npar * 8,
                                       hipMemcpyHostToDevice, setup_stream);
         if (e != hipSuccess) r->err = RR_EDEVICE;
@@ -259,7 +286,7 @@ bool rr_server::step() {
                 if (left <= 0) break;
                 const int p = r->precision == RR_FP64 ? 0 : 1;
                 if (jt[p].njobs >= kMaxJobs) continue;
-                const Series& se = series[r->series];
+                const Series& se = r->se;
                 const int32_t remaining = r->npv - r->next_row;
                 if (remaining <= 0) continue;
                 const int32_t cap = pass == 0 ? std::min(share, left) : left;
@@ -282,11 +309,17 @@ bool rr_server::step() {
             hipStream_t s = streams[tick_stream];
             tick_stream ^= 1;
             hipError_t e = hipStreamWaitEvent(s, setup_ev, 0);
+            if (e == hipSuccess && fail_next_tick.exchange(0)) e = hipErrorLaunchFailure;
             for (int p = 0; p < 2 && e == hipSuccess; ++p)
                 e = launch_forward_jobs(t, jt[p], nb[p], p == 0 ? RR_FP64 : RR_MIXED, s);
             if (e == hipSuccess) e = hipEventCreateWithFlags(&tk.ev, hipEventDisableTiming);
             if (e == hipSuccess) e = hipEventRecord(tk.ev, s);
             if (e != hipSuccess) {
+                // whatever did launch finishes before the tick counts as
+                // complete, so no arena space is released under a kernel
+                if (tk.ev) (void)hipEventDestroy(tk.ev);
+                tk.ev = nullptr;
+                (void)hipStreamSynchronize(s);
                 last_error = RR_EDEVICE;
                 for (auto& pr : tk.parts) pr.first->err = RR_EDEVICE;
             }
@@ -405,11 +438,11 @@ RR_API int rr_server_add_series(rr_server* s, const double* times, const int32_t
     return RR_OK;
 }
 
-RR_API int rr_server_submit(rr_server* s, int32_t series_id, const double* pv, int32_t npv,
-                            int32_t npar, int32_t precision, void* out_host,
-                            int64_t* request_id) {
+static int submit_impl(rr_server* s, int32_t series_id, const double* pv, int32_t npv,
+                       int32_t npar, int32_t precision, void* out_host, void* out_dev,
+                       int64_t* request_id) {
     if (!s || !request_id) { set_error("server or request_id is NULL"); return RR_EINVAL; }
-    if (!pv || !out_host) { set_error("pv and out are required"); return RR_EINVAL; }
+    if (!pv || (!out_host && !out_dev)) { set_error("pv and out are required"); return RR_EINVAL; }
     if (npv < 1) { set_error("npv must be >= 1"); return RR_EINVAL; }
     if (npar != 6 + s->t->npb) { set_error("npar must equal 6 + npb of the tables"); return RR_EINVAL; }
     if (precision != RR_FP64 && precision != RR_MIXED) { set_error("bad precision"); return RR_EINVAL; }
@@ -423,9 +456,11 @@ RR_API int rr_server_submit(rr_server* s, int32_t series_id, const double* pv, i
             set_error("unknown series id");
             return RR_EINVAL;
         }
-        npt = s->series[series_id].npt;
+        r->se = s->series[series_id];
+        npt = r->se.npt;
     }
-    r->bytes = s->footprint(npv, npar, npt, precision);
+    r->out_user = out_dev;
+    r->bytes = s->footprint(npv, npar, npt, precision, out_dev != nullptr);
     if (r->bytes > s->budget) {
         delete r;
         set_error("request footprint exceeds the server's memory budget");
@@ -451,6 +486,26 @@ RR_API int rr_server_submit(rr_server* s, int32_t series_id, const double* pv, i
     }
     s->cv_work.notify_one();
     *request_id = r->id;
+    return RR_OK;
+}
+
+RR_API int rr_server_submit(rr_server* s, int32_t series_id, const double* pv, int32_t npv,
+                            int32_t npar, int32_t precision, void* out_host,
+                            int64_t* request_id) {
+    if (!out_host) { set_error("out is required"); return RR_EINVAL; }
+    return submit_impl(s, series_id, pv, npv, npar, precision, out_host, nullptr, request_id);
+}
+
+RR_API int rr_server_submit_device(rr_server* s, int32_t series_id, const double* pv,
+                                   int32_t npv, int32_t npar, int32_t precision, void* out_dev,
+                                   int64_t* request_id) {
+    if (!out_dev) { set_error("out is required"); return RR_EINVAL; }
+    return submit_impl(s, series_id, pv, npv, npar, precision, nullptr, out_dev, request_id);
+}
+
+RR_API int rr_server_fail_next_tick(rr_server* s) {
+    if (!s) { set_error("server is NULL"); return RR_EINVAL; }
+    s->fail_next_tick.store(1);
     return RR_OK;
 }
 

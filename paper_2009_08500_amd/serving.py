@@ -21,20 +21,24 @@ def _declare(L):
     L.rr_server_create.argtypes = [v, i64, i32, ctypes.POINTER(v)]
     L.rr_server_add_series.argtypes = [v, v, v, i32, v, v, v, i32, ctypes.POINTER(i32)]
     L.rr_server_submit.argtypes = [v, i32, v, i32, i32, i32, v, ctypes.POINTER(i64)]
+    L.rr_server_submit_device.argtypes = [v, i32, v, i32, i32, i32, v, ctypes.POINTER(i64)]
+    L.rr_server_fail_next_tick.argtypes = [v]
     L.rr_server_poll.argtypes = [v, i64, ctypes.POINTER(i32), ctypes.POINTER(dbl)]
     L.rr_server_wait.argtypes = [v, i64, dbl, ctypes.POINTER(dbl)]
     L.rr_server_release.argtypes = [v, i64]
     L.rr_server_stats.argtypes = [v, ctypes.POINTER(i64)]
     L.rr_server_destroy.argtypes = [v]
     L.rr_server_destroy.restype = None
-    for f in ("rr_server_create", "rr_server_add_series", "rr_server_submit", "rr_server_poll",
+    for f in ("rr_server_create", "rr_server_add_series", "rr_server_submit",
+              "rr_server_submit_device", "rr_server_fail_next_tick", "rr_server_poll",
               "rr_server_wait", "rr_server_release", "rr_server_stats"):
         getattr(L, f).restype = ctypes.c_int
     L._rr_serve_declared = True
 
 
 class Request:
-    """A submitted request: its id and the page-locked host output buffer."""
+    """A submitted request: its id and its output buffer (page-locked host
+    memory, or a device tensor for ``submit(..., device_out=True)``)."""
 
     def __init__(self, rid, out, npv, npt):
         self.id, self.out, self.npv, self.npt = rid, out, npv, npt
@@ -73,18 +77,39 @@ class Server:
         self.series_npt[sid.value] = npt
         return sid.value
 
-    def submit(self, series_id, pv, precision="mixed"):
+    def submit(self, series_id, pv, precision="mixed", device_out=False, out=None):
+        """Queue rows ``pv`` against a registered series.  The output goes to
+        page-locked host memory (rr_server_submit), or with ``device_out``
+        to a device tensor (``out``, or a new one) that the kernels write
+        directly (rr_server_submit_device); read it only once the request is
+        done."""
         prec = PRECISIONS[precision]
         pv = np.ascontiguousarray(np.atleast_2d(np.asarray(pv, np.float64)))
         npv, npar = pv.shape
         npt = self.series_npt.get(series_id, 1)
-        out = torch.empty((npv, npt), dtype=torch.float64 if prec == RR_FP64 else torch.float32,
-                          pin_memory=True)
+        dtype = torch.float64 if prec == RR_FP64 else torch.float32
         rid = ctypes.c_int64()
-        check(self.L.rr_server_submit(self._h, series_id, _ptr(pv), npv, npar, prec,
-                                      ctypes.c_void_p(out.data_ptr()), ctypes.byref(rid)),
-              "rr_server_submit")
+        if device_out:
+            if out is None:
+                out = torch.empty((npv, npt), dtype=dtype, device="cuda")
+            elif (not out.is_cuda or out.dtype != dtype or not out.is_contiguous()
+                  or out.numel() != npv * npt):
+                raise ValueError("out must be a contiguous device tensor of npv x npt")
+            check(self.L.rr_server_submit_device(self._h, series_id, _ptr(pv), npv, npar, prec,
+                                                 ctypes.c_void_p(out.data_ptr()),
+                                                 ctypes.byref(rid)),
+                  "rr_server_submit_device")
+        else:
+            out = torch.empty((npv, npt), dtype=dtype, pin_memory=True)
+            check(self.L.rr_server_submit(self._h, series_id, _ptr(pv), npv, npar, prec,
+                                          ctypes.c_void_p(out.data_ptr()), ctypes.byref(rid)),
+                  "rr_server_submit")
         return Request(rid.value, out, npv, npt)
+
+    def fail_next_tick(self):
+        """Test hook: the next grouped launch is treated as failed on the
+        host (rr_server_fail_next_tick)."""
+        check(self.L.rr_server_fail_next_tick(self._h), "rr_server_fail_next_tick")
 
     def poll(self, req):
         st, lat = ctypes.c_int32(), ctypes.c_double()

@@ -152,14 +152,42 @@ def test_loglik_only_and_invalid_rows(rr):
     assert np.isnan(g2.cpu().numpy()[2]).all()
 
 
-def test_deterministic(rr):
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_deterministic(rr, precision):
+    """Every sum has an order fixed by the inputs: logL, the parameter
+    gradient and the profile gradient (shared profile, one or several
+    workgroups per vector, with per-row weights) are bitwise equal across
+    calls, and so are the per-walker profile gradients."""
+    import torch
     w, grid, otab, obs = make(npv=32, npt=8000, nss=2, span=30.0)
     tab = rr.Tables(w["mu_s"], w["I_s"], grid)
     ser = rr.TimeSeries(w["times"], nss=w["nss"], exptimes=w["exptimes"])
-    a = rr.loglik_grad(tab, ser, w["pv"], obs, w["sigma"], "fp64")
-    b = rr.loglik_grad(tab, ser, w["pv"], obs, w["sigma"], "fp64")
-    assert np.array_equal(a[0].cpu().numpy(), b[0].cpu().numpy())
-    assert np.array_equal(a[1].cpu().numpy(), b[1].cpu().numpy())
+    wprof = torch.linspace(0.5, 1.5, 32, device="cuda", dtype=torch.float64)
+
+    def call():
+        out = rr.loglik_grad(tab, ser, w["pv"], obs, w["sigma"], precision, grad=True,
+                             profile=True)
+        out2 = rr.loglik_grad(tab, ser, w["pv"], obs, w["sigma"], precision, grad=True,
+                              profile=True, wprof=wprof)
+        prof = np.broadcast_to(w["I_s"], (32, w["mu_s"].size)).copy()
+        out3 = rr.loglik_grad_ld(tab, ser, w["pv"], prof, obs, w["sigma"], precision)
+        return [x.cpu().numpy() for x in (*out, *out2, *out3)]
+
+    a = call()
+    for _ in range(2):
+        b = call()
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
+    # one workgroup per vector (all times in one tile)
+    w1, grid1, _, obs1 = make(npv=5, npt=900, nss=2, span=4.0)
+    tab1 = rr.Tables(w1["mu_s"], w1["I_s"], grid1)
+    ser1 = rr.TimeSeries(w1["times"], nss=w1["nss"], exptimes=w1["exptimes"])
+    r1 = [x.cpu().numpy() for x in rr.loglik_grad(tab1, ser1, w1["pv"], obs1, w1["sigma"],
+                                                  precision, profile=True)]
+    r2 = [x.cpu().numpy() for x in rr.loglik_grad(tab1, ser1, w1["pv"], obs1, w1["sigma"],
+                                                  precision, profile=True)]
+    for x, y in zip(r1, r2):
+        assert np.array_equal(x, y)
 
 
 def test_autograd_through_ld_coefficients(rr):

@@ -140,3 +140,28 @@ def test_arguments(rr):
                                    pb, nss, ex, nlc, ctypes.c_void_p(pv.data_ptr()), 3, 7, None,
                                    0, ctypes.c_void_p(o.data_ptr()), None)
     assert rc == _lib.RR_EINVAL and "prof" in _lib.last_error()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_deterministic_and_independent_of_batch(rr, precision):
+    """The rows are sorted stably by k-row and both table kernels read the
+    same weights, so two identical calls agree bitwise, and a row's fluxes do
+    not depend on which rows share its call: row 50 sits in a 32-row cluster
+    on one k-row (a matrix-core tile) in one call and among rows spread over
+    many k-rows (the per-row kernel) in another.  Only the order of the FP64
+    additions over bins differs between the two kernels, which rounds to the
+    same float table values in mixed precision."""
+    w = wl.population_ld(npv=96, npt=4000)
+    tab = rr.Tables(w["mu_s"], w["I_s"], wl.TEST_GRID)
+    ser = rr.TimeSeries(w["times"])
+    pv, prof = w["pv"].copy(), w["prof"].copy()
+    pv[40:72, 6] = pv[40, 6]                 # a cluster on one k-row
+    a = rr.evaluate_ld(tab, ser, pv, prof, precision).cpu().numpy()
+    b = rr.evaluate_ld(tab, ser, pv, prof, precision).cpu().numpy()
+    assert np.array_equal(a, b)
+    rows = [50] + list(range(31))            # two 16-row tiles over many k-rows
+    c = rr.evaluate_ld(tab, ser, pv[rows], prof[rows], precision).cpu().numpy()
+    if precision == "fp64":
+        assert np.abs(c[0] - a[50]).max() <= 1e-13
+    else:
+        assert np.array_equal(c[0], a[50])

@@ -102,3 +102,103 @@ def test_admission_by_footprint(env):
     with pytest.raises(rr.RRError):
         srv.submit(sid, pv[:, :7], "mixed")               # npar mismatch
     srv.close()
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_device_output_equals_host_output(env, prec):
+    """rr_server_submit_device: the kernels write the caller's device buffer
+    (no host copy); its values equal the host-output form and rr_evaluate
+    bitwise, mixed with host-output requests in the same ticks."""
+    import torch
+    rr, tab, otab, series, reqs = env
+    srv = rr.Server(tab, budget_bytes=1 << 30, max_tick_blocks=512)
+    sids = [srv.add_series(s["times"], s["lcids"], s["pbids"], s["nss"], s["exptimes"])
+            for s in series]
+    hd, hh = [], []
+    for r in reqs[:16]:
+        hd.append(srv.submit(sids[r["series"]], r["pv"], prec, device_out=True))
+        hh.append(srv.submit(sids[r["series"]], r["pv"], prec))
+    for r, a, b in zip(reqs[:16], hd, hh):
+        srv.wait(a)
+        srv.wait(b)
+        assert a.out.is_cuda and a.latency > 0
+        dev = a.out.cpu().numpy()
+        assert np.array_equal(dev, b.out.numpy())
+        assert np.array_equal(dev, evaluate_direct(rr, tab, series[r["series"]], r["pv"], prec))
+    # footprint without the output: a request whose output alone exceeds the
+    # arena is admitted in device-output form
+    small = rr.Server(tab, budget_bytes=1 << 20, max_tick_blocks=256)
+    se = series[0]
+    sid = small.add_series(se["times"], se["lcids"], se["pbids"], se["nss"], se["exptimes"])
+    npt = se["times"].size
+    nrow = (2 << 20) // (npt * 4) + 1                     # > 2 MiB of float output
+    pv = wl.draw_orbits(np.random.default_rng(5), nrow, npb=4, chromatic=0.05)
+    with pytest.raises(rr.RRError):
+        small.submit(sid, pv, "mixed")
+    out = torch.empty((nrow, npt), dtype=torch.float32, device="cuda")
+    h = small.submit(sid, pv, "mixed", device_out=True, out=out)
+    small.wait(h)
+    assert np.array_equal(out.cpu().numpy(), evaluate_direct(rr, tab, se, pv, "mixed"))
+    small.close()
+    srv.close()
+
+
+def test_series_added_while_requests_run(env):
+    """Series registered from another thread while requests are queued and
+    running: every request completes with the values of rr_evaluate (each
+    request works from its own copy of its series' description)."""
+    import threading
+    rr, tab, otab, series, reqs = env
+    srv = rr.Server(tab, budget_bytes=1 << 30, max_tick_blocks=256)
+    sids = [srv.add_series(s["times"], s["lcids"], s["pbids"], s["nss"], s["exptimes"])
+            for s in series[:2]]
+    extra = []
+    stop = threading.Event()
+
+    def add_many():
+        k = 0
+        while not stop.is_set() and k < 200:
+            se = series[k % len(series)]
+            extra.append(srv.add_series(se["times"], se["lcids"], se["pbids"], se["nss"],
+                                        se["exptimes"]))
+            k += 1
+
+    th = threading.Thread(target=add_many)
+    th.start()
+    hs = [(r, srv.submit(sids[r["series"] % 2], r["pv"][:32], "mixed")) for r in reqs[:24]]
+    th.join()
+    stop.set()
+    for r, h in hs:
+        srv.wait(h)
+        ref = evaluate_direct(rr, tab, series[r["series"] % 2], r["pv"][:32], "mixed")
+        assert np.array_equal(h.out.numpy(), ref)
+    assert len(extra) == 200
+    h = srv.submit(extra[-1], reqs[0]["pv"][:4], "mixed")       # a series added last
+    srv.wait(h)
+    assert np.array_equal(h.out.numpy(),
+                          evaluate_direct(rr, tab, series[199 % len(series)], reqs[0]["pv"][:4],
+                                          "mixed"))
+    srv.close()
+
+
+def test_failed_launch_completes_requests_with_error(env):
+    """A grouped launch that fails (forced on the host: no kernel runs) ends
+    its requests with RR_EDEVICE instead of leaving them pending; later
+    requests are served and the server shuts down."""
+    rr, tab, otab, series, reqs = env
+    srv = rr.Server(tab, budget_bytes=1 << 30, max_tick_blocks=1 << 20)
+    se = series[0]
+    sid = srv.add_series(se["times"], se["lcids"], se["pbids"], se["nss"], se["exptimes"])
+    pv = reqs[0]["pv"][:8]
+    ok = srv.submit(sid, pv, "mixed")
+    srv.wait(ok)
+    srv.fail_next_tick()
+    bad = srv.submit(sid, pv, "mixed")
+    with pytest.raises(rr.RRError) as e:
+        srv.wait(bad)
+    assert e.value.code == -3                              # RR_EDEVICE
+    assert srv.stats()["last_error"] == -3
+    again = srv.submit(sid, pv, "mixed")
+    srv.wait(again)
+    assert np.array_equal(again.out.numpy(), ok.out.numpy())
+    srv.close()
