@@ -146,15 +146,17 @@ def test_arguments(rr):
 def test_deterministic_and_independent_of_batch(rr, precision):
     """The rows are sorted stably by k-row and both table kernels read the
     same weights, so two identical calls agree bitwise, and a row's fluxes do
-    not depend on which rows share its call: row 50 sits in a 32-row cluster
-    on one k-row (a matrix-core tile) in one call and among rows spread over
-    many k-rows (the per-row kernel) in another.  Only the order of the FP64
-    additions over bins differs between the two kernels, which rounds to the
-    same float table values in mixed precision."""
+    not depend on which rows share its call beyond rounding: row 50 sits in a
+    32-row cluster on one k-row (a matrix-core tile) in one call and among
+    rows spread over many k-rows (the per-row kernel) in another.  Only the
+    order of the FP64 additions over bins differs between the two kernels;
+    in mixed precision that can move a table value by one float ulp when the
+    two sums round to different sides of a float, so the bound there is a
+    few float ulps of the flux deficit."""
     w = wl.population_ld(npv=96, npt=4000)
     tab = rr.Tables(w["mu_s"], w["I_s"], wl.TEST_GRID)
     ser = rr.TimeSeries(w["times"])
-    pv, prof = w["pv"].copy(), w["prof"].copy()
+    pv, prof = w["pv"].copy(), w["prof_pv"].copy()
     pv[40:72, 6] = pv[40, 6]                 # a cluster on one k-row
     a = rr.evaluate_ld(tab, ser, pv, prof, precision).cpu().numpy()
     b = rr.evaluate_ld(tab, ser, pv, prof, precision).cpu().numpy()
@@ -164,4 +166,4 @@ def test_deterministic_and_independent_of_batch(rr, precision):
     if precision == "fp64":
         assert np.abs(c[0] - a[50]).max() <= 1e-13
     else:
-        assert np.array_equal(c[0], a[50])
+        assert np.abs(c[0].astype(np.float64) - a[50]).max() <= 2e-7
