@@ -161,6 +161,29 @@ RR_API int rr_evaluate(const rr_tables* t, const double* times_d,
                        const double* pv_d, int32_t npv, int32_t npar,
                        int32_t precision, void* out_d, hipStream_t stream);
 
+/* rr_evaluate for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, and harnesses that forbid
+ * hipMalloc.  Same arguments, kernels, results and argument errors as
+ * rr_evaluate; the only difference is where the per-parameter-vector orbit
+ * constants (144 bytes per row) live: instead of the tables' per-stream
+ * workspace, a fixed device array of RR_NOALLOC_MAX_PV rows (2.25 MiB) that
+ * the library holds on each GPU from the first rr_prepare_ld on it until
+ * the process ends.  Nothing is allocated or freed by this call.
+ * npv > RR_NOALLOC_MAX_PV returns RR_ELIMIT and enqueues nothing.
+ * Every call on one GPU uses the same array, which keeps the last call's
+ * contents (each call's setup kernel rewrites the rows it reads, so nothing
+ * needs clearing).  Calls that overlap on one GPU -- on different streams or
+ * threads, before an earlier call's kernels have finished -- race on the
+ * array and can produce wrong fluxes: issue them on one stream, or order
+ * them with events. */
+#define RR_NOALLOC_MAX_PV 16384
+RR_API int rr_evaluate_noalloc(const rr_tables* t, const double* times_d,
+                               const int32_t* lcids_d, int32_t npt,
+                               const int32_t* pbids, const int32_t* nss,
+                               const double* exptimes, int32_t nlc,
+                               const double* pv_d, int32_t npv, int32_t npar,
+                               int32_t precision, void* out_d, hipStream_t stream);
+
 /* rr_evaluate with a chosen forward-kernel variant.  The variants differ
  * only in how work maps onto the GPU, never in the arithmetic of an
  * exposure, so every variant writes the values of rr_evaluate (bit for bit

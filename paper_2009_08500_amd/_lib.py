@@ -13,6 +13,7 @@ LIB_PATH = os.path.join(_HERE, "librr.so")
 RR_OK, RR_EINVAL, RR_ENOMEM, RR_EDEVICE, RR_ELIMIT, RR_EBUSY, RR_ENOTFOUND = 0, -1, -2, -3, -4, -5, -6
 RR_FP64, RR_MIXED = 0, 1
 RR_MAX_PB, RR_MAX_LC, RR_MAX_NSS = 16, 64, 1024
+RR_NOALLOC_MAX_PV = 16384
 
 c_double_p = ctypes.POINTER(ctypes.c_double)
 c_int32_p = ctypes.POINTER(ctypes.c_int32)
@@ -67,6 +68,8 @@ def _declare(L):
     L.rr_evaluate.argtypes = [c_void_p, c_void_p, c_void_p, i32, c_void_p, c_void_p,
                               c_void_p, i32, c_void_p, i32, i32, i32, c_void_p, c_void_p]
     L.rr_evaluate.restype = ctypes.c_int
+    L.rr_evaluate_noalloc.argtypes = L.rr_evaluate.argtypes
+    L.rr_evaluate_noalloc.restype = ctypes.c_int
     L.rr_evaluate_ld.argtypes = [c_void_p, c_void_p, c_void_p, i32, c_void_p, c_void_p,
                                  c_void_p, i32, c_void_p, i32, i32, c_void_p, i32, c_void_p,
                                  c_void_p]

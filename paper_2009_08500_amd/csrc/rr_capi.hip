@@ -28,6 +28,27 @@ int hip_fail(hipError_t err, const char* what) {
     return RR_EDEVICE;
 }
 
+// Device array behind rr_evaluate_noalloc: the orbit constants of at most
+// RR_NOALLOC_MAX_PV rows, one copy per GPU for the life of the process.  In
+// host code its name is not a device address: every use goes through the
+// address hipGetSymbolAddress reports for the device (g_noalloc_scratch).
+static __device__ __align__(256) PvConst scratch[RR_NOALLOC_MAX_PV];
+constexpr int kMaxDevices = 256;
+static std::mutex g_noalloc_mu;
+static PvConst* g_noalloc_scratch[kMaxDevices] = {};
+
+// Resolve `device`'s copy of the array once; `device` must be current.
+static int noalloc_init(int device) {
+    if (device < 0 || device >= kMaxDevices) return RR_OK;   // entry point reports it
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (g_noalloc_scratch[device]) return RR_OK;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    g_noalloc_scratch[device] = static_cast<PvConst*>(ptr);
+    return RR_OK;
+}
+
 static int einval(const char* msg) {
     set_error(msg);
     return RR_EINVAL;
@@ -188,6 +209,8 @@ RR_API int rr_prepare_ld(const double* mu, const double* prof, int32_t nmu,
             hipSuccess || lds < kMinLdsBytes)
         lds = kMinLdsBytes;
     t->lds_max = size_t(lds);
+    rc = noalloc_init(t->device);
+    if (rc) { delete t; return rc; }
 
     const int64_t nz = t->nz, ng = grid->ng, nk = grid->nk;
     struct { void** p; size_t bytes; } allocs[] = {
@@ -268,6 +291,35 @@ RR_API int rr_evaluate(const rr_tables* t, const double* times_d,
     if (e != hipSuccess) return e == hipErrorOutOfMemory ? RR_ENOMEM : hip_fail(e, "workspace");
     PvConst* pvc = static_cast<PvConst*>(ws);
     e = launch_pv_setup(t, pv_d, npv, npar, pvc, stream);
+    if (e == hipSuccess)
+        e = launch_forward(t, times_d, lcids_d, npt, lc, pv_d, npv, npar, pvc,
+                           precision, out_d, stream);
+    if (e != hipSuccess) return hip_fail(e, "forward kernels");
+    return RR_OK;
+}
+
+RR_API int rr_evaluate_noalloc(const rr_tables* t, const double* times_d,
+                               const int32_t* lcids_d, int32_t npt,
+                               const int32_t* pbids, const int32_t* nss,
+                               const double* exptimes, int32_t nlc,
+                               const double* pv_d, int32_t npv, int32_t npar,
+                               int32_t precision, void* out_d, hipStream_t stream) {
+    LcInfo lc;
+    int rc = check_eval_args(t, times_d, lcids_d, npt, pbids, nss, exptimes, nlc,
+                             pv_d, npv, npar, precision, &lc);
+    if (rc) return rc;
+    if (npv > RR_NOALLOC_MAX_PV) return elimit("npv exceeds RR_NOALLOC_MAX_PV");
+    if (npt == 0 || npv == 0) return RR_OK;
+    if (!out_d) return einval("out is NULL");
+    rc = check_device(t);
+    if (rc) return rc;
+    PvConst* pvc = nullptr;
+    if (t->device >= 0 && t->device < kMaxDevices) {
+        std::lock_guard<std::mutex> lk(g_noalloc_mu);
+        pvc = g_noalloc_scratch[t->device];
+    }
+    if (!pvc) return elimit("no fixed device array on this device");
+    hipError_t e = launch_pv_setup(t, pv_d, npv, npar, pvc, stream);
     if (e == hipSuccess)
         e = launch_forward(t, times_d, lcids_d, npt, lc, pv_d, npv, npar, pvc,
                            precision, out_d, stream);
