@@ -161,6 +161,44 @@ RR_API int rr_evaluate(const rr_tables* t, const double* times_d,
                        const double* pv_d, int32_t npv, int32_t npar,
                        int32_t precision, void* out_d, hipStream_t stream);
 
+/* A registered time series (the model's data set-up of Sect. 4.1 and
+ * Sect. 4.2: mid-exposure times, light-curve ids, and per light curve the
+ * passband, supersampling factor and exposure time), kept on the device
+ * with an index that maps a time to the exposures around it, so that
+ * rr_evaluate_series can hand each transit to its own workgroups.
+ * Arguments as rr_evaluate's, but times[npt] and lcids[npt] (or NULL for
+ * one light curve) are HOST arrays; ids outside [0, nlc) are allowed and
+ * give NaN, as in rr_evaluate.  The index is used when every light curve's
+ * exposures form one contiguous run of the arrays with finite,
+ * non-decreasing times; otherwise the series is still valid and
+ * rr_evaluate_series evaluates it as rr_evaluate does.  Device memory:
+ * 12 npt bytes plus 4 per exposure of the index and 40 per light curve.
+ * Synchronous; the series lives on the current device.  npt >= 0. */
+typedef struct rr_series rr_series;   /* opaque, owned by the library */
+RR_API int rr_series_create(const double* times, const int32_t* lcids, int32_t npt,
+                            const int32_t* pbids, const int32_t* nss,
+                            const double* exptimes, int32_t nlc, rr_series** out);
+
+/* Release a series; no enqueued work may still read it.  NULL is ignored. */
+RR_API void rr_series_free(rr_series* s);
+
+/* Fluxes of npv parameter vectors over a registered series: the values of
+ * rr_evaluate on the same times, computed with the same arithmetic per
+ * exposure (the two kernels may round a multiply-add differently: within a
+ * float ulp of the flux in RR_MIXED, a double ulp in RR_FP64).  With the
+ * index, and when the problem is small enough for it to pay (npv x
+ * ceil(npt / 512) at most 2.5 times the workgroups the device holds at
+ * once), one launch sized to be resident all at once gives every parameter
+ * vector a few workgroups that evaluate only its transits -- each finds a
+ * transit's exposures through the index -- and streams F = 1 over every
+ * other exposure with the remaining workgroups; larger problems, and series
+ * without the index, take rr_evaluate's per-tile kernel.  pv_d, npv, npar,
+ * precision, out_d, stream, errors and temporary memory as rr_evaluate; the
+ * series must live on the tables' device. */
+RR_API int rr_evaluate_series(const rr_tables* t, const rr_series* s, const double* pv_d,
+                              int32_t npv, int32_t npar, int32_t precision, void* out_d,
+                              hipStream_t stream);
+
 /* rr_evaluate for callers that cannot allocate device memory: code under
  * HIP graph capture, tight serving loops, and harnesses that forbid
  * hipMalloc.  Same arguments, kernels, results and argument errors as

@@ -9,6 +9,7 @@ the library has not been built.
 from ._lib import (RR_FP64, RR_MIXED, RRError, lib)  # noqa: F401
 from .api import (DEFAULT_GRID, NUM_VARIANTS, Evaluator, RRLogLik, RRLogLikLD, Tables,  # noqa: F401
                   TimeSeries, evaluate, evaluate_direct, evaluate_ld, evaluate_small_planet,
+                  evaluate_unregistered,
                   flux_at_z, loglik_grad, loglik_grad_ld, loglik_grad_small_planet,
                   make_grid, select_variant)
 from . import ldlaws  # noqa: F401,E402

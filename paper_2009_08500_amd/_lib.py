@@ -70,6 +70,14 @@ def _declare(L):
     L.rr_evaluate.restype = ctypes.c_int
     L.rr_evaluate_noalloc.argtypes = L.rr_evaluate.argtypes
     L.rr_evaluate_noalloc.restype = ctypes.c_int
+    L.rr_series_create.argtypes = [c_void_p, c_void_p, i32, c_void_p, c_void_p, c_void_p, i32,
+                                   ctypes.POINTER(c_void_p)]
+    L.rr_series_create.restype = ctypes.c_int
+    L.rr_series_free.argtypes = [c_void_p]
+    L.rr_series_free.restype = None
+    L.rr_evaluate_series.argtypes = [c_void_p, c_void_p, c_void_p, i32, i32, i32, c_void_p,
+                                     c_void_p]
+    L.rr_evaluate_series.restype = ctypes.c_int
     L.rr_evaluate_ld.argtypes = [c_void_p, c_void_p, c_void_p, i32, c_void_p, c_void_p,
                                  c_void_p, i32, c_void_p, i32, i32, c_void_p, i32, c_void_p,
                                  c_void_p]

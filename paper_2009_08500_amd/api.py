@@ -145,10 +145,38 @@ class TimeSeries:
         self.pbids = _host(0 if pbids is None else pbids, np.int32, nlc)
         self.nss = _host(1 if nss is None else nss, np.int32, nlc)
         self.exptimes = _host(0.0 if exptimes is None else exptimes, np.float64, nlc)
+        # the registered form (rr_series_create, from host copies), which
+        # rr_evaluate_series reads
+        t_h = self.times.cpu().numpy()
+        ids_h = None if self.lcids is None else self.lcids.cpu().numpy()
+        h = ctypes.c_void_p()
+        check(_lib.lib().rr_series_create(_ptr(t_h), None if ids_h is None else _ptr(ids_h),
+                                          self.npt, _ptr(self.pbids), _ptr(self.nss),
+                                          _ptr(self.exptimes), self.nlc, ctypes.byref(h)),
+              "rr_series_create")
+        self._series = h
+
+    @property
+    def handle(self):
+        """The rr_series handle of this series."""
+        if self._series is None:
+            raise ValueError("series already freed")
+        return self._series
 
     def lc_args(self):
         lc = ctypes.c_void_p(self.lcids.data_ptr()) if self.lcids is not None else None
         return (lc, self.npt, _ptr(self.pbids), _ptr(self.nss), _ptr(self.exptimes), self.nlc)
+
+    def close(self):
+        if getattr(self, "_series", None) is not None:
+            _lib.lib().rr_series_free(self._series)
+            self._series = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 NUM_VARIANTS = 6
@@ -173,6 +201,12 @@ def evaluate(tables, series, pv, precision="fp64", out=None, stream=None, varian
         out = torch.empty((npv, series.npt), dtype=dtype, device=pv.device)
     elif out.dtype != dtype or not out.is_contiguous() or out.numel() != npv * series.npt:
         raise ValueError("out has the wrong dtype, layout or size")
+    if variant is None:
+        check(_lib.lib().rr_evaluate_series(tables.handle, series.handle,
+                                            ctypes.c_void_p(pv.data_ptr()), npv, npar, prec,
+                                            ctypes.c_void_p(out.data_ptr()), _stream(stream)),
+              "rr_evaluate_series")
+        return out
     lc, npt, pb, nss, ex, nlc = series.lc_args()
     if variant is not None:
         check(_lib.lib().rr_evaluate_variant(
@@ -180,6 +214,30 @@ def evaluate(tables, series, pv, precision="fp64", out=None, stream=None, varian
             ctypes.c_void_p(pv.data_ptr()), npv, npar, prec, int(variant),
             ctypes.c_void_p(out.data_ptr()), _stream(stream)), "rr_evaluate_variant")
         return out
+    check(_lib.lib().rr_evaluate(tables.handle, ctypes.c_void_p(series.times.data_ptr()),
+                                 lc, npt, pb, nss, ex, nlc,
+                                 ctypes.c_void_p(pv.data_ptr()), npv, npar, prec,
+                                 ctypes.c_void_p(out.data_ptr()), _stream(stream)),
+          "rr_evaluate")
+    return out
+
+
+def evaluate_unregistered(tables, series, pv, precision="fp64", out=None, stream=None):
+    """rr_evaluate on the series' raw arrays (no registered index): the same
+    values as ``evaluate``, through the per-tile kernel."""
+    prec = PRECISIONS[precision]
+    if not isinstance(series, TimeSeries):
+        series = TimeSeries(series)
+    pv = _dev(pv, torch.float64)
+    if pv.dim() == 1:
+        pv = pv.unsqueeze(0)
+    npv, npar = pv.shape
+    dtype = torch.float64 if prec == RR_FP64 else torch.float32
+    if out is None:
+        out = torch.empty((npv, series.npt), dtype=dtype, device=pv.device)
+    elif out.dtype != dtype or not out.is_contiguous() or out.numel() != npv * series.npt:
+        raise ValueError("out has the wrong dtype, layout or size")
+    lc, npt, pb, nss, ex, nlc = series.lc_args()
     check(_lib.lib().rr_evaluate(tables.handle, ctypes.c_void_p(series.times.data_ptr()),
                                  lc, npt, pb, nss, ex, nlc,
                                  ctypes.c_void_p(pv.data_ptr()), npv, npar, prec,
@@ -353,14 +411,17 @@ class Evaluator:
     def _set_variant(self, variant):
         self.variant = variant
         if variant is None:
-            self._fn = _lib.lib().rr_evaluate
-            self._args = self._base + [self.out.data_ptr(), self._stream.cuda_stream]
+            self._fn = _lib.lib().rr_evaluate_series
+            self._args = [self.tables.handle, self.series.handle, None, self.npv, self.npar,
+                          self.prec, self.out.data_ptr(), self._stream.cuda_stream]
+            self._pv_arg = 2
         else:
             if not 0 <= int(variant) < NUM_VARIANTS:
                 raise ValueError("variant must lie in [0, 6)")
             self._fn = _lib.lib().rr_evaluate_variant
             self._args = self._base + [int(variant), self.out.data_ptr(),
                                        self._stream.cuda_stream]
+            self._pv_arg = 8
 
     def select(self, pv, reps=20):
         """Trial run of every variant on rows ``pv`` (``select_variant``);
@@ -380,7 +441,7 @@ class Evaluator:
             self._auto = False
             self.select(pv)
         a = self._args
-        a[8] = pv.data_ptr()
+        a[self._pv_arg] = pv.data_ptr()
         rc = self._fn(*a)
         if rc:
             check(rc, "rr_evaluate")

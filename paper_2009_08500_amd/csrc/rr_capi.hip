@@ -101,6 +101,7 @@ static void free_tables(rr_tables* t) {
         if (b) (void)hipFree(b);
     for (auto& kv : t->ws)
         if (kv.second.first) (void)hipFree(kv.second.first);
+
     (void)hipSetDevice(cur);
     delete t;
 }
@@ -323,6 +324,160 @@ RR_API int rr_evaluate_noalloc(const rr_tables* t, const double* times_d,
     if (e == hipSuccess)
         e = launch_forward(t, times_d, lcids_d, npt, lc, pv_d, npv, npar, pvc,
                            precision, out_d, stream);
+    if (e != hipSuccess) return hip_fail(e, "forward kernels");
+    return RR_OK;
+}
+
+// ------------------------------------------------------------ time series
+static void free_series(rr_series* se) {
+    if (!se) return;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    if (se->device >= 0) (void)hipSetDevice(se->device);
+    void* bufs[] = {se->times, se->lcids, se->lcs, se->buckets};
+    for (void* b : bufs)
+        if (b) (void)hipFree(b);
+    (void)hipSetDevice(cur);
+    delete se;
+}
+
+RR_API int rr_series_create(const double* times, const int32_t* lcids, int32_t npt,
+                            const int32_t* pbids, const int32_t* nss,
+                            const double* exptimes, int32_t nlc, rr_series** out) {
+    if (!out) return einval("out is NULL");
+    *out = nullptr;
+    if (npt < 0) return einval("npt must be >= 0");
+    if (npt > 0 && !times) return einval("times is NULL");
+    if (nlc < 1) return einval("nlc must be >= 1");
+    if (nlc > RR_MAX_LC) return elimit("nlc exceeds RR_MAX_LC");
+    if (!lcids && nlc != 1) return einval("lcids may be NULL only when nlc == 1");
+    if (!pbids || !nss || !exptimes) return einval("pbids, nss and exptimes are required");
+    for (int i = 0; i < nlc; ++i) {
+        if (pbids[i] < 0 || pbids[i] >= RR_MAX_PB) return einval("pbids entry outside [0, RR_MAX_PB)");
+        if (nss[i] < 1) return einval("nss entries must be >= 1");
+        if (nss[i] > RR_MAX_NSS) return elimit("nss entry exceeds RR_MAX_NSS");
+        if (!(exptimes[i] >= 0.0) || !isfinite(exptimes[i]))
+            return einval("exptimes entries must be finite and >= 0");
+    }
+    rr_series* se = new (std::nothrow) rr_series();
+    if (!se) return RR_ENOMEM;
+    se->npt = npt;
+    se->nlc = nlc;
+    se->pbids.assign(pbids, pbids + nlc);
+    se->nss.assign(nss, nss + nlc);
+    se->exptimes.assign(exptimes, exptimes + nlc);
+    se->lc.nlc = nlc;
+    for (int i = 0; i < RR_MAX_LC; ++i) {
+        se->lc.pb[i] = i < nlc ? pbids[i] : 0;
+        se->lc.nss[i] = i < nlc ? nss[i] : 1;
+        se->lc.exptime[i] = i < nlc ? exptimes[i] : 0.0;
+        if (i < nlc) se->max_nss = std::max(se->max_nss, nss[i]);
+    }
+    // Each light curve one contiguous run of finite, non-decreasing times?
+    std::vector<SeriesLc> lcs(size_t(nlc), SeriesLc{0, 0, 0, 0, 0.0, 0.0, 0.0});
+    std::vector<char> seen(size_t(nlc), 0);
+    bool indexed = true, all_zero = true;
+    for (int32_t i = 0; i < npt && indexed; ++i) {
+        const int32_t l = lcids ? lcids[i] : 0;
+        if (l < 0 || l >= nlc || !isfinite(times[i])) { indexed = false; break; }
+        all_zero = all_zero && l == 0;
+        if (i == 0 || l != (lcids ? lcids[i - 1] : 0)) {
+            if (seen[l]) { indexed = false; break; }     // a second run of l
+            seen[l] = 1;
+            lcs[l].start = i;
+        } else if (!(times[i] >= times[i - 1])) {
+            indexed = false;
+        }
+        lcs[l].end = i + 1;
+    }
+    if (!lcids) all_zero = true;
+    // the index: per light curve nb + 1 entries (nb = its exposure count)
+    std::vector<int32_t> buckets;
+    if (indexed) {
+        for (int l = 0; l < nlc; ++l) {
+            SeriesLc& sl = lcs[l];
+            const int32_t n = sl.end - sl.start;
+            sl.boff = int32_t(buckets.size());
+            if (n <= 0) {
+                sl.start = sl.end = 0;
+                sl.nb = 0;
+                buckets.push_back(0);
+                continue;
+            }
+            sl.t_first = times[sl.start];
+            sl.t_last = times[sl.end - 1];
+            if (!(sl.t_last > sl.t_first)) {
+                sl.nb = 1;
+                sl.inv_bw = 0.0;
+                buckets.push_back(sl.start);
+                buckets.push_back(sl.end);
+                continue;
+            }
+            sl.nb = n;
+            const double bw = (sl.t_last - sl.t_first) / n;
+            sl.inv_bw = 1.0 / bw;
+            int32_t i = sl.start;
+            for (int32_t b = 0; b < n; ++b) {
+                const double edge = sl.t_first + b * bw;
+                while (i < sl.end && times[i] < edge) ++i;
+                buckets.push_back(i);
+            }
+            buckets.push_back(sl.end);
+        }
+    }
+    se->indexed = indexed;
+    hipError_t e = hipGetDevice(&se->device);
+    if (e != hipSuccess) { delete se; return hip_fail(e, "hipGetDevice"); }
+    // lcids are kept unless one light curve covers every exposure
+    const bool keep_ids = lcids && !(nlc == 1 && all_zero && indexed);
+    struct { void** p; const void* src; size_t bytes; } up[] = {
+        {(void**)&se->times, times, sizeof(double) * size_t(npt)},
+        {(void**)&se->lcids, keep_ids ? lcids : nullptr, keep_ids ? sizeof(int32_t) * size_t(npt) : 0},
+        {(void**)&se->lcs, indexed ? lcs.data() : nullptr, indexed ? sizeof(SeriesLc) * lcs.size() : 0},
+        {(void**)&se->buckets, indexed ? buckets.data() : nullptr,
+         indexed ? sizeof(int32_t) * buckets.size() : 0},
+    };
+    for (auto& u : up) {
+        if (!u.src || u.bytes == 0) continue;
+        e = hipMalloc(u.p, u.bytes);
+        if (e == hipSuccess) e = hipMemcpy(*u.p, u.src, u.bytes, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            free_series(se);
+            set_error(std::string("series upload: ") + hipGetErrorString(e));
+            return e == hipErrorOutOfMemory ? RR_ENOMEM : RR_EDEVICE;
+        }
+    }
+    *out = se;
+    return RR_OK;
+}
+
+RR_API void rr_series_free(rr_series* s) { free_series(s); }
+
+RR_API int rr_evaluate_series(const rr_tables* t, const rr_series* se, const double* pv_d,
+                              int32_t npv, int32_t npar, int32_t precision, void* out_d,
+                              hipStream_t stream) {
+    if (!se) return einval("series is NULL");
+    LcInfo lc;
+    int rc = check_eval_args(t, se->times, se->lcids, se->npt, se->pbids.data(),
+                             se->nss.data(), se->exptimes.data(), se->nlc, pv_d, npv, npar,
+                             precision, &lc);
+    if (rc) return rc;
+    if (se->npt == 0 || npv == 0) return RR_OK;
+    if (!out_d) return einval("out is NULL");
+    rc = check_device(t);
+    if (rc) return rc;
+    if (se->device != t->device) return einval("series and tables live on different devices");
+    void* ws = nullptr;
+    hipError_t e = stream_workspace(const_cast<rr_tables*>(t), stream,
+                                    sizeof(PvConst) * size_t(npv), &ws);
+    if (e != hipSuccess) return e == hipErrorOutOfMemory ? RR_ENOMEM : hip_fail(e, "workspace");
+    PvConst* pvc = static_cast<PvConst*>(ws);
+    e = launch_pv_setup(t, pv_d, npv, npar, pvc, stream);
+    if (e == hipSuccess)
+        e = se->indexed && split_preferred(t, se, npv, precision)
+                ? launch_forward_split(t, se, pv_d, npv, npar, pvc, precision, out_d, stream)
+                : launch_forward(t, se->times, se->lcids, se->npt, lc, pv_d, npv, npar, pvc,
+                                 precision, out_d, stream);
     if (e != hipSuccess) return hip_fail(e, "forward kernels");
     return RR_OK;
 }

@@ -11,6 +11,7 @@
 #include <mutex>
 #include <string>
 #include <unordered_map>
+#include <vector>
 
 #include "rr.h"
 
@@ -102,6 +103,26 @@ struct SetupTable {
     SetupJob j[kMaxJobs];
 };
 
+// One light curve of a registered series whose exposures are the contiguous
+// run [start, end) of the arrays with non-decreasing times t_first ..
+// t_last.  Its index (nb + 1 entries at boff of the series' bucket array):
+// entry b < nb is the first exposure with t >= t_first + b * bw
+// (bw = (t_last - t_first)/nb, inv_bw = 1/bw, or 0 when all times are
+// equal), entry nb is end.
+struct SeriesLc {
+    int32_t start, end, boff, nb;
+    double t_first, t_last, inv_bw;
+};
+// What the split forward launch (rr_evaluate_series) needs beyond a FwdJob:
+// the light curves' runs and index, and `shares` transit workgroups per
+// parameter vector (the first npv * shares workgroups of the launch).
+struct SplitInfo {
+    const SeriesLc* lcs;       // [nlc], device
+    const int32_t* buckets;    // device
+    int32_t shares;
+    int32_t rows_per;          // rows per streaming workgroup
+};
+
 // Scalars of the table grid needed on the device.
 struct GridDev {
     int32_t nz, ng, nk, npb;
@@ -142,6 +163,20 @@ struct AdjointArgs {
 }  // namespace rr
 
 // Library-owned table handle (opaque in the ABI).
+// A registered time series (rr_series_create).
+struct rr_series {
+    int device = -1;
+    int32_t npt = 0, nlc = 0, max_nss = 1;
+    rr::LcInfo lc;
+    std::vector<int32_t> pbids, nss;   // host copies, [nlc]
+    std::vector<double> exptimes;
+    bool indexed = false;          // every light curve one sorted run: split launch
+    double* times = nullptr;       // [npt] device
+    int32_t* lcids = nullptr;      // [npt] device, or null for one light curve
+    rr::SeriesLc* lcs = nullptr;   // [nlc] device (indexed only)
+    int32_t* buckets = nullptr;    // device (indexed only)
+};
+
 struct rr_tables {
     rr_grid grid;
     int32_t nz, npb, nmu;
@@ -164,6 +199,7 @@ struct rr_tables {
     // ordered, so a stream's buffer is reused without waiting).
     std::mutex ws_mu;
     std::unordered_map<hipStream_t, std::pair<void*, size_t>> ws;
+
 };
 
 namespace rr {
@@ -230,6 +266,15 @@ hipError_t launch_pv_prof_grad(const rr_tables* t, const AdjointArgs& A, const i
 hipError_t launch_profile_grad(const rr_tables* t, const AdjointArgs& a,
                                const ProfGradScratch& w, double* out, hipStream_t s);
 hipError_t launch_fill(double* p, int64_t n, hipStream_t s);
+// Whether rr_evaluate_series takes the split launch for this size: when the
+// per-tile kernel's workgroups (npv x tiles of 512 times) number at most
+// 2.5 x the split kernel's resident workgroups (measured crossover, both
+// precisions); beyond that the per-tile kernel is faster.
+bool split_preferred(const rr_tables* t, const rr_series* se, int32_t npv, int32_t precision);
+// Split launch over a registered, indexed series (rr_evaluate_series).
+hipError_t launch_forward_split(const rr_tables* t, const rr_series* se, const double* pv,
+                                int32_t npv, int32_t npar, const PvConst* pvc,
+                                int32_t precision, void* out, hipStream_t s);
 hipError_t launch_forward_jobs(const rr_tables* t, const JobTable& jt,
                                int32_t nblocks_total, int32_t precision, hipStream_t s);
 hipError_t launch_pv_setup_jobs(const rr_tables* t, const SetupTable& st,

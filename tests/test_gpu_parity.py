@@ -175,8 +175,11 @@ def test_more_rows_than_one_grid_dimension(rr):
     assert (ref < 1.0).sum() > 500
     f64, f32 = both(rr, tab, ser, pv)
     check_parity(ref, f64, f32)
+    # the 70 000-row call takes the per-tile kernel: bitwise equal to it on
+    # the 100 rows; the 100-row call may take the split launch (one rounding)
     last64 = rr.evaluate(tab, ser, big, "fp64").cpu().numpy()[-100:]
-    assert np.array_equal(last64, f64)
+    assert np.array_equal(last64, rr.evaluate_unregistered(tab, ser, pv, "fp64").cpu().numpy())
+    assert np.abs(last64 - f64).max() <= 1e-15
 
 
 def test_population_bjd_offset(rr):

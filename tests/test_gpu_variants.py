@@ -31,11 +31,16 @@ def test_variants_equal_evaluate(rr, npt):
     pv = w["pv"].copy()
     pv[3, 6] = 0.5                                    # an invalid row (k > k1)
     for prec in ("fp64", "mixed"):
-        ref = rr.evaluate(tab, ser, pv, prec).cpu().numpy()
+        ref = rr.evaluate_unregistered(tab, ser, pv, prec).cpu().numpy()
         assert np.isnan(ref[3]).all() and (ref < 1.0).any()
         for v in range(rr.NUM_VARIANTS):
             out = rr.evaluate(tab, ser, pv, prec, variant=v).cpu().numpy()
             assert np.array_equal(out, ref, equal_nan=True), (prec, v)
+        # the registered-series launch: the same exposures at one rounding
+        reg = rr.evaluate(tab, ser, pv, prec).cpu().numpy()
+        assert np.array_equal(np.isnan(reg), np.isnan(ref))
+        assert np.nanmax(np.abs(reg.astype(np.float64) - ref)) <= (2e-7 if prec == "mixed"
+                                                                      else 1e-15)
 
 
 def test_supersampled_variants(rr):
@@ -54,8 +59,8 @@ def test_supersampled_variants(rr):
     ser = rr.TimeSeries(w["times"], w["lcids"], w["pbids"], w["nss"], w["exptimes"])
     oref = orr.evaluate(otab, w["times"], w["pv"], **kw)
     assert (oref < 1.0).any()
-    ref64 = rr.evaluate(tab, ser, w["pv"], "fp64").cpu().numpy()
-    ref32 = rr.evaluate(tab, ser, w["pv"], "mixed").cpu().numpy().astype(np.float64)
+    ref64 = rr.evaluate_unregistered(tab, ser, w["pv"], "fp64").cpu().numpy()
+    ref32 = rr.evaluate_unregistered(tab, ser, w["pv"], "mixed").cpu().numpy().astype(np.float64)
     for v in range(rr.NUM_VARIANTS):
         o64 = rr.evaluate(tab, ser, w["pv"], "fp64", variant=v).cpu().numpy()
         o32 = rr.evaluate(tab, ser, w["pv"], "mixed", variant=v).cpu().numpy().astype(np.float64)
@@ -78,7 +83,9 @@ def test_select_variant_and_evaluator(rr):
     assert all(m > 0.0 for m in ms) and ms[3:] == ms[:3]
     assert ms[best] == min(ms)
     ev = rr.Evaluator(tab, ser, 64, "mixed")
-    ref = ev(pv).clone()
+    reg = ev(pv).clone()                      # the registered-series launch
+    ref = rr.evaluate_unregistered(tab, ser, pv, "mixed")
+    assert (reg.double() - ref.double()).abs().max().item() <= 2e-7
     b2, _ = ev.select(pv, reps=3)
     assert ev.variant == b2
     assert torch.equal(ev(pv), ref)
