@@ -39,9 +39,13 @@ def parse():
                     help="budget of the CPU-oracle baseline leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--serving-requests", type=int, default=240)
+    ap.add_argument("--serving-requests", type=int, default=2000)
+    ap.add_argument("--serving-burst", type=int, default=300)
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the heterogeneous-series and log-likelihood legs")
+    ap.add_argument("--legs", default="heterogeneous,per_vector_ld,direct,small_planet,"
+                                      "variants,loglik",
+                    help="comma-separated extra legs to run (unless --no-extra)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy --steps times "
                          "(the reference kernel for scaling HBM byte counters)")
@@ -133,10 +137,40 @@ def pct(x, q):
     return float(np.percentile(np.asarray(x), q))
 
 
+_POOL_STATE = {}
+
+
+def _pool_rows(args):
+    """Worker of the N-core oracle leg: the oracle on one chunk of rows,
+    single-threaded (the tables come with the forked process)."""
+    from threadpoolctl import threadpool_limits
+    from oracle import roadrunner as orr
+    r0, r1 = args
+    st = _POOL_STATE
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        orr.evaluate(st["otab"], st["times"], st["pv"][r0:r1])
+        return r1 - r0, time.perf_counter() - t0
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(w, grid, budget_s, gpu_out64, gpu_out32):
     """The FP64 oracle, untuned, on the host: whole population passes over
-    parameter-row chunks until the time budget is used.  Tables are built
+    parameter-row chunks until the time budget is used, first on one core,
+    then on N cores (a pool of N forked worker processes over row chunks,
+    N = the host cores given to this GPU, at most 16).  Tables are built
     outside the timed region, as on the GPU side."""
+    import multiprocessing as mp
     import numpy as np
     from threadpoolctl import threadpool_limits
     from oracle import roadrunner as orr
@@ -158,10 +192,27 @@ def cpu_baseline(w, grid, budget_s, gpu_out64, gpu_out32):
                 err64 = max(err64, float(np.abs(gpu_out64[rows] - ref).max()))
                 err32 = max(err32, float(np.abs(gpu_out32[rows] - ref).max()))
     pts = done_rows * w["times"].size
-    sample = (f"{done_rows} parameter rows of the same population (chunks of {chunk}, "
-              f"cycling through all {npv}) x {w['times'].size} times, "
-              f"{t_used:.1f} s of single-thread NumPy FP64")
-    return dict(value=pts / t_used, unit="points/s", cores=1, kind="oracle", sample=sample), \
+    single = dict(value=pts / t_used, unit="points/s", cores=1,
+                  sample=f"{done_rows} rows x {w['times'].size} times, {t_used:.1f} s")
+    # N cores: fork (no exec) after the tables are built; workers use no GPU
+    ncores = max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity")
+                        else (os.cpu_count() or 1)))
+    _POOL_STATE.update(otab=otab, times=w["times"], pv=w["pv"])
+    jobs = [(r0, min(npv, r0 + 8)) for r0 in range(0, npv, 8)]
+    ctx = mp.get_context("fork")
+    rows_done, t_wall = 0, 0.0
+    with ctx.Pool(ncores) as pool:
+        while t_wall < budget_s:
+            t0 = time.perf_counter()
+            for n, _ in pool.imap_unordered(_pool_rows, jobs):
+                rows_done += n
+            t_wall += time.perf_counter() - t0
+    pts_n = rows_done * w["times"].size
+    sample = (f"{rows_done} parameter rows of the same population (chunks of 8 rows over "
+              f"{ncores} forked single-threaded workers, whole passes over all {npv} rows) x "
+              f"{w['times'].size} times, {t_wall:.1f} s wall; one core: {single['sample']}")
+    return dict(value=pts_n / t_wall, unit="points/s", cores=ncores, kind="oracle",
+                sample=sample, cpu_model=cpu_model(), single_core=single), \
         dict(rows_checked=min(done_rows, npv), max_abs_err_fp64=err64,
              max_abs_err_mixed_ppm=err32 * 1e6)
 
@@ -476,68 +527,199 @@ def loglik_leg(rr, wl, steps, warmup):
     return res
 
 
-def serving_leg(rr, wl, nreq):
-    """Serving: a Poisson stream of population requests against resident
-    tables (the four heterogeneous-workload passbands) and 12 resident time
-    series (npt ~ logU(1e3, 1e5), nss in {1, 5, 10}, 1-4 passbands), each
-    request with npv ~ logU(1, 2048) rows, mixed precision, outputs copied to
-    page-locked host memory.  First a burst of a quarter of the requests
-    measures the saturated rate; the rest arrive at 0.7 x that rate and give
-    the latency percentiles (submission to output in host memory)."""
+class _Ring:
+    """First-in, first-out allocator over one preallocated byte buffer (page-
+    locked host or device memory), so that the serving protocol allocates
+    nothing per request: requests take their outputs from it in submission
+    order and give them back in the same order once done."""
+
+    def __init__(self, nbytes, device):
+        import threading
+        import torch
+        self.size = int(nbytes)
+        self.buf = (torch.empty(self.size, dtype=torch.uint8, device="cuda") if device
+                    else torch.empty(self.size, dtype=torch.uint8, pin_memory=True))
+        self.live = []            # (start, end) in allocation order
+        self.head = 0
+        self.lock = threading.Lock()
+
+    def alloc(self, nbytes):
+        n = (int(nbytes) + 255) // 256 * 256
+        with self.lock:
+            if not self.live:
+                self.head = 0
+            tail = self.live[0][0] if self.live else 0
+            if not self.live or self.head > tail:
+                if self.head + n <= self.size:
+                    start = self.head
+                elif n <= tail:
+                    start = 0
+                else:
+                    return None
+            else:
+                if self.head + n <= tail:
+                    start = self.head
+                else:
+                    return None
+            self.live.append((start, start + n))
+            self.head = start + n
+            return start
+
+    def free_oldest(self):
+        with self.lock:
+            self.live.pop(0)
+
+    def view(self, start, npv, npt, dtype):
+        import torch
+        nb = npv * npt * (8 if dtype is torch.float64 else 4)
+        return self.buf[start:start + nb].view(dtype).view(npv, npt)
+
+
+def serving_leg(rr, wl, nreq, nburst):
+    """Serving protocol: requests each with their own resident time series
+    (npt ~ logU(1e3, 1e5), nss in {1, 5, 10}, 1-4 passbands split evenly
+    into 2-min light curves) and npv ~ logU(1, 2048) rows, against resident
+    tables of four passbands.  For each precision and output mode (device
+    buffer; page-locked host buffer) a burst of `nburst` requests submitted
+    at once gives the saturated request rate, then the same `nreq` requests
+    arrive as a Poisson stream at 0.5 and at 0.9 times that rate.  Outputs
+    come from preallocated ring buffers, so nothing is allocated per
+    request.  Latency is the server's (submission to the kernels that wrote
+    the output having completed, or to the output being in host memory);
+    `submit_lag` is how late the submitting thread was against the drawn
+    arrival times."""
+    import queue
+    import threading
     import numpy as np
+    import torch
     het = wl.heterogeneous(npv=1)
     tab = rr.Tables(het["mu_s"], het["I_s"], wl.DEFAULT_GRID)
-    series, reqs = wl.serving_mix(nreq)
+    series, reqs = wl.serving_stream(nreq)
     srv = rr.Server(tab, budget_bytes=16 << 30, max_tick_blocks=32768)
+    t_reg = time.perf_counter()
     sids = [srv.add_series(se["times"], se["lcids"], se["pbids"], se["nss"], se["exptimes"])
             for se in series]
+    t_reg = time.perf_counter() - t_reg
     nsub = [int(np.sum(se["nss"][se["lcids"]])) for se in series]
-    work = [r["pv"].shape[0] * nsub[r["series"]] for r in reqs]
-    nburst = max(4, nreq // 4)
-    # burst: saturated throughput
-    t0 = time.perf_counter()
-    hs = [srv.submit(sids[r["series"]], r["pv"], "mixed") for r in reqs[:nburst]]
-    for h in hs:
-        srv.wait(h)
-    t_burst = time.perf_counter() - t0
-    sat_rps = nburst / t_burst
-    del hs
-    # Poisson stream at 0.7 x the saturated rate
-    rate = 0.7 * sat_rps
-    rng = np.random.default_rng(2009085004)
-    gaps = rng.exponential(1.0 / rate, nreq - nburst)
-    stream = reqs[nburst:]
-    handles = []
+    npts = [int(se["times"].size) for se in series]
+    work = np.array([r["pv"].shape[0] * nsub[r["series"]] for r in reqs], dtype=np.float64)
+    rings = {True: _Ring(8 << 30, True), False: _Ring(8 << 30, False)}
+    res = dict(
+        workload="Poisson streams of requests, each with its own series: npv~logU(1,2048), "
+                 "npt~logU(1e3,1e5), nss in {1,5,10}, 1-4 passbands; resident tables and series",
+        requests_per_stream=nreq, burst_requests=nburst, series_registered=len(series),
+        series_registration_s=t_reg, mean_points_per_request=float(np.mean(work)),
+        max_points_per_request=float(np.max(work)))
 
-    t1 = time.perf_counter()
-    next_t = t1
-    for r, gap in zip(stream, gaps):
-        next_t += gap
-        d = next_t - time.perf_counter()
-        if d > 0:
-            time.sleep(d)
-        handles.append(srv.submit(sids[r["series"]], r["pv"], "mixed"))
-    lat = []
-    for h in handles:
-        srv.wait(h)
-        lat.append(h.latency)
-        h.out = None
-    t_stream = time.perf_counter() - t1
+    def run(prec, device, idx, gaps):
+        """Submit requests `idx` (after the given gaps, or all at once) and
+        wait for them in order on a second thread.  Returns (elapsed s,
+        latencies s, submit lags s, ring stalls)."""
+        dtype = torch.float64 if prec == "fp64" else torch.float32
+        ring = rings[device]
+        q = queue.Queue()
+        lat = []
+
+        def waiter():
+            while True:
+                h = q.get()
+                if h is None:
+                    return
+                srv.wait(h, timeout=300.0)
+                lat.append(h.latency)
+                srv.release(h)
+                h.out = None
+                ring.free_oldest()
+
+        th = threading.Thread(target=waiter)
+        th.start()
+        lags, stalls = [], 0
+        t0 = time.perf_counter()
+        due = t0
+        for k, i in enumerate(idx):
+            r = reqs[i]
+            npv, npt = r["pv"].shape[0], npts[r["series"]]
+            if gaps is not None:
+                due += gaps[k]
+                d = due - time.perf_counter()
+                if d > 0:
+                    time.sleep(d)
+            while True:
+                off = ring.alloc(npv * npt * (8 if prec == "fp64" else 4))
+                if off is not None:
+                    break
+                stalls += 1
+                time.sleep(50e-6)
+            out = ring.view(off, npv, npt, dtype)
+            if gaps is not None:
+                lags.append(time.perf_counter() - due)
+            q.put(srv.submit(sids[r["series"]], r["pv"], prec, device_out=device, out=out))
+        q.put(None)
+        th.join()
+        return time.perf_counter() - t0, lat, lags, stalls
+
+    rng = np.random.default_rng(2009085004)
+    unit = rng.exponential(1.0, nreq)                  # the same arrival pattern, scaled
+    for prec in ("mixed", "fp64"):
+        for device in (True, False):
+            key = f"{prec}_{'device' if device else 'host'}_output"
+            run(prec, device, range(min(nburst, 64)), None)        # untimed warm-up
+            el, _, _, _ = run(prec, device, range(nburst), None)
+            sat = nburst / el
+            entry = dict(saturated_requests_per_s=sat,
+                         saturated_points_per_s=float(np.sum(work[:nburst])) / el)
+            for frac in (0.5, 0.9):
+                rate = frac * sat
+                el, lat, lags, stalls = run(prec, device, range(nreq), unit / rate)
+                entry[f"rate_{frac}"] = dict(
+                    arrival_rate_per_s=rate, points_per_s=float(np.sum(work[:nreq])) / el,
+                    latency_ms=dict(p50=1e3 * float(np.percentile(lat, 50)),
+                                    p99=1e3 * float(np.percentile(lat, 99)),
+                                    max=1e3 * float(np.max(lat))),
+                    submit_lag_ms_p99=1e3 * float(np.percentile(lags, 99)),
+                    ring_stalls=stalls)
+            res[key] = entry
+            print(f"serving {key}: " + json.dumps(entry), file=sys.stderr, flush=True)
     st = srv.stats()
+    res["grouped_launches"] = st["ticks"]
+    res["device_errors"] = st["last_error"]
     srv.close()
     tab.close()
-    pts_stream = float(np.sum(work[nburst:]))
-    return dict(
-        workload="Poisson stream, npv~logU(1,2048), npt~logU(1e3,1e5), nss in {1,5,10}, "
-                 "1-4 passbands, mixed precision, outputs to pinned host memory",
-        requests=nreq, burst_requests=nburst, saturated_requests_per_s=sat_rps,
-        saturated_points_per_s=float(np.sum(work[:nburst])) / t_burst,
-        arrival_rate_per_s=rate, stream_points_per_s=pts_stream / t_stream,
-        latency_ms=dict(p50=1e3 * float(np.percentile(lat, 50)),
-                        p99=1e3 * float(np.percentile(lat, 99)),
-                        max=1e3 * float(np.max(lat))),
-        mean_points_per_request=float(np.mean(work)), grouped_launches=st["ticks"],
-        device_errors=st["last_error"])
+    return res
+
+
+def single_lc_leg(rr, wl, steps, warmup):
+    """One light curve, the smallest call (npv 1, 1000 times, circular orbit,
+    quadratic LD at 100 mu, no supersampling): microseconds per call, as
+    throughput of back-to-back calls and as per-call latency percentiles
+    (HIP events around each call); latency-bound, not a throughput figure."""
+    import numpy as np
+    import torch
+    w = wl.single_light_curve()
+    tab = rr.Tables(w["mu_s"], w["I_s"], wl.DEFAULT_GRID)
+    ser = rr.TimeSeries(w["times"])
+    pv = torch.as_tensor(w["pv"], device="cuda")
+    res = dict(workload="single light curve: npv 1, npt 1000, circular, quadratic LD, nss 1")
+    for prec in ("fp64", "mixed"):
+        ev = rr.Evaluator(tab, ser, 1, prec)
+        for _ in range(warmup):
+            ev(pv)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ev(pv)
+        torch.cuda.synchronize()
+        us = 1e6 * (time.perf_counter() - t0) / steps
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(steps)]
+        for a, b in evs:
+            a.record()
+            ev(pv)
+            b.record()
+        torch.cuda.synchronize()
+        lat = [1e3 * a.elapsed_time(b) for a, b in evs]
+        res[prec] = dict(us_per_call=us, latency_us=dict(p50=pct(lat, 50), p99=pct(lat, 99)))
+    return res
 
 
 def main():
@@ -628,13 +810,21 @@ def main():
     o64 = out64.cpu().numpy()
     line["in_transit_fraction"] = float(np.mean(o64 < 1.0))
     if not args.no_serving:
-        line["serving"] = serving_leg(rr, wl, args.serving_requests)
-    if not args.no_extra:
+        line["serving"] = serving_leg(rr, wl, args.serving_requests, args.serving_burst)
+    if not args.no_serving:
+        line["single_light_curve"] = single_lc_leg(rr, wl, min(args.steps, 200), 20)
+    legs = set() if args.no_extra else set(args.legs.split(","))
+    if "heterogeneous" in legs:
         line["heterogeneous"] = heterogeneous_leg(rr, wl, min(args.steps, 50), 5, lib)
+    if "per_vector_ld" in legs:
         line["per_vector_ld"] = per_vector_ld_leg(rr, wl, min(args.steps, 50), 5, lib)
+    if "direct" in legs:
         line["direct_model"] = direct_leg(rr, wl, min(args.steps, 20), 2)
+    if "small_planet" in legs:
         line["small_planet"] = small_planet_leg(rr, wl, min(args.steps, 20), 2)
+    if "variants" in legs:
         line["variant_selection"] = variant_leg(rr, wl)
+    if "loglik" in legs:
         line["loglik_grad"] = loglik_leg(rr, wl, 10, 2)
     if not args.no_cpu_baseline:
         cb, acc = cpu_baseline(w, grid, args.cpu_seconds, o64, o32)

@@ -79,10 +79,11 @@ class Server:
 
     def submit(self, series_id, pv, precision="mixed", device_out=False, out=None):
         """Queue rows ``pv`` against a registered series.  The output goes to
-        page-locked host memory (rr_server_submit), or with ``device_out``
-        to a device tensor (``out``, or a new one) that the kernels write
-        directly (rr_server_submit_device); read it only once the request is
-        done."""
+        host memory (rr_server_submit: ``out``, page-locked for an
+        asynchronous copy, or a new page-locked tensor), or with
+        ``device_out`` to a device tensor (``out``, or a new one) that the
+        kernels write directly (rr_server_submit_device); read it only once
+        the request is done."""
         prec = PRECISIONS[precision]
         pv = np.ascontiguousarray(np.atleast_2d(np.asarray(pv, np.float64)))
         npv, npar = pv.shape
@@ -100,7 +101,11 @@ class Server:
                                                  ctypes.byref(rid)),
                   "rr_server_submit_device")
         else:
-            out = torch.empty((npv, npt), dtype=dtype, pin_memory=True)
+            if out is None:
+                out = torch.empty((npv, npt), dtype=dtype, pin_memory=True)
+            elif (out.is_cuda or out.dtype != dtype or not out.is_contiguous()
+                  or out.numel() != npv * npt):
+                raise ValueError("out must be a contiguous host tensor of npv x npt")
             check(self.L.rr_server_submit(self._h, series_id, _ptr(pv), npv, npar, prec,
                                           ctypes.c_void_p(out.data_ptr()), ctypes.byref(rid)),
                   "rr_server_submit")

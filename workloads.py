@@ -198,6 +198,31 @@ def serving_mix(nreq, nseries=12, seed_extra=0, max_npv=2048, max_npt=100000,
     return series, reqs
 
 
+def serving_stream(nreq, seed_extra=0, max_npv=2048, max_npt=100000, min_npt=1000):
+    """Request stream for the serving protocol: every request has its own
+    time series, with npt ~ logU(min_npt, max_npt), nss in {1, 5, 10} and
+    npb in {1..4} (the resident passbands 0..npb-1), its times split evenly
+    into one 2-min-cadence light curve per passband with exptime = cadence,
+    and npv ~ logU(1, max_npv) parameter rows drawn as in ``population``
+    (chromatic k within 5 %).  Returns (series, requests) with request i on
+    series i."""
+    rng = rng_for(8, seed_extra)
+    series, reqs = [], []
+    for i in range(nreq):
+        npt = int(np.exp(rng.uniform(np.log(min_npt), np.log(max_npt))))
+        nss = int(rng.choice([1, 5, 10]))
+        npb = int(rng.integers(1, 5))
+        per = max(1, npt // npb)
+        times = np.concatenate([np.arange(per) * (2.0 * MINUTE) for _ in range(npb)])
+        lcids = np.repeat(np.arange(npb), per).astype(np.int32)
+        series.append(dict(times=times, lcids=lcids, pbids=np.arange(npb, dtype=np.int32),
+                           nss=np.full(npb, nss, np.int32),
+                           exptimes=np.full(npb, 2.0 * MINUTE), npb=npb))
+        npv = int(np.exp(rng.uniform(0.0, np.log(max_npv))))
+        reqs.append(dict(series=i, pv=draw_orbits(rng, npv, npb=4, chromatic=0.05)))
+    return series, reqs
+
+
 def loglik_walkers(npv=1024, npt=50000, nss=5, seed_extra=0):
     """Walkers around a truth vector for the log-likelihood workload:
     the truth is drawn as in ``population``; walkers are the truth plus
