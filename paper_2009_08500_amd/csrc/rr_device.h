@@ -4,30 +4,45 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "rr_internal.h"
 
 namespace rr {
 
-template <typename R> struct Num;
+// The hardware primitives the device math is built on: the GPU's
+// reciprocal and square-root estimates.  The functions below are written
+// once against this interface (a template parameter defaulting to it), so
+// that a host build for tests can instantiate the same code with host
+// stand-ins of these three operations.
+struct HwOps {
+    __device__ static float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+    __device__ static float sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+    __device__ static double rcp(double x) { return __builtin_amdgcn_rcp(x); }
+};
+
+template <typename R, class Ops = HwOps> struct Num;
 // atan2 for float on the kernels' paths: r = min(|x|,|y|)/max(|x|,|y|) in
 // [0, 1], atan r = r P(r^2) with P of degree 7 (a least-squares fit to
-// atan(r)/r at Chebyshev nodes in r^2, weighted for relative error: max
-// relative error 1.1e-7 in exact arithmetic, 2.4e-7 evaluated in float),
-// then the octant fix-ups.  About 20 instructions, half those of a
-// correctly rounded atan2f; the lens areas need ~1e-6 relative.
-__device__ inline float atan2_poly(float y, float x) {
+// atan(r)/r at 64 Chebyshev nodes in r^2, weighted for relative error;
+// fit_atan_poly.py beside this file derives it: max relative error 1.14e-7
+// in exact arithmetic), then the octant fix-ups.  About 20 instructions,
+// half those of a correctly rounded atan2f; the lens areas need ~1e-6
+// relative.
+template <class Ops = HwOps>
+__host__ __device__ inline float atan2_poly(float y, float x) {
     const float ax = fabsf(x), ay = fabsf(y);
     const float mx = fmaxf(ax, ay), mn = fminf(ax, ay);
-    const float r = mx > 0.0f ? mn * __builtin_amdgcn_rcpf(mx) : 0.0f;
+    const float r = mx > 0.0f ? mn * Ops::rcp(mx) : 0.0f;
     const float t = r * r;
-    float p = -4.583734553e-03f;
-    p = p * t + 2.386576869e-02f;
-    p = p * t - 5.894939974e-02f;
-    p = p * t + 9.877229482e-02f;
-    p = p * t - 1.400631070e-01f;
-    p = p * t + 1.996748596e-01f;
-    p = p * t - 3.333184719e-01f;
-    p = p * t + 9.999998808e-01f;
+    float p = -4.583679842e-03f;
+    p = p * t + 2.386548698e-02f;
+    p = p * t - 5.894885931e-02f;
+    p = p * t + 9.877179037e-02f;
+    p = p * t - 1.400628610e-01f;
+    p = p * t + 1.996748018e-01f;
+    p = p * t - 3.333184671e-01f;
+    p = p * t + 9.999998857e-01f;
     float a = r * p;
     a = ay > ax ? 1.57079632679f - a : a;
     a = x < 0.0f ? 3.14159265359f - a : a;
@@ -37,8 +52,9 @@ __device__ inline float atan2_poly(float y, float x) {
 // 1/x in double from the hardware estimate and two Newton steps
 // (y <- y + y (1 - x y)), each doubling the correct bits: within ~1 ulp.
 // For the normal, non-zero arguments of the kernels' paths only.
-__device__ inline double rcp_nr(double x) {
-    double y = __builtin_amdgcn_rcp(x);
+template <class Ops = HwOps>
+__host__ __device__ inline double rcp_nr(double x) {
+    double y = Ops::rcp(x);
     double e = fma(-x, y, 1.0);
     y = fma(y, e, y);
     e = fma(-x, y, 1.0);
@@ -48,14 +64,16 @@ __device__ inline double rcp_nr(double x) {
 // atan2 for double on the kernels' paths: r = min/max in [0, 1]; above
 // tan(pi/8) use atan r = pi/4 + atan((r - 1)/(r + 1)), so |t| <= tan(pi/8);
 // atan t = t P(t^2) with P of degree 10 (a least-squares fit to atan(t)/t
-// at Chebyshev nodes in t^2 on [0, tan^2(pi/8)], done in 40-digit
-// arithmetic and weighted for relative error: ~1 ulp evaluated in double).
-__device__ inline double atan2_poly(double y, double x) {
+// at 64 Chebyshev nodes in t^2 on [0, tan^2(pi/8)], done in 40-digit
+// arithmetic and weighted for relative error, as fit_atan_poly.py beside
+// this file derives it: 3.5e-17 in exact arithmetic, ~1 ulp in double).
+template <class Ops = HwOps>
+__host__ __device__ inline double atan2_poly(double y, double x) {
     const double ax = fabs(x), ay = fabs(y);
     const double mx = fmax(ax, ay), mn = fmin(ax, ay);
-    const double r = mx > 0.0 ? mn * rcp_nr(mx) : 0.0;
+    const double r = mx > 0.0 ? mn * rcp_nr<Ops>(mx) : 0.0;
     const bool big = r > 0.41421356237309503;             // tan(pi/8)
-    const double t = big ? (r - 1.0) * rcp_nr(r + 1.0) : r;
+    const double t = big ? (r - 1.0) * rcp_nr<Ops>(r + 1.0) : r;
     const double u = t * t;
     double p = 2.11428279540593587e-02;
     p = fma(p, u, -4.34869344380681838e-02);
@@ -74,13 +92,13 @@ __device__ inline double atan2_poly(double y, double x) {
     return y < 0.0 ? -a : a;
 }
 
-template <> struct Num<double> {
+template <class Ops> struct Num<double, Ops> {
     static constexpr double pi = 3.14159265358979323846;
-    __device__ static double sqrt_(double x) { return sqrt(x); }
-    __device__ static double rcp_(double x) { return rcp_nr(x); }
-    __device__ static double atan2_(double y, double x) { return atan2_poly(y, x); }
-    __device__ static void sincos_(double x, double* s, double* c) { sincos(x, s, c); }
-    __device__ static double abs_(double x) { return fabs(x); }
+    __host__ __device__ static double sqrt_(double x) { return sqrt(x); }
+    __host__ __device__ static double rcp_(double x) { return rcp_nr<Ops>(x); }
+    __host__ __device__ static double atan2_(double y, double x) { return atan2_poly<Ops>(y, x); }
+    __host__ __device__ static void sincos_(double x, double* s, double* c) { sincos(x, s, c); }
+    __host__ __device__ static double abs_(double x) { return fabs(x); }
     // Halley iterations stop once a step is below this; the cubic rate then
     // leaves an error far below one ulp.
     static constexpr double kepler_stop = 1e-6;
@@ -88,13 +106,13 @@ template <> struct Num<double> {
 };
 // Float: the hardware reciprocal and square root (1 ulp) stand in for the
 // correctly rounded forms; every use tolerates a relative error of 1e-6.
-template <> struct Num<float> {
+template <class Ops> struct Num<float, Ops> {
     static constexpr float pi = 3.14159265358979323846f;
-    __device__ static float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
-    __device__ static float rcp_(float x) { return __builtin_amdgcn_rcpf(x); }
-    __device__ static float atan2_(float y, float x) { return atan2_poly(y, x); }
-    __device__ static void sincos_(float x, float* s, float* c) { sincosf(x, s, c); }
-    __device__ static float abs_(float x) { return fabsf(x); }
+    __host__ __device__ static float sqrt_(float x) { return Ops::sqrt(x); }
+    __host__ __device__ static float rcp_(float x) { return Ops::rcp(x); }
+    __host__ __device__ static float atan2_(float y, float x) { return atan2_poly<Ops>(y, x); }
+    __host__ __device__ static void sincos_(float x, float* s, float* c) { sincosf(x, s, c); }
+    __host__ __device__ static float abs_(float x) { return fabsf(x); }
     static constexpr float kepler_stop = 2e-3f;
     static constexpr int kepler_maxit = 20;
 };
@@ -105,7 +123,7 @@ template <> struct Num<float> {
 // (truncation below 1e-11); larger float arguments and every double
 // argument use the library sincos (a double series of the same accuracy
 // measured slower).
-__device__ inline void sincos_small(float x, float* s, float* c) {
+__host__ __device__ inline void sincos_small(float x, float* s, float* c) {
     if (fabsf(x) > 0.25f) {
         sincosf(x, s, c);
         return;
@@ -121,12 +139,14 @@ __device__ inline void sincos_small(float x, float* s, float* c) {
     pc = pc * x2 - 0.5f;
     *c = 1.0f + x2 * pc;
 }
-__device__ inline void sincos_small(double x, double* s, double* c) { sincos(x, s, c); }
+__host__ __device__ inline void sincos_small(double x, double* s, double* c) {
+    sincos(x, s, c);
+}
 
 // (sin x, cos x) -> (sin(x + y), cos(x + y)) for |y| <= 1e-3, with
 // sin y = y - y^3/6 and cos y = 1 - y^2/2 + y^4/24 (truncation below 1e-17).
 template <typename R>
-__device__ inline void rotate_small(R y, R* s, R* c) {
+__host__ __device__ inline void rotate_small(R y, R* s, R* c) {
     const R y2 = y * y;
     const R sy = y - y * y2 * R(1.0 / 6.0);
     const R cy = R(1) - y2 * (R(0.5) - y2 * R(1.0 / 24.0));
@@ -142,11 +162,13 @@ __device__ inline void rotate_small(R y, R* s, R* c) {
 // Heron's formula (sides sorted a >= b >= c), the half chord is h = 2D/c and
 // the two half-angles are atan2(h, x) with x the signed distances from each
 // centre to the chord.  A = Rd^2 k1 + k^2 k0 - c h.  Unlike the arccos form
-// this keeps full relative accuracy near contact points, where FP32 would
-// otherwise lose several ppm.
-template <typename R>
-__device__ inline R lens_area(R Rd, R k, R c) {
-    using N = Num<R>;
+// this keeps its accuracy at the contact points, where FP32 would otherwise
+// lose several ppm: the host build against 40-digit arithmetic gives an
+// absolute error below 5e-7 min(1, k) in float and 5e-13 min(1, k)^2 in
+// double for k from 0.001 to 1.5.
+template <typename R, class Ops = HwOps>
+__host__ __device__ inline R lens_area(R Rd, R k, R c) {
+    using N = Num<R, Ops>;
     if (c >= Rd + k) return R(0);
     const R dk = Rd - k;
     if (c <= N::abs_(dk)) {
@@ -174,7 +196,7 @@ __device__ inline R lens_area(R Rd, R k, R c) {
 template <typename R>
 struct OrbitR {
     R n, e, sE, cE, q, a, cosw, sinw, rtr, cosi;
-    __device__ explicit OrbitR(const PvConst& p)
+    __host__ __device__ explicit OrbitR(const PvConst& p)
         : n(R(p.n)), e(R(p.e)), sE(R(p.sE)), cE(R(p.cE)), q(R(p.q)),
           a(R(p.a)), cosw(R(p.cosw)), sinw(R(p.sinw)), rtr(R(p.rtr)),
           cosi(R(p.cosi)) {}
@@ -189,9 +211,9 @@ struct OrbitR {
 // sin(d/2), cos(d/2) at d; after the last, small step they are rotated
 // rather than recomputed.  cos d - 1 = -2 sin^2(d/2) keeps every quantity
 // small near transit, so float keeps its relative precision there.
-template <typename R>
-__device__ inline R kepler_halley(R dM, R e, R sE, R cE, R* s2, R* c2) {
-    using N = Num<R>;
+template <typename R, class Ops = HwOps>
+__host__ __device__ inline R kepler_halley(R dM, R e, R sE, R cE, R* s2, R* c2) {
+    using N = Num<R, Ops>;
     R lo = dM - R(2) * e, hi = dM + R(2) * e;
     R d = dM * N::rcp_(R(1) - e * cE);
     d = d < lo ? lo : (d > hi ? hi : d);
@@ -217,32 +239,31 @@ __device__ inline R kepler_halley(R dM, R e, R sE, R cE, R* s2, R* c2) {
     return d;
 }
 
-template <typename R>
-__device__ inline R kepler_offset(R dM, R e, R sE, R cE, R* s2, R* c2) {
-    return kepler_halley<R>(dM, e, sE, cE, s2, c2);
-}
-
-// Double: the float solve's root (good to ~1e-7) and one Halley step in
-// double, whose cubic rate leaves an error far below one ulp.  If that step
-// is not small (float too coarse, e.g. e close to 1 near periapsis), the
-// bracketed solve is repeated in double.
-template <>
-__device__ inline double kepler_offset<double>(double dM, double e, double sE, double cE,
-                                               double* s2, double* c2) {
-    float s2f, c2f;
-    const double d = kepler_halley<float>(float(dM), float(e), float(sE), float(cE), &s2f, &c2f);
-    sincos_small(0.5 * d, s2, c2);
-    const double sd = 2.0 * *s2 * *c2;
-    const double cm1 = -2.0 * *s2 * *s2;
-    const double h = d - e * (sE * cm1 + cE * sd) - dM;
-    const double hp = 1.0 - e * (cE * (1.0 + cm1) - sE * sd);
-    const double hpp = e * (sE * (1.0 + cm1) + cE * sd);
-    const double step = -2.0 * h * hp / (2.0 * hp * hp - h * hpp);
-    if (fabs(step) < 2e-6) {
-        rotate_small(0.5 * step, s2, c2);
-        return d + step;
+// Kepler solve of the bulk precision.  Double: the float solve's root (good
+// to ~1e-7) and one Halley step in double, whose cubic rate leaves an error
+// far below one ulp.  If that step is not small (float too coarse, e.g. e
+// close to 1 near periapsis), the bracketed solve is repeated in double.
+template <typename R, class Ops = HwOps>
+__host__ __device__ inline R kepler_offset(R dM, R e, R sE, R cE, R* s2, R* c2) {
+    if constexpr (std::is_same<R, double>::value) {
+        float s2f, c2f;
+        const double d = kepler_halley<float, Ops>(float(dM), float(e), float(sE), float(cE),
+                                                   &s2f, &c2f);
+        sincos_small(0.5 * d, s2, c2);
+        const double sd = 2.0 * *s2 * *c2;
+        const double cm1 = -2.0 * *s2 * *s2;
+        const double h = d - e * (sE * cm1 + cE * sd) - dM;
+        const double hp = 1.0 - e * (cE * (1.0 + cm1) - sE * sd);
+        const double hpp = e * (sE * (1.0 + cm1) + cE * sd);
+        const double step = -2.0 * h * hp / (2.0 * hp * hp - h * hpp);
+        if (fabs(step) < 2e-6) {
+            rotate_small(0.5 * step, s2, c2);
+            return d + step;
+        }
+        return kepler_halley<double, Ops>(dM, e, sE, cE, s2, c2);
+    } else {
+        return kepler_halley<R, Ops>(dM, e, sE, cE, s2, c2);
     }
-    return kepler_halley<double>(dM, e, sE, cE, s2, c2);
 }
 
 // Projected separation for a time offset dt from conjunction.  The sky
@@ -252,12 +273,12 @@ __device__ inline double kepler_offset<double>(double dM, double e, double sE, d
 //   rho = r sin(w + f) = r_tr + a [(cos E - cos E_tr) sin w
 //                                  + q (sin E - sin E_tr) cos w]
 //   Y   = -rho cos i,  z = sqrt(X^2 + Y^2),  in front iff rho > 0.
-template <typename R>
-__device__ inline R separation(R dt, const OrbitR<R>& o, bool* front) {
-    using N = Num<R>;
+template <typename R, class Ops = HwOps>
+__host__ __device__ inline R separation(R dt, const OrbitR<R>& o, bool* front) {
+    using N = Num<R, Ops>;
     const R dM = o.n * dt;
     R s2, c2;
-    if (o.e > R(0)) kepler_offset<R>(dM, o.e, o.sE, o.cE, &s2, &c2);
+    if (o.e > R(0)) kepler_offset<R, Ops>(dM, o.e, o.sE, o.cE, &s2, &c2);
     else sincos_small(R(0.5) * dM, &s2, &c2);
     const R sd = R(2) * s2 * c2;
     const R cm1 = R(-2) * s2 * s2;
