@@ -133,6 +133,23 @@ RR_API int rr_prepare_ld(const double* mu, const double* prof, int32_t nmu,
 RR_API int rr_set_profile(rr_tables* t, const double* prof_d,
                           hipStream_t stream);
 
+/* Set the normaliser I_star of every passband to istar_d[npb] (device
+ * FP64, finite and > 0; other values give NaN fluxes), in place of the
+ * exact integral of the profile interpolant, or with istar_d = NULL go
+ * back to that integral.  For profiles that come from a law with a known
+ * disk integral, such as the named laws, which the paper normalises by
+ * their analytic integral (Sect. 3.2.1), or a callable with its own
+ * normalising integral (Sect. 3.2.2).  The values stay in force across
+ * rr_set_profile until changed or cleared; they apply wherever the
+ * tables' own profile is used (rr_evaluate, rr_evaluate_series,
+ * rr_evaluate_direct, rr_evaluate_small_planet, rr_flux_at_z,
+ * rr_loglik_grad*), not to the per-vector profiles of rr_evaluate_ld and
+ * rr_loglik_grad_ld, which are normalised by their own integrals.  Enqueued
+ * on `stream` without a host synchronisation (the first call allocates
+ * 8 npb bytes); work on other streams that reads the tables must be
+ * ordered after it by the caller. */
+RR_API int rr_set_istar(rr_tables* t, const double* istar_d, hipStream_t stream);
+
 /* Fluxes for npv parameter vectors at npt mid-exposure times.
  * times_d[npt]   device FP64 mid-exposure times;
  * lcids_d[npt]   device int32 light-curve index of each time, each in
@@ -381,15 +398,17 @@ RR_API int rr_evaluate_ld(const rr_tables* t, const double* times_d,
  * grad_prof_d device double[npb][nmu], or NULL: the gradient of
  *           sum_ipv wprof[ipv] logl[ipv] with respect to the tables' LD
  *           profile samples (through the profile interpolation, I_star and
- *           T = W . ldp);
+ *           T = W . ldp; with I_star held at the caller's values while
+ *           rr_set_istar is in force);
  * wprof_d   device double[npv] weights for grad_prof_d, or NULL for ones.
  * At least one output must be requested.  Invalid rows give NaN in logl
- * and grad and contribute nothing to grad_prof.  logl and grad are summed
- * in FP64 in a fixed order (bitwise reproducible); grad_prof sums each
- * workgroup's share through LDS FP64 atomics and adds the shares in a fixed
- * order, reproducible to rounding.  The adjoint keeps npb * ng * (2
- * sizeof(real) + 8) bytes of tables in LDS, at most 64 KiB (RR_ELIMIT
- * beyond).  Temporary device memory comes from the stream-ordered
+ * and grad and contribute nothing to grad_prof.  Every sum is formed in
+ * FP64 in an order fixed by the inputs (grad_prof: each wave's partial sums
+ * in its own LDS copy, the copies added in wave order, then the workgroups
+ * in order), so all outputs are bitwise reproducible.  The adjoint keeps
+ * npb * ng * (2 sizeof(real) + 8) bytes of tables in LDS (and with
+ * grad_prof a copy of d logL / d ldw per wave), at most the device's LDS per
+ * workgroup (RR_ELIMIT beyond).  Temporary device memory comes from the stream-ordered
  * allocator: ~(160 + 8 (7 + npb) npt / 1024) bytes per parameter vector,
  * and with grad_prof a further 8 npb ng bytes per vector plus at most
  * 512 MiB of partial sums. */
@@ -401,6 +420,22 @@ RR_API int rr_loglik_grad(const rr_tables* t, const double* times_d,
                           int32_t precision, const void* obs_d, double sigma,
                           const double* wprof_d, double* logl_d, double* grad_d,
                           double* grad_prof_d, hipStream_t stream);
+
+/* rr_loglik_grad with one more output: grad_istar_d, device double[npb]
+ * (or NULL), the gradient of sum_ipv wprof[ipv] logl[ipv] with respect to
+ * each passband's normaliser I_star, for callers that set I_star
+ * themselves (rr_set_istar) and carry its dependence on LD coefficients
+ * (Sect. 3.2.1: named laws integrated analytically).  Arguments, errors
+ * and memory otherwise as rr_loglik_grad. */
+RR_API int rr_loglik_grad_istar(const rr_tables* t, const double* times_d,
+                                const int32_t* lcids_d, int32_t npt,
+                                const int32_t* pbids, const int32_t* nss,
+                                const double* exptimes, int32_t nlc,
+                                const double* pv_d, int32_t npv, int32_t npar,
+                                int32_t precision, const void* obs_d, double sigma,
+                                const double* wprof_d, double* logl_d, double* grad_d,
+                                double* grad_prof_d, double* grad_istar_d,
+                                hipStream_t stream);
 
 /* rr_loglik_grad with a limb-darkening profile per parameter vector (as
  * rr_evaluate_ld; prof_d[npv][npb][nmu] device FP64 on the tables' mu

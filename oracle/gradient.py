@@ -147,12 +147,14 @@ def _pv_terms(tab, row, ts, pb):
 
 
 def loglik_grad(tab, times, pv, obs, sigma, lcids=None, pbids=None, nss=None,
-                exptimes=None, want_profile=True):
-    """(logL[npv], grad[npv][npar], grad_profile[npb][nmu] or None).
+                exptimes=None, want_profile=True, want_istar=False):
+    """(logL[npv], grad[npv][npar], grad_profile[npb][nmu] or None), and with
+    ``want_istar`` a fourth entry: d(sum_pv logL)/d I_star[npb].
 
     grad_profile is the gradient of sum_pv logL with respect to the profile
-    samples I_s of the tables.  Invalid rows give NaN logL and gradients and
-    do not contribute to grad_profile."""
+    samples I_s of the tables, through I_star as well unless the tables hold
+    a fixed normaliser (``Tables(..., istar=...)``).  Invalid rows give NaN
+    logL and gradients and do not contribute to grad_profile."""
     times = np.asarray(times, float)
     obs = np.asarray(obs, float)
     pv = np.atleast_2d(np.asarray(pv, float))
@@ -203,7 +205,11 @@ def loglik_grad(tab, times, pv, obs, sigma, lcids=None, pbids=None, nss=None,
     if want_profile:
         R, q = profile_maps(tab)
         Gldp = np.einsum("imj,pim->pj", tab.W, GT)
-        gprof = Gldp @ R + Gist[:, None] * q[None, :]
+        gprof = Gldp @ R
+        if not getattr(tab, "istar_fixed", False):
+            gprof = gprof + Gist[:, None] * q[None, :]
+    if want_istar:
+        return logl, grad, gprof, (Gist if want_profile else None)
     return logl, grad, gprof
 
 

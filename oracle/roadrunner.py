@@ -142,9 +142,15 @@ def ld_tables(W, ldp):
 
 
 class Tables:
-    """Everything Oracle-A precomputes for one grid and one set of profiles."""
+    """Everything Oracle-A precomputes for one grid and one set of profiles.
 
-    def __init__(self, mu_s, I_s, zcut, nzin, nzlimb, ng, nk, k0, k1):
+    ``istar`` (one value per passband) replaces the interpolant's integral
+    as the normaliser, for a law whose disk integral is known in closed form
+    (Sect. 3.2.1: the named laws are normalised by their analytic integral;
+    Sect. 3.2.2: a callable may come with its normalising integral); it then
+    stays fixed when the profile samples change."""
+
+    def __init__(self, mu_s, I_s, zcut, nzin, nzlimb, ng, nk, k0, k1, istar=None):
         self.mu_s = np.asarray(mu_s, float)
         self.I_s = np.atleast_2d(np.asarray(I_s, float))
         self.zcut, self.nzin, self.nzlimb = zcut, nzin, nzlimb
@@ -152,7 +158,9 @@ class Tables:
         self.ze, self.zm, self.mu = z_grid(zcut, nzin, nzlimb)
         self.dk, self.dg, self.W = weights_3d(self.ze, nk, k0, k1, ng)
         self.ldp = profile_on_grid(self.mu_s, self.I_s, self.mu)
-        self.istar = istar_of_profile(self.mu_s, self.I_s)
+        self.istar_fixed = istar is not None
+        self.istar = (np.broadcast_to(np.asarray(istar, float), (self.npb,)).copy()
+                      if self.istar_fixed else istar_of_profile(self.mu_s, self.I_s))
         self.T = ld_tables(self.W, self.ldp)
 
     @property
@@ -270,7 +278,8 @@ def with_profile(tab, I_s):
     if t.I_s.shape != tab.I_s.shape:
         raise ValueError("profile samples must have the tables' shape")
     t.ldp = profile_on_grid(t.mu_s, t.I_s, t.mu)
-    t.istar = istar_of_profile(t.mu_s, t.I_s)
+    if not getattr(t, "istar_fixed", False):
+        t.istar = istar_of_profile(t.mu_s, t.I_s)
     t.T = ld_tables(t.W, t.ldp)
     return t
 

@@ -124,6 +124,10 @@ def _declare(L):
                                         i32, c_void_p, dbl, c_void_p, c_void_p, c_void_p,
                                         c_void_p]
         L.rr_loglik_grad_ld.restype = ctypes.c_int
+        L.rr_loglik_grad_istar.argtypes = L.rr_loglik_grad.argtypes[:-1] + [c_void_p, c_void_p]
+        L.rr_loglik_grad_istar.restype = ctypes.c_int
+    L.rr_set_istar.argtypes = [c_void_p, c_void_p, c_void_p]
+    L.rr_set_istar.restype = ctypes.c_int
     _ = dbl
 
 

@@ -92,6 +92,20 @@ class Tables:
                                         _stream(stream)), "rr_set_profile")
         return prof_d
 
+    def set_istar(self, istar=None, stream=None):
+        """Normalise passband pb by istar[pb] instead of the profile
+        interpolant's integral (rr_set_istar), e.g. a named law's analytic
+        integral from ``ldlaws.istar``; None goes back to the integral."""
+        if istar is None:
+            check(_lib.lib().rr_set_istar(self.handle, None, _stream(stream)), "rr_set_istar")
+            return None
+        istar = _dev(istar, torch.float64).reshape(-1)
+        if istar.numel() != self.npb:
+            raise ValueError("istar needs one value per passband")
+        check(_lib.lib().rr_set_istar(self.handle, ctypes.c_void_p(istar.data_ptr()),
+                                      _stream(stream)), "rr_set_istar")
+        return istar
+
     def copy(self, name):
         """Copy one device table to a NumPy array (synchronous)."""
         L = _lib.lib()
@@ -449,12 +463,14 @@ class Evaluator:
 
 
 def loglik_grad(tables, series, pv, obs, sigma, precision="fp64", grad=True, profile=False,
-                wprof=None, stream=None):
+                wprof=None, stream=None, istar_grad=False):
     """Gaussian log-likelihood of ``obs`` under each parameter row and its
     gradients (rr_loglik_grad).  Returns (logl[npv], grad[npv, npar] or None,
     grad_profile[npb, nmu] or None), float64 device tensors; grad_profile is
     the gradient of sum(wprof * logl) (wprof = ones if None) with respect to
-    the tables' LD profile samples."""
+    the tables' LD profile samples.  With ``istar_grad`` (rr_loglik_grad_istar)
+    a fourth tensor, the gradient of the same sum with respect to each
+    passband's I_star, follows."""
     prec = PRECISIONS[precision]
     if not isinstance(series, TimeSeries):
         series = TimeSeries(series)
@@ -475,6 +491,14 @@ def loglik_grad(tables, series, pv, obs, sigma, precision="fp64", grad=True, pro
         return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
     lc, npt, pb, nss, ex, nlc = series.lc_args()
+    if istar_grad:
+        gi = torch.empty(tables.npb, dtype=torch.float64, device=pv.device)
+        check(_lib.lib().rr_loglik_grad_istar(tables.handle, p(series.times), lc, npt, pb, nss,
+                                              ex, nlc, p(pv), npv, npar, prec, p(obs),
+                                              float(sigma), p(w), p(logl), p(g), p(gp), p(gi),
+                                              _stream(stream)),
+              "rr_loglik_grad_istar")
+        return logl, g, gp, gi
     check(_lib.lib().rr_loglik_grad(tables.handle, p(series.times), lc, npt, pb, nss, ex, nlc,
                                     p(pv), npv, npar, prec, p(obs), float(sigma), p(w),
                                     p(logl), p(g), p(gp), _stream(stream)),

@@ -662,7 +662,7 @@ constexpr int kMuLds = 1024;
 __global__ void k_prof_grad(const double* __restrict__ gldp, const double* __restrict__ gist,
                             const double* __restrict__ mu_s, int32_t nmu,
                             const double* __restrict__ zm, int32_t nz, int32_t npb,
-                            double* __restrict__ out) {
+                            int32_t istar_fixed, double* __restrict__ out) {
     __shared__ int seg_lo[kJChunk];
     __shared__ double seg_tau[kJChunk];
     __shared__ double gl[kJChunk];
@@ -741,7 +741,8 @@ __global__ void k_prof_grad(const double* __restrict__ gldp, const double* __res
     if (s == 0) qs += 0.5 * ms[0] * ms[0];
     if (s == nmu - 1) qs += 0.5 * (1.0 - ms[nmu - 1] * ms[nmu - 1]);
     qs *= 2.0 * Num<double>::pi;
-    out[int64_t(pb) * nmu + s] = acc + qs * gist[pb];
+    // a normaliser set by the caller does not depend on the samples
+    out[int64_t(pb) * nmu + s] = istar_fixed ? acc : acc + qs * gist[pb];
 }
 
 inline unsigned nblocks(int64_t n) { return unsigned((n + kBlock - 1) / kBlock); }
@@ -966,6 +967,7 @@ hipError_t launch_pv_prof_grad(const rr_tables* t, const AdjointArgs& A, const i
         const int32_t n = int32_t(std::min<int64_t>(65535, nr - r0));
         hipLaunchKernelGGL(k_prof_grad, dim3(nblocks(t->nmu), unsigned(n)), dim3(kBlock), 0, s,
                            gldp + r0 * t->nz, A.gist_pv + r0, t->mu_s, t->nmu, t->zm, t->nz, n,
+                           0,
                            out + r0 * t->nmu);
     }
     return hipGetLastError();
@@ -996,8 +998,15 @@ hipError_t launch_profile_grad(const rr_tables* t, const AdjointArgs& A,
                        A.pvc, g.npb, w.gist);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_prof_grad, dim3(nblocks(t->nmu), unsigned(g.npb)), dim3(kBlock), 0, s,
-                       w.gldp, w.gist, t->mu_s, t->nmu, t->zm, t->nz, g.npb, out);
+    if (w.grad_istar) {
+        e = hipMemcpyAsync(w.grad_istar, w.gist, sizeof(double) * g.npb,
+                           hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return e;
+    }
+    if (out)
+        hipLaunchKernelGGL(k_prof_grad, dim3(nblocks(t->nmu), unsigned(g.npb)), dim3(kBlock), 0,
+                           s, w.gldp, w.gist, t->mu_s, t->nmu, t->zm, t->nz, g.npb,
+                           w.istar_fixed, out);
     return hipGetLastError();
 }
 

@@ -96,7 +96,7 @@ static void free_tables(rr_tables* t) {
     (void)hipGetDevice(&cur);
     (void)hipSetDevice(t->device);
     void* bufs[] = {t->mu_s, t->prof, t->ze, t->zm, t->ldp, t->istar,
-                    t->W, t->W32, t->T64, t->T32, t->inv_istar};
+                    t->W, t->W32, t->T64, t->T32, t->inv_istar, t->istar_user};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     for (auto& kv : t->ws)
@@ -269,6 +269,27 @@ RR_API int rr_set_profile(rr_tables* t, const double* prof_d, hipStream_t stream
     if (e != hipSuccess) return hip_fail(e, "copy profile");
     e = launch_prepare_profile(t, stream);
     if (e != hipSuccess) return hip_fail(e, "profile kernels");
+    return RR_OK;
+}
+
+RR_API int rr_set_istar(rr_tables* t, const double* istar_d, hipStream_t stream) {
+    if (!t) return einval("tables handle is NULL");
+    int rc = check_device(t);
+    if (rc) return rc;
+    hipError_t e;
+    if (!istar_d) {
+        t->istar_fixed = false;
+        e = launch_istar_from_profile(t, stream);
+        if (e != hipSuccess) return hip_fail(e, "I_star kernel");
+        return RR_OK;
+    }
+    if (!t->istar_user) {
+        e = hipMalloc((void**)&t->istar_user, sizeof(double) * t->npb);
+        if (e != hipSuccess) return e == hipErrorOutOfMemory ? RR_ENOMEM : hip_fail(e, "hipMalloc");
+    }
+    e = launch_istar_set(t, istar_d, stream);
+    if (e != hipSuccess) return hip_fail(e, "I_star kernel");
+    t->istar_fixed = true;
     return RR_OK;
 }
 
@@ -734,15 +755,17 @@ static int loglik_impl(const rr_tables* t, const double* times_d,
                        int32_t precision, const void* obs_d, double sigma,
                        const double* wprof_d, double* logl_d, double* grad_d,
                        double* grad_prof_d, bool per_row, const double* prof_pv_d,
-                       hipStream_t stream, double k_small = -1.0) {
+                       hipStream_t stream, double k_small = -1.0,
+                       double* grad_istar_d = nullptr) {
     LcInfo lc;
     int rc = check_eval_args(t, times_d, lcids_d, npt, pbids, nss, exptimes, nlc,
                              pv_d, npv, npar, precision, &lc);
     if (rc) return rc;
     if (!(sigma > 0.0) || !isfinite(sigma)) return einval("sigma must be finite and > 0");
     if (npt > 0 && npv > 0 && !obs_d) return einval("obs is NULL");
-    if (npv > 0 && !logl_d && !grad_d && !grad_prof_d) return einval("no output requested");
-    if (adjoint_lds_bytes(precision, t->npb, t->grid.ng, grad_prof_d != nullptr) +
+    if (npv > 0 && !logl_d && !grad_d && !grad_prof_d && !grad_istar_d)
+        return einval("no output requested");
+    if (adjoint_lds_bytes(precision, t->npb, t->grid.ng, grad_prof_d || grad_istar_d) +
             kAdjStaticLds > t->lds_max)
         return elimit("npb * ng adjoint LDS tables exceed the device's LDS per workgroup");
     rc = check_device(t);
@@ -757,9 +780,13 @@ static int loglik_impl(const rr_tables* t, const double* times_d,
             e = launch_fill(grad_prof_d, int64_t(t->npb) * t->nmu, stream);
             if (e != hipSuccess) return hip_fail(e, "fill");
         }
+        if (grad_istar_d) {
+            e = launch_fill(grad_istar_d, t->npb, stream);
+            if (e != hipSuccess) return hip_fail(e, "fill");
+        }
         return RR_OK;
     }
-    const bool prof = grad_prof_d != nullptr;
+    const bool prof = grad_prof_d != nullptr || grad_istar_d != nullptr;
     const int32_t tile = adj_tile(prof, precision == RR_FP64);
     const int32_t ntiles = npt > 0 ? (npt + tile - 1) / tile : 1;
     const int32_t nq = 7 + t->npb;
@@ -872,6 +899,8 @@ static int loglik_impl(const rr_tables* t, const double* times_d,
         w.ldp_part = reinterpret_cast<double*>(base + o_ldpp);
         w.gldp = reinterpret_cast<double*>(base + o_gldp);
         w.gist = reinterpret_cast<double*>(base + o_gist_sum);
+        w.istar_fixed = t->istar_fixed ? 1 : 0;
+        w.grad_istar = grad_istar_d;
         e = launch_profile_grad(t, A, w, grad_prof_d, stream);
     }
     hipError_t ef = hipFreeAsync(base, stream);
@@ -891,6 +920,20 @@ RR_API int rr_loglik_grad(const rr_tables* t, const double* times_d,
     return loglik_impl(t, times_d, lcids_d, npt, pbids, nss, exptimes, nlc, pv_d, npv, npar,
                        precision, obs_d, sigma, wprof_d, logl_d, grad_d, grad_prof_d, false,
                        nullptr, stream);
+}
+
+RR_API int rr_loglik_grad_istar(const rr_tables* t, const double* times_d,
+                                const int32_t* lcids_d, int32_t npt,
+                                const int32_t* pbids, const int32_t* nss,
+                                const double* exptimes, int32_t nlc,
+                                const double* pv_d, int32_t npv, int32_t npar,
+                                int32_t precision, const void* obs_d, double sigma,
+                                const double* wprof_d, double* logl_d, double* grad_d,
+                                double* grad_prof_d, double* grad_istar_d,
+                                hipStream_t stream) {
+    return loglik_impl(t, times_d, lcids_d, npt, pbids, nss, exptimes, nlc, pv_d, npv, npar,
+                       precision, obs_d, sigma, wprof_d, logl_d, grad_d, grad_prof_d, false,
+                       nullptr, stream, -1.0, grad_istar_d);
 }
 
 RR_API int rr_loglik_grad_ld(const rr_tables* t, const double* times_d,

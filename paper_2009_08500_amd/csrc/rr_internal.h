@@ -195,6 +195,10 @@ struct rr_tables {
     double* T64 = nullptr;       // [npb][nk][ng]
     float* T32 = nullptr;        // [npb][nk][ng]
     double* inv_istar = nullptr; // [npb]
+    // rr_set_istar: normalisers given by the caller, [npb] device, used in
+    // place of the profile interpolant's integral while istar_fixed
+    double* istar_user = nullptr;
+    bool istar_fixed = false;
     // Per-stream temporaries of rr_evaluate (grow-only; work on one stream is
     // ordered, so a stream's buffer is reused without waiting).
     std::mutex ws_mu;
@@ -255,6 +259,8 @@ struct ProfGradScratch {
     double* ldp_part;     // [npb][nz][16]
     double* gldp;         // [npb][nz]
     double* gist;         // [npb]
+    int32_t istar_fixed;  // 1: I_star does not depend on the samples (rr_set_istar)
+    double* grad_istar;   // [npb] output (d logL / d I_star) or null
 };
 // Per-vector LD: d logL / d prof[ipv][pb][s] from the adjoint's per-vector
 // d logL / d ldw and d logL / d I_star; ikr and perm are launch_pv_ld's sort
@@ -266,6 +272,12 @@ hipError_t launch_pv_prof_grad(const rr_tables* t, const AdjointArgs& A, const i
 hipError_t launch_profile_grad(const rr_tables* t, const AdjointArgs& a,
                                const ProfGradScratch& w, double* out, hipStream_t s);
 hipError_t launch_fill(double* p, int64_t n, hipStream_t s);
+// I_star and 1/I_star from the caller's normalisers (rr_set_istar): copy
+// src[npb] into the tables' istar and istar_user (when given) and set
+// inv_istar; a value that is not finite and positive gives NaN fluxes.
+hipError_t launch_istar_set(rr_tables* t, const double* src, hipStream_t s);
+// I_star from the profile samples (the interpolant's exact integral).
+hipError_t launch_istar_from_profile(rr_tables* t, hipStream_t s);
 // Whether rr_evaluate_series takes the split launch for this size: when the
 // per-tile kernel's workgroups (npv x tiles of 512 times) number at most
 // 2.5 x the split kernel's resident workgroups (measured crossover, both

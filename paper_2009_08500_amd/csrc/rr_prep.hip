@@ -675,15 +675,37 @@ hipError_t launch_pv_ld(const rr_tables* t, const double* prof, const double* pv
     return hipGetLastError();
 }
 
+__global__ void k_istar_set(const double* __restrict__ src, int32_t npb,
+                            double* __restrict__ user, double* __restrict__ istar,
+                            double* __restrict__ inv_istar) {
+    const int pb = blockIdx.x * blockDim.x + threadIdx.x;
+    if (pb >= npb) return;
+    const double v = src[pb];
+    if (user) user[pb] = v;
+    istar[pb] = v;
+    inv_istar[pb] = (v > 0.0 && is_finite(v)) ? 1.0 / v : NAN;
+}
+
+hipError_t launch_istar_set(rr_tables* t, const double* src, hipStream_t s) {
+    hipLaunchKernelGGL(k_istar_set, dim3(1), dim3(kBlock), 0, s, src, t->npb,
+                       src == t->istar_user ? nullptr : t->istar_user, t->istar, t->inv_istar);
+    return hipGetLastError();
+}
+
+hipError_t launch_istar_from_profile(rr_tables* t, hipStream_t s) {
+    hipLaunchKernelGGL(k_istar, dim3(t->npb), dim3(kBlock), 0, s, t->mu_s, t->prof,
+                       t->nmu, t->istar, t->inv_istar);
+    return hipGetLastError();
+}
+
 hipError_t launch_prepare_profile(rr_tables* t, hipStream_t s) {
     const GridDev g = grid_dev(t);
     hipLaunchKernelGGL(k_profile, dim3(nblocks(int64_t(t->nz) * t->npb)), dim3(kBlock), 0, s,
                        t->mu_s, t->prof, t->nmu, t->zm, t->nz, t->npb, t->ldp);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_istar, dim3(t->npb), dim3(kBlock), 0, s, t->mu_s, t->prof,
-                       t->nmu, t->istar, t->inv_istar);
-    e = hipGetLastError();
+    // the caller's normalisers, if set, stay in force over a new profile
+    e = t->istar_fixed ? launch_istar_set(t, t->istar_user, s) : launch_istar_from_profile(t, s);
     if (e != hipSuccess) return e;
     const int64_t nt = int64_t(g.npb) * g.nk * g.ng;
     hipLaunchKernelGGL(k_tables, dim3(nblocks(nt)), dim3(kBlock), 0, s, t->W, t->ldp, g,
