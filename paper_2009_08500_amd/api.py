@@ -595,35 +595,54 @@ class RRLogLikLD(torch.autograd.Function):
 
 class RRLogLik(torch.autograd.Function):
     """logL[npv] = rr_loglik_grad(...) as a differentiable function of the
-    parameter rows ``pv`` [npv, npar] and the LD profile samples ``profile``
-    [npb, nmu] (written into ``tables`` on the current stream); backward
-    returns the hand-written adjoint's gradients."""
+    parameter rows ``pv`` [npv, npar], the LD profile samples ``profile``
+    [npb, nmu] and, optionally, the normalisers ``istar`` [npb] (a law's
+    closed-form disk integral, e.g. ``ldlaws.istar``; None: the profile
+    interpolant's integral).  Backward returns the hand-written adjoint's
+    gradients (rr_loglik_grad_istar for ``istar``).
+
+    The profile (and ``istar``) are written into ``tables`` on the current
+    stream (rr_set_profile, rr_set_istar): the tables then hold them for
+    every later use, and work on other streams must not read those tables
+    meanwhile -- give the function a Tables object of its own."""
 
     @staticmethod
-    def forward(ctx, pv, profile, tables, series, obs, sigma, precision):
+    def forward(ctx, pv, profile, tables, series, obs, sigma, precision, istar=None):
         if profile is not None:
             tables.set_profile(profile.detach())
+        if istar is not None:
+            tables.set_istar(istar.detach())
         want_prof = profile is not None and profile.requires_grad
-        logl, g, gp = loglik_grad(tables, series, pv.detach(), obs, sigma, precision,
-                                  grad=True, profile=want_prof)
+        want_ist = istar is not None and istar.requires_grad
+        out = loglik_grad(tables, series, pv.detach(), obs, sigma, precision,
+                          grad=True, profile=want_prof, istar_grad=want_ist)
+        logl, g, gp = out[:3]
+        gi = out[3] if want_ist else None
         ctx.tables, ctx.series, ctx.sigma, ctx.precision = tables, series, sigma, precision
-        ctx.want_prof = want_prof
+        ctx.want_prof, ctx.want_ist = want_prof, want_ist
         ctx.save_for_backward(pv.detach(), profile.detach() if profile is not None else None,
+                              istar.detach() if istar is not None else None,
                               obs if isinstance(obs, torch.Tensor) else torch.as_tensor(obs),
-                              g, gp)
+                              g, gp, gi)
         return logl
 
     @staticmethod
     def backward(ctx, gout):
-        pv, profile, obs, g, gp = ctx.saved_tensors
+        pv, profile, istar, obs, g, gp, gi = ctx.saved_tensors
         gpv = gout[:, None] * g
-        gprof = None
-        if ctx.want_prof:
+        gprof = gist = None
+        if ctx.want_prof or ctx.want_ist:
             if bool(torch.all(gout == gout[0])):
-                gprof = gp * gout[0]
+                gprof = gp * gout[0] if ctx.want_prof else None
+                gist = gi * gout[0] if ctx.want_ist else None
             else:
-                ctx.tables.set_profile(profile)
-                _, _, gprof = loglik_grad(ctx.tables, ctx.series, pv, obs, ctx.sigma,
-                                          ctx.precision, grad=False, profile=True,
-                                          wprof=gout.detach())
-        return gpv, gprof, None, None, None, None, None
+                if profile is not None:
+                    ctx.tables.set_profile(profile)
+                if istar is not None:
+                    ctx.tables.set_istar(istar)
+                out = loglik_grad(ctx.tables, ctx.series, pv, obs, ctx.sigma, ctx.precision,
+                                  grad=False, profile=ctx.want_prof, wprof=gout.detach(),
+                                  istar_grad=ctx.want_ist)
+                gprof = out[2] if ctx.want_prof else None
+                gist = out[3] if ctx.want_ist else None
+        return gpv, gprof, None, None, None, None, None, gist

@@ -113,3 +113,49 @@ def test_named_law_with_closed_form_istar_against_analytic(rr):
     fm = np.where(front, an.quadratic_flux(z, row[6], 0.4, 0.25), 1.0)
     assert np.abs(got - fm).max() <= 1e-6
     tab.close()
+
+
+def test_autograd_through_law_and_its_closed_form_istar(rr):
+    """RRLogLik with the power-2 profile and its closed-form I_star both
+    generated from (c, alpha) in torch: the gradient with respect to (c,
+    alpha) -- through the samples with I_star held fixed, plus through I_star
+    -- against central differences of the GPU log-likelihood."""
+    import torch
+    w = wl.loglik_walkers(npv=8, npt=4000, nss=2, seed_extra=52)
+    w["times"] = np.linspace(0.0, 15.0, 4000)
+    otab = orr.Tables(w["mu_s"], w["I_s"], **wl.TEST_GRID)
+    obs = orr.evaluate(otab, w["times"], w["truth"][None, :], nss=w["nss"],
+                       exptimes=w["exptimes"])[0] + w["noise"]
+    tab = rr.Tables(w["mu_s"], w["I_s"], wl.TEST_GRID)
+    ser = rr.TimeSeries(w["times"], nss=w["nss"], exptimes=w["exptimes"])
+    mu = torch.tensor(w["mu_s"], device="cuda")
+    c = torch.tensor(w["ld_c"], device="cuda", dtype=torch.float64, requires_grad=True)
+    al = torch.tensor(w["ld_alpha"], device="cuda", dtype=torch.float64, requires_grad=True)
+    pv = torch.tensor(w["pv"], device="cuda")
+    obs_t = torch.tensor(obs, device="cuda")
+    weights = torch.linspace(0.5, 1.5, 8, device="cuda", dtype=torch.float64)
+
+    def loss_fn(c_, al_):
+        coeffs = torch.stack([c_, al_])
+        prof = rr.ldlaws.profile("power-2", mu, coeffs)[None, :]
+        ist = rr.ldlaws.istar("power-2", coeffs).reshape(1).to("cuda")
+        ll = rr.RRLogLik.apply(pv, prof, tab, ser, obs_t, w["sigma"], "fp64", ist)
+        return (weights * ll).sum()
+
+    loss = loss_fn(c, al)
+    loss.backward()
+    with torch.no_grad():
+        h = 1e-6
+        fd_c = (loss_fn(c + h, al) - loss_fn(c - h, al)).item() / (2 * h)
+        fd_a = (loss_fn(c, al + h) - loss_fn(c, al - h)).item() / (2 * h)
+    assert c.grad.item() == pytest.approx(fd_c, rel=1e-4)
+    assert al.grad.item() == pytest.approx(fd_a, rel=1e-4)
+    # I_star's own part is not negligible: the gradient without it differs
+    c2 = c.detach().clone().requires_grad_(True)
+    coeffs = torch.stack([c2, al.detach()])
+    prof = rr.ldlaws.profile("power-2", mu, coeffs)[None, :]
+    ist = rr.ldlaws.istar("power-2", coeffs).reshape(1).to("cuda").detach()
+    ((weights * rr.RRLogLik.apply(pv, prof, tab, ser, obs_t, w["sigma"], "fp64", ist))
+     .sum()).backward()
+    assert abs(c2.grad.item() - fd_c) > 1e-3 * abs(fd_c)
+    tab.close()

