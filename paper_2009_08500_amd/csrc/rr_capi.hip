@@ -395,57 +395,11 @@ RR_API int rr_series_create(const double* times, const int32_t* lcids, int32_t n
         if (i < nlc) se->max_nss = std::max(se->max_nss, nss[i]);
     }
     // Each light curve one contiguous run of finite, non-decreasing times?
-    std::vector<SeriesLc> lcs(size_t(nlc), SeriesLc{0, 0, 0, 0, 0.0, 0.0, 0.0});
-    std::vector<char> seen(size_t(nlc), 0);
-    bool indexed = true, all_zero = true;
-    for (int32_t i = 0; i < npt && indexed; ++i) {
-        const int32_t l = lcids ? lcids[i] : 0;
-        if (l < 0 || l >= nlc || !isfinite(times[i])) { indexed = false; break; }
-        all_zero = all_zero && l == 0;
-        if (i == 0 || l != (lcids ? lcids[i - 1] : 0)) {
-            if (seen[l]) { indexed = false; break; }     // a second run of l
-            seen[l] = 1;
-            lcs[l].start = i;
-        } else if (!(times[i] >= times[i - 1])) {
-            indexed = false;
-        }
-        lcs[l].end = i + 1;
-    }
-    if (!lcids) all_zero = true;
-    // the index: per light curve nb + 1 entries (nb = its exposure count)
+    // Then the per-light-curve time index for the split launch.
+    std::vector<SeriesLc> lcs;
     std::vector<int32_t> buckets;
-    if (indexed) {
-        for (int l = 0; l < nlc; ++l) {
-            SeriesLc& sl = lcs[l];
-            const int32_t n = sl.end - sl.start;
-            sl.boff = int32_t(buckets.size());
-            if (n <= 0) {
-                sl.start = sl.end = 0;
-                sl.nb = 0;
-                buckets.push_back(0);
-                continue;
-            }
-            sl.t_first = times[sl.start];
-            sl.t_last = times[sl.end - 1];
-            if (!(sl.t_last > sl.t_first)) {
-                sl.nb = 1;
-                sl.inv_bw = 0.0;
-                buckets.push_back(sl.start);
-                buckets.push_back(sl.end);
-                continue;
-            }
-            sl.nb = n;
-            const double bw = (sl.t_last - sl.t_first) / n;
-            sl.inv_bw = 1.0 / bw;
-            int32_t i = sl.start;
-            for (int32_t b = 0; b < n; ++b) {
-                const double edge = sl.t_first + b * bw;
-                while (i < sl.end && times[i] < edge) ++i;
-                buckets.push_back(i);
-            }
-            buckets.push_back(sl.end);
-        }
-    }
+    bool all_zero = true;
+    const bool indexed = build_series_index(times, lcids, npt, nlc, &lcs, &buckets, &all_zero);
     se->indexed = indexed;
     hipError_t e = hipGetDevice(&se->device);
     if (e != hipSuccess) { delete se; return hip_fail(e, "hipGetDevice"); }

@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "rr.h"
+#include "rr_host.h"
 
 namespace rr {
 
@@ -103,16 +104,7 @@ struct SetupTable {
     SetupJob j[kMaxJobs];
 };
 
-// One light curve of a registered series whose exposures are the contiguous
-// run [start, end) of the arrays with non-decreasing times t_first ..
-// t_last.  Its index (nb + 1 entries at boff of the series' bucket array):
-// entry b < nb is the first exposure with t >= t_first + b * bw
-// (bw = (t_last - t_first)/nb, inv_bw = 1/bw, or 0 when all times are
-// equal), entry nb is end.
-struct SeriesLc {
-    int32_t start, end, boff, nb;
-    double t_first, t_last, inv_bw;
-};
+// SeriesLc (one light curve's run and time index) is in rr_host.h.
 // What the split forward launch (rr_evaluate_series) needs beyond a FwdJob:
 // the light curves' runs and index, and `shares` transit workgroups per
 // parameter vector (the first npv * shares workgroups of the launch).

@@ -84,44 +84,6 @@ struct Tick {
     std::vector<std::pair<Request*, int32_t>> parts;
 };
 
-// First-fit allocator over [0, size) with 256-byte granules.
-class Arena {
-  public:
-    void init(size_t size) { free_[0] = size; }
-    bool alloc(size_t bytes, size_t* off) {
-        bytes = (bytes + 255) / 256 * 256;
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second >= bytes) {
-                *off = it->first;
-                const size_t rest = it->second - bytes, o = it->first + bytes;
-                free_.erase(it);
-                if (rest) free_[o] = rest;
-                return true;
-            }
-        }
-        return false;
-    }
-    void release(size_t off, size_t bytes) {
-        bytes = (bytes + 255) / 256 * 256;
-        auto it = free_.emplace(off, bytes).first;
-        auto nx = std::next(it);
-        if (nx != free_.end() && it->first + it->second == nx->first) {
-            it->second += nx->second;
-            free_.erase(nx);
-        }
-        if (it != free_.begin()) {
-            auto pv = std::prev(it);
-            if (pv->first + pv->second == it->first) {
-                pv->second += it->second;
-                free_.erase(it);
-            }
-        }
-    }
-
-  private:
-    std::map<size_t, size_t> free_;
-};
-
 }  // namespace
 }  // namespace rr
 
@@ -236,35 +198,34 @@ bool rr_server::step() {
     SetupTable st;
     st.njobs = 0;
     int32_t nthreads = 0;
-    while (!pending.empty() && st.njobs < kMaxJobs) {
-        Request* r = pending.front();
-        size_t off = 0;
-        if (!arena.alloc(r->bytes, &off)) break;
-        pending.pop_front();
-        r->off = off;
-        char* base = arena_base + off;
-        const size_t pvb = (size_t(r->npv) * r->npar * 8 + 255) / 256 * 256;
-        const size_t pcb = (size_t(r->npv) * sizeof(PvConst) + 255) / 256 * 256;
-        r->pv_dev = reinterpret_cast<double*>(base);
-        r->pvc_dev = reinterpret_cast<PvConst*>(base + pvb);
-        r->out_dev = r->out_user ? r->out_user : base + pvb + pcb;
-        hipError_t e = hipMemcpyAsync(r->pv_dev, r->pv.data(), size_t(r->npv) * r->npar * 8,
-                                      hipMemcpyHostToDevice, setup_stream);
-        if (e != hipSuccess) r->err = RR_EDEVICE;
-        SetupJob& sj = st.j[st.njobs++];
-        sj.pv = r->pv_dev;
-        sj.pvc = r->pvc_dev;
-        sj.npv = r->npv;
-        sj.npar = r->npar;
-        sj.thread0 = nthreads;
-        nthreads += r->npv;
-        {
-            std::lock_guard<std::mutex> lk(mu);
-            r->state = kRunning;
-        }
-        active.push_back(r);
-        did = true;
-    }
+    const int nadm = admit_in_order(
+        pending, arena, kMaxJobs, [](Request* r) { return r->bytes; },
+        [&](Request* r, size_t off) {
+            r->off = off;
+            char* base = arena_base + off;
+            const size_t pvb = Arena::round(size_t(r->npv) * r->npar * 8);
+            const size_t pcb = Arena::round(size_t(r->npv) * sizeof(PvConst));
+            r->pv_dev = reinterpret_cast<double*>(base);
+            r->pvc_dev = reinterpret_cast<PvConst*>(base + pvb);
+            r->out_dev = r->out_user ? r->out_user : base + pvb + pcb;
+            hipError_t e = hipMemcpyAsync(r->pv_dev, r->pv.data(),
+                                          size_t(r->npv) * r->npar * 8,
+                                          hipMemcpyHostToDevice, setup_stream);
+            if (e != hipSuccess) r->err = RR_EDEVICE;
+            SetupJob& sj = st.j[st.njobs++];
+            sj.pv = r->pv_dev;
+            sj.pvc = r->pvc_dev;
+            sj.npv = r->npv;
+            sj.npar = r->npar;
+            sj.thread0 = nthreads;
+            nthreads += r->npv;
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                r->state = kRunning;
+            }
+            active.push_back(r);
+        });
+    if (nadm) did = true;
     if (st.njobs) {
         if (launch_pv_setup_jobs(t, st, nthreads, setup_stream) != hipSuccess ||
             hipEventRecord(setup_ev, setup_stream) != hipSuccess)
@@ -275,35 +236,27 @@ bool rr_server::step() {
                                 [](Request* r) { return r->next_row >= r->npv; }),
                  active.end());
     if (!active.empty() && ticks.size() < 2) {
-        int32_t left = max_tick_blocks;
+        std::vector<TickReq> want(active.size());
+        for (size_t i = 0; i < active.size(); ++i)
+            want[i] = TickReq{active[i]->npv - active[i]->next_row, active[i]->se.ntiles,
+                              active[i]->precision == RR_FP64 ? 0 : 1};
         JobTable jt[2];
         int32_t nb[2] = {0, 0};
         jt[0].njobs = jt[1].njobs = 0;
         Tick tk;
-        const int32_t share = std::max<int32_t>(1, max_tick_blocks / int32_t(active.size()));
-        for (int pass = 0; pass < 2 && left > 0; ++pass) {
-            for (Request* r : active) {
-                if (left <= 0) break;
-                const int p = r->precision == RR_FP64 ? 0 : 1;
-                if (jt[p].njobs >= kMaxJobs) continue;
-                const Series& se = r->se;
-                const int32_t remaining = r->npv - r->next_row;
-                if (remaining <= 0) continue;
-                const int32_t cap = pass == 0 ? std::min(share, left) : left;
-                int32_t rows = std::min(remaining, cap / se.ntiles);
-                if (rows == 0 && pass == 0 && tk.parts.empty()) rows = 1;   // one row > tick
-                if (rows == 0) continue;
-                FwdJob& j = jt[p].j[jt[p].njobs++];
-                j.times = se.times; j.lcids = se.lcids; j.lc = se.lc; j.pv = r->pv_dev;
-                j.pvc = r->pvc_dev; j.out = r->out_dev; j.npt = se.npt; j.npar = r->npar;
-                j.pv0 = r->next_row; j.npv = rows; j.ntiles = se.ntiles; j.block0 = nb[p];
-                j.max_nss = se.max_nss;
-                j.ldw_pv = nullptr; j.inv_istar_pv = nullptr; j.ldw_exact_k = 0; j.spread = 1;
-                nb[p] += rows * se.ntiles;
-                left -= rows * se.ntiles;
-                r->next_row += rows;
-                tk.parts.emplace_back(r, rows);
-            }
+        for (const TickPart& part : plan_tick(want, max_tick_blocks, kMaxJobs)) {
+            Request* r = active[size_t(part.req)];
+            const int p = want[size_t(part.req)].slot;
+            const Series& se = r->se;
+            FwdJob& j = jt[p].j[jt[p].njobs++];
+            j.times = se.times; j.lcids = se.lcids; j.lc = se.lc; j.pv = r->pv_dev;
+            j.pvc = r->pvc_dev; j.out = r->out_dev; j.npt = se.npt; j.npar = r->npar;
+            j.pv0 = r->next_row; j.npv = part.rows; j.ntiles = se.ntiles; j.block0 = nb[p];
+            j.max_nss = se.max_nss;
+            j.ldw_pv = nullptr; j.inv_istar_pv = nullptr; j.ldw_exact_k = 0; j.spread = 1;
+            nb[p] += part.rows * se.ntiles;
+            r->next_row += part.rows;
+            tk.parts.emplace_back(r, part.rows);
         }
         if (!tk.parts.empty()) {
             hipStream_t s = streams[tick_stream];
