@@ -203,15 +203,15 @@ RR_API void rr_series_free(rr_series* s);
  * rr_evaluate on the same times, computed with the same arithmetic per
  * exposure (the two kernels may round a multiply-add differently: within a
  * float ulp of the flux in RR_MIXED, a double ulp in RR_FP64).  With the
- * index, and when the problem is small enough for it to pay (npv x
- * ceil(npt / 512) at most 2.5 times the workgroups the device holds at
- * once), one launch sized to be resident all at once gives every parameter
- * vector a few workgroups that evaluate only its transits -- each finds a
- * transit's exposures through the index -- and streams F = 1 over every
- * other exposure with the remaining workgroups; larger problems, and series
- * without the index, take rr_evaluate's per-tile kernel.  pv_d, npv, npar,
- * precision, out_d, stream, errors and temporary memory as rr_evaluate; the
- * series must live on the tables' device. */
+ * index and one subsample per exposure, one launch gives every parameter
+ * vector up to 16 workgroups that evaluate only its transits -- each finds
+ * a transit's exposures through the index, and they start first -- while
+ * the other workgroups stream F = 1 over every other exposure; series
+ * without the index, supersampled series and the shortest series under
+ * more than 1024 vectors (two time tiles of 512 exposures or fewer) take
+ * rr_evaluate's per-tile kernel.  pv_d, npv, npar, precision, out_d,
+ * stream, errors and temporary memory as rr_evaluate; the series must live
+ * on the tables' device. */
 RR_API int rr_evaluate_series(const rr_tables* t, const rr_series* s, const double* pv_d,
                               int32_t npv, int32_t npar, int32_t precision, void* out_d,
                               hipStream_t stream);

@@ -145,45 +145,6 @@ __device__ inline R exposure_flux(const PvConst& p, const OrbitR<R>& orb, const 
     return R(1) - acc * R(inv_nss);
 }
 
-// The same three steps with the LD vector already interpolated in k and
-// staged in LDS (ng values of the row's passband): the transit workgroups
-// of the split launch read their row's from there instead of the table.
-template <typename R>
-__device__ inline R occulted_lds(R z, const PbConst<R>& c, const R* ldw, const GridDev& g) {
-    if (!(z < c.onepk)) return R(0);
-    const R v = z * c.inv1pk * R(g.gscale);
-    int m = int(v);
-    m = m > g.ng - 2 ? g.ng - 2 : m;
-    const R al = v - R(m);
-    const R ip = (R(1) - al) * ldw[m] + al * ldw[m + 1];
-    return ip * lens_area<R>(R(1), c.k, z) * c.istar_inv;
-}
-
-template <typename R>
-__device__ inline R subsample_delta_lds(const PvConst& p, const OrbitR<R>& orb,
-                                        const PbConst<R>& c, const R* ldw, double t, double ex,
-                                        double inv_nss, int s, const GridDev& g) {
-    const double x = (t + ex * ((s + 0.5) * inv_nss - 0.5)) - p.t0;
-    const double u = x * p.invP;
-    if (!in_phase_window(u, p, 0.0)) return R(0);
-    const double dt = x - p.P * rint(u);
-    bool front;
-    const R z = separation<R>(R(dt), orb, &front);
-    if (!front) return R(0);
-    return occulted_lds<R>(z, c, ldw, g);
-}
-
-template <typename R>
-__device__ inline R exposure_flux_lds(const PvConst& p, const OrbitR<R>& orb,
-                                      const PbConst<R>& c, const R* ldw, double t, double ex,
-                                      int nss, const GridDev& g) {
-    const double inv_nss = 1.0 / nss;
-    R acc = R(0);
-    for (int s = 0; s < nss; ++s)
-        acc += subsample_delta_lds<R>(p, orb, c, ldw, t, ex, inv_nss, s, g);
-    return R(1) - acc * R(inv_nss);
-}
-
 // The work of one workgroup: population row ipv, time tile `tile`.  Each
 // wave64 owns 64 J consecutive exposures of the tile and works
 // on its own, with no workgroup barrier: a wave whose exposures all lie
@@ -586,47 +547,33 @@ __device__ inline int owner_lane(int excl, int j) {
     return s;
 }
 
-// Transit role: share `share` of row ipv's in-window exposures, in two
-// phases per light curve.
-//  A. Candidates: 64 transits (epochs) at a time, one per lane, the lane
-//     turns its epoch's phase range [n, n + min(wn, 1)) into a time range
-//     and, through the light curve's index, into a run of candidate
-//     exposures (widened by a bucket on each side, so that it holds every
-//     exposure of the epoch); a scan across the wave concatenates the runs,
-//     and the row's shares take every shares-th chunk of 64 candidates, so
-//     each gets an equal part of the row's transits whatever their lengths.
-//     A candidate the window test puts in the epoch of its run is appended,
-//     with its time, to the workgroup's list in LDS (ballot compaction).
-//  B. Evaluation of the list (when it fills, and at the end of the light
-//     curve): two exposures per lane as independent chains (nss = 1), 64 /
-//     nss exposures with one subsample per lane (nss <= 32), or one exposure
-//     per lane; the LD vector of the light curve's passband, interpolated in
-//     k, is staged in LDS first.
-constexpr int kTransitList = 256;    // list entries in LDS
-
+// Transit role: share `share` of row ipv's transit exposures.  Per light
+// curve, 64 transits (epochs) at a time, one per lane: the lane turns its
+// epoch's phase range [n, n + min(wn, 1)) into a time range and, through the
+// light curve's index, into a run of candidate exposures (widened by a
+// bucket on each side, so that it holds every exposure of the epoch); a
+// scan across the wave concatenates the runs, and the row's shares take
+// every shares-th chunk of 64 candidates, so each gets an equal part of the
+// row's transits whatever their lengths.  A candidate is evaluated where it
+// stands: one outside the window comes out as exactly 1 (each of its
+// subsamples fails the window test), the value the streaming workgroups
+// store there, and an exposure two runs share is written twice with the
+// same bits; so nothing is compacted or staged.  One subsample per
+// exposure (the launch serves such series only); two candidates per lane as
+// independent chains.
 template <typename R>
-__host__ __device__ inline size_t transit_lds_bytes(int ng) {
-    return (size_t(ng) * sizeof(R) + 7) / 8 * 8 + size_t(kTransitList) * (8 + 4);
-}
-
-template <typename R, bool kSubPar>
 __device__ inline void transit_share(const FwdJob& job, const LcInfo& lc, const SplitInfo& si,
                                      int ipv, int share, const GridDev& g,
                                      const R* __restrict__ T,
-                                     const double* __restrict__ inv_istar, char* lds) {
+                                     const double* __restrict__ inv_istar) {
     const int lane = threadIdx.x & 63;
     const PvConst p = job.pvc[ipv];
     if (!(p.flags & kValid)) return;
-    R* ldw = reinterpret_cast<R*>(lds);
-    double* lst_t = reinterpret_cast<double*>(lds + (size_t(g.ng) * sizeof(R) + 7) / 8 * 8);
-    int* lst_i = reinterpret_cast<int*>(lst_t + kTransitList);
     const double* __restrict__ times = job.times;
     R* __restrict__ orow = static_cast<R*>(job.out) + int64_t(ipv) * job.npt;
     const OrbitR<R> orb(p);
     const int E = si.shares;
-    const uint64_t below = __lanemask_lt();
     int64_t chunk0 = 0;              // candidate chunks dealt so far for this row
-    int pb_staged = -1;
     for (int l = 0; l < lc.nlc; ++l) {
         const SeriesLc sl = si.lcs[l];
         if (sl.end <= sl.start) continue;
@@ -635,139 +582,61 @@ __device__ inline void transit_share(const FwdJob& job, const LcInfo& lc, const 
         const double span = w.wn < 1.0 ? w.wn : 1.0;
         const double n_first = floor(win_phase(sl.t_first, p.invP, w));
         const double n_last = floor(win_phase(sl.t_last, p.invP, w));
-        const int pb = lc.pb[l];
-        const PbConst<R> c = pb_const<R>(job.pv, ipv, job.npar, pb, g, T, inv_istar, job);
-        const int N = kSubPar ? lc.nss[l] : 1;
-        int nlist = 0;
-
-        // Phase B over the current list.
-        auto flush = [&]() {
-            if (nlist == 0) return;
-            if (pb != pb_staged) {
-                // the k-interpolated LD vector of passband pb (the
-                // k-interpolation of occulted_at, once per node)
-                __builtin_amdgcn_wave_barrier();
-                for (int m = lane; m < g.ng; m += 64)
-                    ldw[m] = (R(1) - c.ak) * c.t0r[m] + c.ak * c.t0r[g.ng + m];
-                pb_staged = pb;
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            if (N == 1) {
-                for (int j0 = 0; j0 < nlist; j0 += 128) {
-                    const int ja = j0 + lane, jb = j0 + 64 + lane;
-                    R da = R(0), db = R(0);
-                    if (ja < nlist)
-                        da = subsample_delta_lds<R>(p, orb, c, ldw, lst_t[ja], ex, 1.0, 0, g);
-                    if (jb < nlist)
-                        db = subsample_delta_lds<R>(p, orb, c, ldw, lst_t[jb], ex, 1.0, 0, g);
-                    if (ja < nlist) orow[lst_i[ja]] = R(1) - da;
-                    if (jb < nlist) orow[lst_i[jb]] = R(1) - db;
-                }
-            } else if (N <= 32) {
-                // one subsample per lane, each group's terms summed by its
-                // first lane in subsample order
-                const int G = 64 / N;
-                const int gi = lane / N, sub = lane - gi * N;
-                const double inv_nss = 1.0 / N;
-                for (int j0 = 0; j0 < nlist; j0 += G) {
-                    const int j = j0 + gi;
-                    const bool have = gi < G && j < nlist;
-                    R val = R(0);
-                    if (have)
-                        val = subsample_delta_lds<R>(p, orb, c, ldw, lst_t[j], ex, inv_nss, sub,
-                                                     g);
-                    R acc = R(0);
-                    const int src0 = gi < G ? gi * N : 0;
-                    for (int k = 0; k < N; ++k) acc += __shfl(val, src0 + k);
-                    if (have && sub == 0) orow[lst_i[j]] = R(1) - acc * R(inv_nss);
-                }
-            } else {
-                for (int j0 = 0; j0 < nlist; j0 += 64) {
-                    const int j = j0 + lane;
-                    if (j < nlist)
-                        orow[lst_i[j]] = exposure_flux_lds<R>(p, orb, c, ldw, lst_t[j], ex, N, g);
-                }
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            nlist = 0;
-        };
-        // Append the lane's exposure `it` at time t (if it >= 0).
-        auto append = [&](int it, double t) {
-            const uint64_t m = __ballot(it >= 0);
-            if (it >= 0) {
-                const int pos = nlist + __popcll(m & below);
-                lst_i[pos] = it;
-                lst_t[pos] = t;
-            }
-            nlist += __popcll(m);
-            if (nlist > kTransitList - 64) flush();
-        };
-
-        if (n_last - n_first >= double(sl.end - sl.start) || !(fabs(n_first) < 1e15) ||
-            !(fabs(n_last) < 1e15)) {
-            // more transits than exposures (a period shorter than the
-            // cadence), or epoch numbers too large to step through exactly:
-            // every exposure of the light curve is a candidate
-            const int n = sl.end - sl.start;
-            const int64_t nchunks = (n + 63) / 64;
-            for (int64_t q = (share - chunk0 % E + E) % E; q < nchunks; q += E) {
-                const int it = sl.start + int(q) * 64 + lane;
-                double t = 0.0;
-                bool in = false;
-                if (it < sl.end) {
-                    t = times[it];
-                    in = win_in(win_phase(t, p.invP, w), w);
-                }
-                append(in ? it : -1, t);
-            }
-            chunk0 += nchunks;
-            flush();
-            continue;
-        }
+        // more transits than exposures (a period shorter than the cadence),
+        // or epoch numbers too large to step through exactly: every
+        // exposure of the light curve is a candidate, in one batch
+        const bool dense = n_last - n_first >= double(sl.end - sl.start) ||
+                           !(fabs(n_first) < 1e15) || !(fabs(n_last) < 1e15);
+        const PbConst<R> c = pb_const<R>(job.pv, ipv, job.npar, lc.pb[l], g, T, inv_istar, job);
         const int32_t* __restrict__ bk = si.buckets + sl.boff;
-        for (double nb0 = n_first; nb0 <= n_last; nb0 += 64.0) {
-            const double n = nb0 + double(lane);
-            int i0 = 0, cnt = 0;
-            if (n <= n_last) {
-                const double ta = (n - w.c0) * p.P;
-                const double tb = (n + span - w.c0) * p.P;
-                const double fa = floor((ta - sl.t_first) * sl.inv_bw) - 1.0;
-                const double fb = floor((tb - sl.t_first) * sl.inv_bw) + 2.0;
-                const int bl = !(fa > 0.0) ? 0 : (fa > double(sl.nb) ? sl.nb : int(fa));
-                const int bh = !(fb > 0.0) ? 0 : (fb > double(sl.nb) ? sl.nb : int(fb));
-                i0 = bk[bl];
-                cnt = bk[bh] - i0;
-            }
-            int incl = cnt;
-#pragma unroll
-            for (int off = 1; off < 64; off <<= 1) {
-                const int x = __shfl_up(incl, off);
-                if (lane >= off) incl += x;
-            }
-            const int total = __shfl(incl, 63);
-            const int excl = incl - cnt;
-            if (total == 0) continue;
-            const int64_t nchunks = (total + 63) / 64;
-            for (int64_t q = (share - chunk0 % E + E) % E; q < nchunks; q += E) {
-                const int j = int(q) * 64 + lane;
-                const int s = owner_lane(excl, j);
-                const int it = __shfl(i0, s) + (j - __shfl(excl, s));
-                double t = 0.0;
-                bool in = false;
-                if (j < total) {
-                    t = times[it];
-                    const double gph = win_phase(t, p.invP, w);
-                    in = floor(gph) == nb0 + double(s) && gph - floor(gph) < w.wn;
+        for (double nb0 = n_first; dense || nb0 <= n_last; nb0 += 64.0) {
+            int i0 = sl.start, excl = 0, total = sl.end - sl.start;
+            if (!dense) {
+                const double n = nb0 + double(lane);
+                int cnt = 0;
+                i0 = 0;
+                if (n <= n_last) {
+                    const double ta = (n - w.c0) * p.P;
+                    const double tb = (n + span - w.c0) * p.P;
+                    const double fa = floor((ta - sl.t_first) * sl.inv_bw) - 1.0;
+                    const double fb = floor((tb - sl.t_first) * sl.inv_bw) + 2.0;
+                    const int bl = !(fa > 0.0) ? 0 : (fa > double(sl.nb) ? sl.nb : int(fa));
+                    const int bh = !(fb > 0.0) ? 0 : (fb > double(sl.nb) ? sl.nb : int(fb));
+                    i0 = bk[bl];
+                    cnt = bk[bh] - i0;
                 }
-                append(in ? it : -1, t);
+                int incl = cnt;
+#pragma unroll
+                for (int off = 1; off < 64; off <<= 1) {
+                    const int x = __shfl_up(incl, off);
+                    if (lane >= off) incl += x;
+                }
+                total = __shfl(incl, 63);
+                excl = incl - cnt;
             }
+            const int64_t nchunks = (int64_t(total) + 63) / 64;
+            const int64_t q0 = (share - chunk0 % E + E) % E;
             chunk0 += nchunks;
+            // exposure of flat candidate position q * 64 + lane (-1 past the
+            // end); every lane takes part in the shuffles
+            auto cand = [&](int64_t q) -> int {
+                const int j = int(q) * 64 + lane;
+                if (dense) return j < total ? sl.start + j : -1;
+                const int src = owner_lane(excl, j);
+                const int it = __shfl(i0, src) + (j - __shfl(excl, src));
+                return j < total ? it : -1;
+            };
+            for (int64_t q = q0; q < nchunks; q += 2 * int64_t(E)) {
+                const int ia = cand(q);
+                const int ib = q + E < nchunks ? cand(q + E) : -1;
+                R da = R(0), db = R(0);
+                if (ia >= 0) da = subsample_delta<R>(p, orb, c, times[ia], ex, 1.0, 0, g);
+                if (ib >= 0) db = subsample_delta<R>(p, orb, c, times[ib], ex, 1.0, 0, g);
+                if (ia >= 0) orow[ia] = R(1) - da;
+                if (ib >= 0) orow[ib] = R(1) - db;
+            }
+            if (dense) break;
         }
-        flush();
     }
 }
 
@@ -776,18 +645,16 @@ __device__ inline void transit_share(const FwdJob& job, const LcInfo& lc, const 
 // of rows (tile u % ntiles of rows [rows_per u / ntiles, ...)).  The launch
 // is sized to be resident all at once, so the transit work runs beside the
 // streaming stores from the start instead of forming a tail.
-template <typename R, bool kSubPar>
+template <typename R>
 __global__ __launch_bounds__(kFwdBlock) void k_forward_split(FwdJob job, LcInfo lc, GridDev g,
                                                           const R* __restrict__ T,
                                                           const double* __restrict__ inv_istar,
                                                           SplitInfo si) {
-    extern __shared__ __align__(16) char split_lds[];
     const int b = int(blockIdx.x);
     const int n2 = job.npv * si.shares;
     if (b < n2) {
         const int ipv = b / si.shares;
-        transit_share<R, kSubPar>(job, lc, si, ipv, b - ipv * si.shares, g, T, inv_istar,
-                                  split_lds);
+        transit_share<R>(job, lc, si, ipv, b - ipv * si.shares, g, T, inv_istar);
         return;
     }
     const int u = b - n2;
@@ -937,14 +804,14 @@ hipError_t launch_forward(const rr_tables* t, const double* times,
     return hipGetLastError();
 }
 
-// Workgroups of the split kernel (one wave each, `lds` bytes of dynamic
-// LDS) resident at once on the current device; 0 if the query fails.
-static int split_capacity(int32_t precision, bool sub, size_t lds) {
+// Workgroups of the split kernel (one wave each) resident at once on the
+// current device; 0 if the query fails.
+static int split_capacity(int32_t precision) {
     static std::mutex mu;
-    static std::map<std::tuple<int, int, int, size_t>, int> cache;
+    static std::map<std::tuple<int, int>, int> cache;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
-    const auto key = std::make_tuple(dev, precision == RR_FP64 ? 0 : 1, sub ? 1 : 0, lds);
+    const auto key = std::make_tuple(dev, precision == RR_FP64 ? 0 : 1);
     std::lock_guard<std::mutex> lk(mu);
     auto it = cache.find(key);
     if (it != cache.end()) return it->second;
@@ -953,24 +820,22 @@ static int split_capacity(int32_t precision, bool sub, size_t lds) {
         return 0;
     hipError_t e;
     if (precision == RR_FP64)
-        e = sub ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_forward_split<double, true>, kFwdBlock, lds)
-                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_forward_split<double, false>, kFwdBlock, lds);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_forward_split<double>, kFwdBlock, 0);
     else
-        e = sub ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_forward_split<float, true>, kFwdBlock, lds)
-                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_forward_split<float, false>, kFwdBlock, lds);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_forward_split<float>, kFwdBlock, 0);
     if (e != hipSuccess || per_cu <= 0) return 0;
     cache[key] = per_cu * ncu;
     return per_cu * ncu;
 }
 
 bool split_preferred(const rr_tables* t, const rr_series* se, int32_t npv, int32_t precision) {
-    const bool sub = se->max_nss > 1;
-    const size_t lds = precision == RR_FP64 ? transit_lds_bytes<double>(t->grid.ng)
-                                            : transit_lds_bytes<float>(t->grid.ng);
-    const int cap = split_capacity(precision, sub, lds);
-    if (cap <= 0) return false;
-    const int64_t tiles = int64_t(npv) * ((int64_t(se->npt) + kFwdTile - 1) / kFwdTile);
-    return 2 * tiles <= 5 * int64_t(cap);
+    (void)t;
+    // Measured: the split launch wins on series with one subsample per
+    // exposure except the shortest (two time tiles or fewer) under more than
+    // 1024 rows; the per-tile kernel stays ahead on supersampled series.
+    const int64_t ntiles = (int64_t(se->npt) + kFwdTile - 1) / kFwdTile;
+    if (se->max_nss != 1 || (ntiles <= 2 && npv > 1024)) return false;
+    return split_capacity(precision) > 0;
 }
 
 hipError_t launch_forward_split(const rr_tables* t, const rr_series* se, const double* pv,
@@ -981,45 +846,39 @@ hipError_t launch_forward_split(const rr_tables* t, const rr_series* se, const d
     job.times = se->times; job.lcids = se->lcids; job.pv = pv; job.pvc = pvc; job.out = out;
     job.npt = se->npt; job.npar = npar; job.pv0 = 0; job.npv = npv;
     job.ntiles = (se->npt + kFwdTile - 1) / kFwdTile; job.max_nss = se->max_nss; job.spread = 1;
-    const bool sub = se->max_nss > 1;
-    const size_t lds = precision == RR_FP64 ? transit_lds_bytes<double>(g.ng)
-                                            : transit_lds_bytes<float>(g.ng);
-    int cap = split_capacity(precision, sub, lds);
+    if (se->max_nss != 1) return hipErrorInvalidValue;    // see split_preferred
+    int cap = split_capacity(precision);
     if (cap <= 0) cap = 2048;
-    // About half the resident workgroups take the transits (at most one per
-    // 64 exposures of a row), the other half stream; the streaming
-    // workgroups take as many rows each as keeps them within that half.
+    // The transit workgroups (at most 16 per row, one per 64 exposures of a
+    // row) start first; the streaming workgroups, kSplitRows rows of one
+    // time tile each (2 for small problems, so that there are enough of
+    // them), take the slots as transit workgroups finish.  Measured on the
+    // population workloads (16 to 4096 rows, 1000 to 50 000 times): as many
+    // transit workgroups as are resident at once for 512 rows or more over
+    // 16 tiles or more, else at most 2048 -- fewer leave too much serial
+    // work per lane, more queue behind each other or spend their time on
+    // set-up.
     SplitInfo si;
     si.lcs = se->lcs;
     si.buckets = se->buckets;
-    const int64_t half = std::max<int64_t>(1, cap / 2);
     const int64_t max_sh = std::max<int64_t>(1, (int64_t(se->npt) + 63) / 64);
-    si.shares = int32_t(std::min<int64_t>({64, max_sh, std::max<int64_t>(1, half / npv)}));
-    const int64_t want_st = std::max<int64_t>({int64_t(job.ntiles), half,
-                                               cap - int64_t(npv) * si.shares});
-    const int64_t groups = std::max<int64_t>(1, std::min<int64_t>(npv, want_st / job.ntiles));
-    si.rows_per = int32_t((npv + groups - 1) / groups);
+    const int64_t n_transit =
+        npv >= 512 && job.ntiles >= 16 ? int64_t(cap) : std::min<int64_t>(cap, 2048);
+    si.shares = int32_t(std::min<int64_t>({16, max_sh, std::max<int64_t>(1, n_transit / npv)}));
+    const int64_t tiles_total = int64_t(job.ntiles) * npv;
+    si.rows_per = std::min<int32_t>(tiles_total < 2 * int64_t(cap) ? 2 : kSplitRows, npv);
     const int64_t n_tr = int64_t(npv) * si.shares;
     const int64_t n_st = int64_t(job.ntiles) * ((npv + si.rows_per - 1) / si.rows_per);
     if (n_tr + n_st >= (int64_t(1) << 31)) return hipErrorInvalidValue;
     const dim3 grid{unsigned(n_tr + n_st), 1u, 1u};
     const dim3 block{unsigned(kFwdBlock), 1u, 1u};
     const KernelEvents ev = kernel_events();
-    if (precision == RR_FP64) {
-        if (sub)
-            launch_timed(k_forward_split<double, true>, grid, block, lds, s, ev.before, ev.after,
-                         job, se->lc, g, t->T64, t->inv_istar, si);
-        else
-            launch_timed(k_forward_split<double, false>, grid, block, lds, s, ev.before, ev.after,
-                         job, se->lc, g, t->T64, t->inv_istar, si);
-    } else {
-        if (sub)
-            launch_timed(k_forward_split<float, true>, grid, block, lds, s, ev.before, ev.after,
-                         job, se->lc, g, t->T32, t->inv_istar, si);
-        else
-            launch_timed(k_forward_split<float, false>, grid, block, lds, s, ev.before, ev.after,
-                         job, se->lc, g, t->T32, t->inv_istar, si);
-    }
+    if (precision == RR_FP64)
+        launch_timed(k_forward_split<double>, grid, block, 0, s, ev.before, ev.after, job, se->lc,
+                     g, t->T64, t->inv_istar, si);
+    else
+        launch_timed(k_forward_split<float>, grid, block, 0, s, ev.before, ev.after, job, se->lc,
+                     g, t->T32, t->inv_istar, si);
     return hipGetLastError();
 }
 

@@ -28,6 +28,7 @@ constexpr int kTimesPerThread = RR_TIMES_PER_THREAD;   // times per thread
 // a finished wave frees its slot at once), each owning kFwdTile times.
 constexpr int kFwdBlock = 64;
 constexpr int kFwdTile = kFwdBlock * kTimesPerThread;
+constexpr int kSplitRows = 4;       // rows per streaming workgroup of the split launch
 // Log-likelihood kernel: two wave64 per workgroup share the LDS tables.
 // Times per thread: 16, except 8 with the LD-profile gradient in mixed
 // precision (measured fastest for each).

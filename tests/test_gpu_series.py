@@ -7,8 +7,9 @@ cover what the split launch depends on: the transit workgroups' index of
 each light curve (uniform cadence, gaps, repeated times, an empty light
 curve, several light curves), periods shorter than the cadence and windows
 covering whole orbits, ragged and misaligned row lengths, invalid rows,
-absolute (BJD-like) times, and series the index does not apply to (unsorted
-times, a light curve split into two runs), which take the per-tile kernel.
+absolute (BJD-like) times, and series the split launch does not serve
+(unsorted times, a light curve split into two runs, supersampled light
+curves), which take the per-tile kernel.
 """
 
 import numpy as np
@@ -132,10 +133,14 @@ def test_gaps_repeats_and_an_empty_light_curve(rr):
     w = dict(base)
     w["times"], w["lcids"] = times, lcids
     w["pbids"] = np.zeros(3, np.int32)                       # light curve 1 is empty
-    w["nss"] = np.array([1, 1, 3], np.int32)
+    w["nss"] = np.array([1, 1, 1], np.int32)
     w["exptimes"] = np.array([2.0, 2.0, 30.0]) / 1440.0
     w["name"] = "gaps"
     _ = rng
+    run_case(rr, w)
+    # the same with the last light curve supersampled (the per-tile kernel)
+    w["nss"] = np.array([1, 1, 3], np.int32)
+    w["name"] = "gaps supersampled"
     run_case(rr, w)
 
 
