@@ -776,14 +776,18 @@ def main():
 
     m = summary("mixed", 4)
     d = summary("fp64", 8)
+    # the forward kernel the library launches on this series (rr_series_kernel)
+    kname = {p: ("k_forward_split<%s>" % t if series.kernel(tab, npv, p) == "split"
+                 else "k_forward<%s, false, 8>" % t)
+             for p, t in (("mixed", "float"), ("fp64", "double"))}
     achieved = m["alg_bytes"] / (m["kernel_ms"]["mean"] / 1e3) / 1e9
-    kc = profile_counters("k_forward<float, false, 8>")
+    kc = profile_counters(kname["mixed"])
     traffic = kc.get("hbm_bytes_per_launch") if kc else None
     roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=achieved / HBM_PEAK_GBS, traffic=traffic,
-                kernel="k_forward<float, false, 8>", alg_bytes_per_launch=m["alg_bytes"],
+                kernel=kname["mixed"], alg_bytes_per_launch=m["alg_bytes"],
                 kernel_ms=m["kernel_ms"]["mean"],
-                valu=valu_view("k_forward<float, false, 8>", m["kernel_ms"]["mean"]))
+                valu=valu_view(kname["mixed"], m["kernel_ms"]["mean"]))
     achieved64 = d["alg_bytes"] / (d["kernel_ms"]["mean"] / 1e3) / 1e9
 
     line = dict(
@@ -799,8 +803,9 @@ def main():
                   dtype="f64", roofline=dict(bound="hbm", achieved=achieved64,
                                              peak=HBM_PEAK_GBS, unit="GB/s",
                                              frac=achieved64 / HBM_PEAK_GBS,
+                                             kernel=kname["fp64"],
                                              kernel_ms=d["kernel_ms"]["mean"],
-                                             valu=valu_view("k_forward<double, false, 8>",
+                                             valu=valu_view(kname["fp64"],
                                                             d["kernel_ms"]["mean"]))),
         roofline=roof,
         in_transit_fraction=None,

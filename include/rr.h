@@ -216,6 +216,17 @@ RR_API int rr_evaluate_series(const rr_tables* t, const rr_series* s, const doub
                               int32_t npv, int32_t npar, int32_t precision, void* out_d,
                               hipStream_t stream);
 
+/* Which forward kernel rr_evaluate_series launches for npv parameter
+ * vectors in `precision` over this series: *kind = RR_KERNEL_TILES (0:
+ * rr_evaluate's per-tile kernel) or RR_KERNEL_SPLIT (1: the split launch of
+ * transit and streaming workgroups).  For benchmarks and profiles that name
+ * the kernel they time.  Enqueues nothing (the choice may query the
+ * device's occupancy once); errors as rr_evaluate_series's checks. */
+#define RR_KERNEL_TILES 0
+#define RR_KERNEL_SPLIT 1
+RR_API int rr_series_kernel(const rr_tables* t, const rr_series* s, int32_t npv,
+                            int32_t precision, int32_t* kind);
+
 /* rr_evaluate for callers that cannot allocate device memory: code under
  * HIP graph capture, tight serving loops, and harnesses that forbid
  * hipMalloc.  Same arguments, kernels, results and argument errors as

@@ -14,6 +14,7 @@ RR_OK, RR_EINVAL, RR_ENOMEM, RR_EDEVICE, RR_ELIMIT, RR_EBUSY, RR_ENOTFOUND = 0, 
 RR_FP64, RR_MIXED = 0, 1
 RR_MAX_PB, RR_MAX_LC, RR_MAX_NSS = 16, 64, 1024
 RR_NOALLOC_MAX_PV = 16384
+RR_KERNEL_TILES, RR_KERNEL_SPLIT = 0, 1
 
 c_double_p = ctypes.POINTER(ctypes.c_double)
 c_int32_p = ctypes.POINTER(ctypes.c_int32)
@@ -78,6 +79,8 @@ def _declare(L):
     L.rr_evaluate_series.argtypes = [c_void_p, c_void_p, c_void_p, i32, i32, i32, c_void_p,
                                      c_void_p]
     L.rr_evaluate_series.restype = ctypes.c_int
+    L.rr_series_kernel.argtypes = [c_void_p, c_void_p, i32, i32, c_int32_p]
+    L.rr_series_kernel.restype = ctypes.c_int
     L.rr_evaluate_ld.argtypes = [c_void_p, c_void_p, c_void_p, i32, c_void_p, c_void_p,
                                  c_void_p, i32, c_void_p, i32, i32, c_void_p, i32, c_void_p,
                                  c_void_p]

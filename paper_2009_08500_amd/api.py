@@ -177,6 +177,15 @@ class TimeSeries:
             raise ValueError("series already freed")
         return self._series
 
+    def kernel(self, tables, npv, precision="mixed"):
+        """The forward kernel ``evaluate`` launches on this series for npv
+        rows (rr_series_kernel): "split" or "tiles"."""
+        k = ctypes.c_int32(-1)
+        check(_lib.lib().rr_series_kernel(tables.handle, self.handle, int(npv),
+                                          PRECISIONS[precision], ctypes.byref(k)),
+              "rr_series_kernel")
+        return "split" if k.value == _lib.RR_KERNEL_SPLIT else "tiles"
+
     def lc_args(self):
         lc = ctypes.c_void_p(self.lcids.data_ptr()) if self.lcids is not None else None
         return (lc, self.npt, _ptr(self.pbids), _ptr(self.nss), _ptr(self.exptimes), self.nlc)

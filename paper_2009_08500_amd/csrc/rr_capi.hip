@@ -457,6 +457,20 @@ RR_API int rr_evaluate_series(const rr_tables* t, const rr_series* se, const dou
     return RR_OK;
 }
 
+RR_API int rr_series_kernel(const rr_tables* t, const rr_series* se, int32_t npv,
+                            int32_t precision, int32_t* kind) {
+    if (!kind) return einval("kind is NULL");
+    *kind = RR_KERNEL_TILES;
+    if (!t) return einval("tables handle is NULL");
+    if (!se) return einval("series is NULL");
+    if (npv < 0) return einval("npv must be >= 0");
+    if (precision != RR_FP64 && precision != RR_MIXED) return einval("unknown precision");
+    int rc = check_device(t);
+    if (rc) return rc;
+    if (se->indexed && split_preferred(t, se, npv, precision)) *kind = RR_KERNEL_SPLIT;
+    return RR_OK;
+}
+
 RR_API int rr_evaluate_variant(const rr_tables* t, const double* times_d,
                                const int32_t* lcids_d, int32_t npt,
                                const int32_t* pbids, const int32_t* nss,

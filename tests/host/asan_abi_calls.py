@@ -145,6 +145,7 @@ def main(lib_path, lib_py):
         ("noalloc", lambda: L.rr_evaluate_noalloc(None, None, None, 0, p1, p1, pz, 1, None, 0,
                                                   7, 0, None, None)),
         ("series", lambda: L.rr_evaluate_series(None, None, None, 0, 7, 0, None, None)),
+        ("series kernel", lambda: L.rr_series_kernel(None, None, 1, 0, None)),
         ("ld", lambda: L.rr_evaluate_ld(None, None, None, 0, p1, p1, pz, 1, None, 0, 7, None,
                                         0, None, None)),
         ("direct", lambda: L.rr_evaluate_direct(None, None, None, 0, p1, p1, pz, 1, None, 0, 7,

@@ -198,3 +198,31 @@ def test_deterministic_and_errors(rr):
                               _lib.RR_MIXED, ctypes.c_void_p(out.data_ptr()), None)
     assert rc == _lib.RR_OK
     tab.close()
+
+
+def test_kernel_query(rr):
+    """rr_series_kernel names the launch the documented rule picks: the split
+    launch for an indexed series with one subsample per exposure, the
+    per-tile kernel for supersampled, unindexed and the shortest series
+    under more than 1024 rows; the two give the same fluxes either way."""
+    w = wl.population(npv=8, npt=3000, seed_extra=32)
+    tab = rr.Tables(w["mu_s"], w["I_s"], wl.TEST_GRID)
+    ser = rr.TimeSeries(w["times"])
+    for prec in ("mixed", "fp64"):
+        assert ser.kernel(tab, 8, prec) == "split"
+        assert ser.kernel(tab, 4096, prec) == "split"         # 6 tiles of 512
+    short = rr.TimeSeries(w["times"][:1000])
+    assert short.kernel(tab, 1024, "mixed") == "split"
+    assert short.kernel(tab, 1025, "mixed") == "tiles"
+    sup = rr.TimeSeries(w["times"], nss=[3], exptimes=[0.02])
+    assert sup.kernel(tab, 8, "mixed") == "tiles"
+    unsorted = rr.TimeSeries(w["times"][::-1].copy())
+    assert unsorted.kernel(tab, 8, "mixed") == "tiles"
+    import ctypes
+    from paper_2009_08500_amd import _lib
+    k = ctypes.c_int32(7)
+    assert _lib.lib().rr_series_kernel(tab.handle, ser.handle, 1, 5, ctypes.byref(k)) == \
+        _lib.RR_EINVAL
+    for s_ in (ser, short, sup, unsorted):
+        s_.close()
+    tab.close()
