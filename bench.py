@@ -97,11 +97,15 @@ def valu_view(kernel, kernel_ms):
 
 
 def time_path(rr, tab, series, pv, prec, steps, warmup, lib):
-    """Throughput: `steps` back-to-back calls between two synchronisations
-    (no per-step instrumentation).  Then the same number of calls again with
-    HIP events around each call, for latency percentiles, and, through
+    """Throughput: `steps` back-to-back evaluations between two
+    synchronisations (no per-step instrumentation), first as eager calls
+    from Python, then as replays of one call captured in a HIP graph
+    (Evaluator.capture: the same setup and forward kernels, without the
+    host's per-call launch work).  Then the same number of eager calls again
+    with HIP events around each call, for latency percentiles, and, through
     rr_set_kernel_events, as the forward kernel launch's own start and stop
-    events, for the kernel time."""
+    events, for the kernel time.  Returns (eager wall, graph wall, step ms,
+    kernel ms, output)."""
     import torch
     ev_fn = rr.Evaluator(tab, series, pv.shape[0], prec)
     for _ in range(warmup):
@@ -111,7 +115,19 @@ def time_path(rr, tab, series, pv, prec, steps, warmup, lib):
     for _ in range(steps):
         ev_fn(pv)
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    wall_eager = time.perf_counter() - t0
+    ev_g = rr.Evaluator(tab, series, pv.shape[0], prec)
+    ev_g.capture(pv)
+    for _ in range(warmup):
+        ev_g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ev_g.replay()
+    torch.cuda.synchronize()
+    wall_graph = time.perf_counter() - t0
+    if not torch.equal(ev_g.out, ev_fn.out):
+        raise RuntimeError("graph replay and eager call disagree")
     step_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                for _ in range(steps)]
     kern_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
@@ -129,7 +145,7 @@ def time_path(rr, tab, series, pv, prec, steps, warmup, lib):
     lib.rr_set_kernel_events(None, None)
     step_ms = [a.elapsed_time(b) for a, b in step_ev]
     kern_ms = [a.elapsed_time(b) for a, b in kern_ev]
-    return wall, step_ms, kern_ms, ev_fn.out
+    return wall_eager, wall_graph, step_ms, kern_ms, ev_fn.out
 
 
 def pct(x, q):
@@ -237,9 +253,11 @@ def heterogeneous_leg(rr, wl, steps, warmup, lib):
                subsamples_per_call=subs)
     outs = {}
     for prec in ("mixed", "fp64"):
-        wall, step_ms, kern_ms, out = time_path(rr, tab, ser, pv, prec, steps, warmup, lib)
+        wall, wall_graph, step_ms, kern_ms, out = time_path(rr, tab, ser, pv, prec, steps,
+                                                            warmup, lib)
         ms = 1e3 * wall / steps
         res[prec] = dict(subsamples_per_s=subs / (ms / 1e3), ms_per_step=ms,
+                         graph_replay_ms_per_step=1e3 * wall_graph / steps,
                          kernel_ms=float(np.mean(kern_ms)),
                          latency_ms=dict(p50=pct(step_ms, 50), p99=pct(step_ms, 99)))
         outs[prec] = out.cpu().numpy().astype(np.float64)
@@ -757,9 +775,9 @@ def main():
     res = {}
     outs = {}
     for prec in ("mixed", "fp64"):
-        wall, step_ms, kern_ms, out = time_path(rr, tab, series, pv, prec,
-                                                args.steps, args.warmup, lib)
-        res[prec] = dict(wall=wall, step_ms=step_ms, kern_ms=kern_ms)
+        wall, wall_graph, step_ms, kern_ms, out = time_path(rr, tab, series, pv, prec,
+                                                            args.steps, args.warmup, lib)
+        res[prec] = dict(wall=wall, wall_graph=wall_graph, step_ms=step_ms, kern_ms=kern_ms)
         outs[prec] = out
     out32, out64 = outs["mixed"], outs["fp64"]
     points = npv * npt * nss
@@ -769,7 +787,9 @@ def main():
         ms = 1e3 * r["wall"] / args.steps
         kern = float(np.mean(r["kern_ms"]))
         traffic_alg = npv * npt * out_bytes + npt * 8 + npv * (8 * pv.shape[1] + PVCONST_BYTES)
+        ms_graph = 1e3 * r["wall_graph"] / args.steps
         return dict(value=points / (ms / 1e3), ms_per_step=ms,
+                    graph_replay=dict(value=points / (ms_graph / 1e3), ms_per_step=ms_graph),
                     latency_ms=dict(p50=pct(r["step_ms"], 50), p99=pct(r["step_ms"], 99)),
                     kernel_ms=dict(mean=kern, p50=pct(r["kern_ms"], 50), p99=pct(r["kern_ms"], 99)),
                     alg_bytes=traffic_alg)
@@ -797,9 +817,14 @@ def main():
         config=dict(workload=f"population evaluation npv={npv} npt={npt} nss={nss}, "
                              "2-min cadence, power-2 LD tabulated at 200 mu",
                     npv=npv, npt=npt, nss=nss, precision="mixed (FP64 time reduction, FP32 bulk)",
-                    grid=grid),
+                    grid=grid,
+                    launch="one rr_evaluate_series call per step from Python (setup kernel + "
+                           "forward kernel); 'graph_replay' = the same call captured as a HIP "
+                           "graph and replayed"),
+        graph_replay=m["graph_replay"],
         latency_ms=m["latency_ms"],
-        fp64=dict(value=d["value"], ms_per_step=d["ms_per_step"], latency_ms=d["latency_ms"],
+        fp64=dict(value=d["value"], ms_per_step=d["ms_per_step"], graph_replay=d["graph_replay"],
+                  latency_ms=d["latency_ms"],
                   dtype="f64", roofline=dict(bound="hbm", achieved=achieved64,
                                              peak=HBM_PEAK_GBS, unit="GB/s",
                                              frac=achieved64 / HBM_PEAK_GBS,

@@ -470,6 +470,42 @@ class Evaluator:
             check(rc, "rr_evaluate")
         return self.out
 
+    def capture(self, pv):
+        """Record one call on rows ``pv`` as a HIP graph (torch.cuda.CUDAGraph)
+        on a private stream, after a warm-up call there.  ``replay()`` then
+        runs the same kernels from one graph launch: the graph reads the rows
+        from ``pv``'s memory (write new rows into that tensor in place
+        between replays) and writes ``self.out``.  For callers that work
+        under graph capture or build larger graphs around the evaluation; a
+        replay is not faster than an eager call here (on one MI355X, 512
+        rows x 20 000 times: 33.7 us per replay against 28.9 us per call).
+        Nothing the graph records allocates or fills memory."""
+        if (pv.dtype is not torch.float64 or not pv.is_cuda or not pv.is_contiguous()
+                or pv.numel() != self.npv * self.npar):
+            raise ValueError("pv must be a float64 device tensor of shape (npv, npar)")
+        s = torch.cuda.Stream()
+        args = list(self._args)
+        args[self._pv_arg] = pv.data_ptr()
+        args[-1] = s.cuda_stream
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            for _ in range(2):           # workspace for this stream, cached choices
+                check(self._fn(*args), "rr_evaluate (graph warm-up)")
+        s.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            rc = self._fn(*args)
+        check(rc, "rr_evaluate (graph capture)")
+        self._graph, self._graph_pv = g, pv
+        return g
+
+    def replay(self):
+        """Run the captured call (``capture``); returns ``self.out``."""
+        if getattr(self, "_graph", None) is None:
+            raise RuntimeError("capture(pv) first")
+        self._graph.replay()
+        return self.out
+
 
 def loglik_grad(tables, series, pv, obs, sigma, precision="fp64", grad=True, profile=False,
                 wprof=None, stream=None, istar_grad=False):
