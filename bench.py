@@ -798,7 +798,11 @@ def main():
         r = res[prec]
         ms = 1e3 * r["wall"] / args.steps
         kern = float(np.mean(r["kern_ms"]))
-        traffic_alg = npv * npt * out_bytes + npt * 8 + npv * (8 * pv.shape[1] + PVCONST_BYTES)
+        # outputs, times and parameter rows, plus the per-row setup's output
+        # where the kernel reads it (every launch but the fused split one)
+        fused = series.kernel(tab, npv, prec) == "split_fused"
+        traffic_alg = (npv * npt * out_bytes + npt * 8 +
+                       npv * (8 * pv.shape[1] + (0 if fused else PVCONST_BYTES)))
         ms_graph = 1e3 * r["wall_graph"] / args.steps
         return dict(value=points / (ms / 1e3), ms_per_step=ms,
                     graph_replay=dict(value=points / (ms_graph / 1e3), ms_per_step=ms_graph),
@@ -809,8 +813,9 @@ def main():
     m = summary("mixed", 4)
     d = summary("fp64", 8)
     # the forward kernel the library launches on this series (rr_series_kernel)
-    kname = {p: ("k_forward_split<%s>" % t if series.kernel(tab, npv, p) == "split"
-                 else "k_forward<%s, false, 8>" % t)
+    kform = {"split": "k_forward_split<%s, false>", "split_fused": "k_forward_split<%s, true>",
+             "tiles": "k_forward<%s, false, 8>"}
+    kname = {p: kform[series.kernel(tab, npv, p)] % t
              for p, t in (("mixed", "float"), ("fp64", "double"))}
     achieved = m["alg_bytes"] / (m["kernel_ms"]["mean"] / 1e3) / 1e9
     kc = profile_counters(kname["mixed"])
@@ -830,9 +835,11 @@ def main():
                              "2-min cadence, power-2 LD tabulated at 200 mu",
                     npv=npv, npt=npt, nss=nss, precision="mixed (FP64 time reduction, FP32 bulk)",
                     grid=grid,
-                    launch="one rr_evaluate_series call per step from Python (setup kernel + "
-                           "forward kernel); 'graph_replay' = the same call captured as a HIP "
-                           "graph and replayed"),
+                    launch="one rr_evaluate_series call per step from Python (%sforward "
+                           "kernel '%s'); 'graph_replay' = the same call captured as a HIP "
+                           "graph and replayed" % (
+                               "" if kname["mixed"].endswith("true>") else "per-row setup + ",
+                               kname["mixed"])),
         graph_replay=m["graph_replay"],
         latency_ms=m["latency_ms"],
         fp64=dict(value=d["value"], ms_per_step=d["ms_per_step"], graph_replay=d["graph_replay"],

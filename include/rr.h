@@ -218,12 +218,18 @@ RR_API int rr_evaluate_series(const rr_tables* t, const rr_series* s, const doub
 
 /* Which forward kernel rr_evaluate_series launches for npv parameter
  * vectors in `precision` over this series: *kind = RR_KERNEL_TILES (0:
- * rr_evaluate's per-tile kernel) or RR_KERNEL_SPLIT (1: the split launch of
- * transit and streaming workgroups).  For benchmarks and profiles that name
- * the kernel they time.  Enqueues nothing (the choice may query the
- * device's occupancy once); errors as rr_evaluate_series's checks. */
+ * rr_evaluate's per-tile kernel, after the per-vector setup),
+ * RR_KERNEL_SPLIT (1: the split launch of transit and streaming
+ * workgroups, after the per-vector setup) or RR_KERNEL_SPLIT_FUSED (2: the
+ * split launch alone, its workgroups deriving their vectors' constants
+ * themselves; taken when all of its workgroups are resident at once, so
+ * small calls cost one launch).  All three give the same bits.  For
+ * benchmarks and profiles that name the kernel they time.  Enqueues
+ * nothing (the choice may query the device's occupancy once); errors as
+ * rr_evaluate_series's checks. */
 #define RR_KERNEL_TILES 0
 #define RR_KERNEL_SPLIT 1
+#define RR_KERNEL_SPLIT_FUSED 2
 RR_API int rr_series_kernel(const rr_tables* t, const rr_series* s, int32_t npv,
                             int32_t precision, int32_t* kind);
 

@@ -14,7 +14,7 @@ RR_OK, RR_EINVAL, RR_ENOMEM, RR_EDEVICE, RR_ELIMIT, RR_EBUSY, RR_ENOTFOUND = 0, 
 RR_FP64, RR_MIXED = 0, 1
 RR_MAX_PB, RR_MAX_LC, RR_MAX_NSS = 16, 64, 1024
 RR_NOALLOC_MAX_PV = 16384
-RR_KERNEL_TILES, RR_KERNEL_SPLIT = 0, 1
+RR_KERNEL_TILES, RR_KERNEL_SPLIT, RR_KERNEL_SPLIT_FUSED = 0, 1, 2
 
 c_double_p = ctypes.POINTER(ctypes.c_double)
 c_int32_p = ctypes.POINTER(ctypes.c_int32)

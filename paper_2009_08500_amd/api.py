@@ -179,12 +179,16 @@ class TimeSeries:
 
     def kernel(self, tables, npv, precision="mixed"):
         """The forward kernel ``evaluate`` launches on this series for npv
-        rows (rr_series_kernel): "split" or "tiles"."""
+        rows (rr_series_kernel): "tiles" (per-tile kernel after the per-row
+        setup), "split" (split launch after the per-row setup) or
+        "split_fused" (the split launch alone, deriving the rows' constants
+        itself)."""
         k = ctypes.c_int32(-1)
         check(_lib.lib().rr_series_kernel(tables.handle, self.handle, int(npv),
                                           PRECISIONS[precision], ctypes.byref(k)),
               "rr_series_kernel")
-        return "split" if k.value == _lib.RR_KERNEL_SPLIT else "tiles"
+        return {_lib.RR_KERNEL_SPLIT: "split",
+                _lib.RR_KERNEL_SPLIT_FUSED: "split_fused"}.get(k.value, "tiles")
 
     def lc_args(self):
         lc = ctypes.c_void_p(self.lcids.data_ptr()) if self.lcids is not None else None

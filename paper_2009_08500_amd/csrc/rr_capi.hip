@@ -442,17 +442,24 @@ RR_API int rr_evaluate_series(const rr_tables* t, const rr_series* se, const dou
     rc = check_device(t);
     if (rc) return rc;
     if (se->device != t->device) return einval("series and tables live on different devices");
-    void* ws = nullptr;
-    hipError_t e = stream_workspace(const_cast<rr_tables*>(t), stream,
-                                    sizeof(PvConst) * size_t(npv), &ws);
-    if (e != hipSuccess) return e == hipErrorOutOfMemory ? RR_ENOMEM : hip_fail(e, "workspace");
-    PvConst* pvc = static_cast<PvConst*>(ws);
-    e = launch_pv_setup(t, pv_d, npv, npar, pvc, stream);
+    const bool split = se->indexed && split_preferred(t, se, npv, precision);
+    const SplitPlan sp = split ? plan_forward_split(se, npv, precision) : SplitPlan{};
+    hipError_t e = hipSuccess;
+    PvConst* pvc = nullptr;
+    if (!(split && sp.self_setup)) {
+        void* ws = nullptr;
+        e = stream_workspace(const_cast<rr_tables*>(t), stream, sizeof(PvConst) * size_t(npv),
+                             &ws);
+        if (e != hipSuccess)
+            return e == hipErrorOutOfMemory ? RR_ENOMEM : hip_fail(e, "workspace");
+        pvc = static_cast<PvConst*>(ws);
+        e = launch_pv_setup(t, pv_d, npv, npar, pvc, stream);
+    }
     if (e == hipSuccess)
-        e = se->indexed && split_preferred(t, se, npv, precision)
-                ? launch_forward_split(t, se, pv_d, npv, npar, pvc, precision, out_d, stream)
-                : launch_forward(t, se->times, se->lcids, se->npt, lc, pv_d, npv, npar, pvc,
-                                 precision, out_d, stream);
+        e = split ? launch_forward_split(t, se, sp, pv_d, npv, npar, pvc, precision, out_d,
+                                         stream)
+                  : launch_forward(t, se->times, se->lcids, se->npt, lc, pv_d, npv, npar, pvc,
+                                   precision, out_d, stream);
     if (e != hipSuccess) return hip_fail(e, "forward kernels");
     return RR_OK;
 }
@@ -467,7 +474,9 @@ RR_API int rr_series_kernel(const rr_tables* t, const rr_series* se, int32_t npv
     if (precision != RR_FP64 && precision != RR_MIXED) return einval("unknown precision");
     int rc = check_device(t);
     if (rc) return rc;
-    if (se->indexed && split_preferred(t, se, npv, precision)) *kind = RR_KERNEL_SPLIT;
+    if (se->indexed && split_preferred(t, se, npv, precision))
+        *kind = plan_forward_split(se, npv, precision).self_setup ? RR_KERNEL_SPLIT_FUSED
+                                                                  : RR_KERNEL_SPLIT;
     return RR_OK;
 }
 

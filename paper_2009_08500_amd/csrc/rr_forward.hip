@@ -418,18 +418,28 @@ __device__ inline double win_phase(double t, double invP, const Win& w) {
 }
 __device__ inline bool win_in(double gph, const Win& w) { return gph - floor(gph) < w.wn; }
 
+// Constants of row ipv in the split launch: read from the per-row setup's
+// output, or (kSelf) derived here from the parameter row by the same
+// function, so both give the same bits.
+template <bool kSelf>
+__device__ inline PvConst split_row_const(const FwdJob& job, const SplitInfo& si, int ipv) {
+    if (kSelf)
+        return make_pv_const(job.pv + int64_t(ipv) * job.npar, job.npar - 6, si.k_lo, si.k_hi);
+    return job.pvc[ipv];
+}
+
 // Streaming role: tile `tile` of 64 J consecutive times for rows
 // [r0, r1).  The lane loads its J times once and, row by row, writes F = 1
 // to every exposure outside the row's window (NaN to every exposure of an
 // invalid row), leaving the others to the transit workgroups.  Only four
-// constants per row are read (scalar loads), so a row costs a handful of
-// VALU operations per exposure and its stores.  On the aligned path (whole
+// constants per row are used, so a row costs a handful of VALU operations
+// per exposure and its stores.  On the aligned path (whole
 // tile in one light curve, 16-B aligned rows) lane L owns the kVec
 // consecutive exposures 64 kVec q + kVec L + v of group q and stores a
 // group with one 16-B store when none of it is in the window.
-template <typename R, int J>
-__device__ inline void stream_rows(const FwdJob& job, const LcInfo& lc, int r0, int r1,
-                                   int tile) {
+template <typename R, int J, bool kSelf>
+__device__ inline void stream_rows(const FwdJob& job, const LcInfo& lc, const SplitInfo& si,
+                                   int r0, int r1, int tile) {
     constexpr int kSpan = 64 * J;
     constexpr int kVec = 16 / int(sizeof(R));
     constexpr int kGroups = J / kVec;
@@ -474,9 +484,8 @@ __device__ inline void stream_rows(const FwdJob& job, const LcInfo& lc, int r0, 
         }
     }
     const double ex_vec = lc.exptime[lvec];
-    // The rows' four constants, 64 rows per vector load (lane i holds row
-    // r0 + 64 k + i), handed to the row loop by readlane: one memory round
-    // trip per 64 rows instead of one per row.
+    // The rows' four window constants, 64 rows at a time (lane i takes row
+    // r0 + 64 k + i), handed to the row loop by readlane.
     double c_t0 = 0.0, c_invP = 0.0, c_flo = 0.0, c_wn = 0.0;
     int c_ok = 0;
     for (int ipv = r0; ipv < r1; ++ipv) {
@@ -484,9 +493,9 @@ __device__ inline void stream_rows(const FwdJob& job, const LcInfo& lc, int r0, 
         if (k == 0) {
             const int rl = ipv + lane;
             if (rl < r1) {
-                const PvConst* __restrict__ pl = job.pvc + rl;
-                c_t0 = pl->t0; c_invP = pl->invP; c_flo = pl->flo; c_wn = pl->wn;
-                c_ok = pl->flags & kValid;
+                const PvConst pl = split_row_const<kSelf>(job, si, rl);
+                c_t0 = pl.t0; c_invP = pl.invP; c_flo = pl.flo; c_wn = pl.wn;
+                c_ok = pl.flags & kValid;
             }
         }
         R* __restrict__ orow = static_cast<R*>(job.out) + int64_t(ipv) * npt;
@@ -561,13 +570,13 @@ __device__ inline int owner_lane(int excl, int j) {
 // same bits; so nothing is compacted or staged.  One subsample per
 // exposure (the launch serves such series only); two candidates per lane as
 // independent chains.
-template <typename R>
+template <typename R, bool kSelf>
 __device__ inline void transit_share(const FwdJob& job, const LcInfo& lc, const SplitInfo& si,
                                      int ipv, int share, const GridDev& g,
                                      const R* __restrict__ T,
                                      const double* __restrict__ inv_istar) {
     const int lane = threadIdx.x & 63;
-    const PvConst p = job.pvc[ipv];
+    const PvConst p = split_row_const<kSelf>(job, si, ipv);
     if (!(p.flags & kValid)) return;
     const double* __restrict__ times = job.times;
     R* __restrict__ orow = static_cast<R*>(job.out) + int64_t(ipv) * job.npt;
@@ -642,10 +651,11 @@ __device__ inline void transit_share(const FwdJob& job, const LcInfo& lc, const 
 
 // The split launch: workgroups [0, npv * shares) take the transits (share
 // b % shares of row b / shares); the others stream time tiles over blocks
-// of rows (tile u % ntiles of rows [rows_per u / ntiles, ...)).  The launch
-// is sized to be resident all at once, so the transit work runs beside the
-// streaming stores from the start instead of forming a tail.
-template <typename R>
+// of rows (tile u % ntiles of rows [rows_per u / ntiles, ...)).  The
+// transit workgroups are resident from the start, so their work runs beside
+// the streaming stores instead of forming a tail.  kSelf: each workgroup
+// derives its rows' constants itself (no setup launch before it).
+template <typename R, bool kSelf>
 __global__ __launch_bounds__(kFwdBlock) void k_forward_split(FwdJob job, LcInfo lc, GridDev g,
                                                           const R* __restrict__ T,
                                                           const double* __restrict__ inv_istar,
@@ -654,14 +664,14 @@ __global__ __launch_bounds__(kFwdBlock) void k_forward_split(FwdJob job, LcInfo 
     const int n2 = job.npv * si.shares;
     if (b < n2) {
         const int ipv = b / si.shares;
-        transit_share<R>(job, lc, si, ipv, b - ipv * si.shares, g, T, inv_istar);
+        transit_share<R, kSelf>(job, lc, si, ipv, b - ipv * si.shares, g, T, inv_istar);
         return;
     }
     const int u = b - n2;
     const int rg = u / job.ntiles;
     const int r0 = rg * si.rows_per;
     const int r1 = r0 + si.rows_per < job.npv ? r0 + si.rows_per : job.npv;
-    stream_rows<R, kTimesPerThread>(job, lc, r0, r1, u - rg * job.ntiles);
+    stream_rows<R, kTimesPerThread, kSelf>(job, lc, si, r0, r1, u - rg * job.ntiles);
 }
 
 // One population (rr_evaluate): workgroup (x, y) -> row pv0 + y, tile x of
@@ -806,12 +816,12 @@ hipError_t launch_forward(const rr_tables* t, const double* times,
 
 // Workgroups of the split kernel (one wave each) resident at once on the
 // current device; 0 if the query fails.
-static int split_capacity(int32_t precision) {
+static int split_capacity(int32_t precision, bool self) {
     static std::mutex mu;
-    static std::map<std::tuple<int, int>, int> cache;
+    static std::map<std::tuple<int, int, int>, int> cache;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
-    const auto key = std::make_tuple(dev, precision == RR_FP64 ? 0 : 1);
+    const auto key = std::make_tuple(dev, precision == RR_FP64 ? 0 : 1, self ? 1 : 0);
     std::lock_guard<std::mutex> lk(mu);
     auto it = cache.find(key);
     if (it != cache.end()) return it->second;
@@ -820,9 +830,15 @@ static int split_capacity(int32_t precision) {
         return 0;
     hipError_t e;
     if (precision == RR_FP64)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_forward_split<double>, kFwdBlock, 0);
+        e = self ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                       &per_cu, k_forward_split<double, true>, kFwdBlock, 0)
+                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                       &per_cu, k_forward_split<double, false>, kFwdBlock, 0);
     else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_forward_split<float>, kFwdBlock, 0);
+        e = self ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                       &per_cu, k_forward_split<float, true>, kFwdBlock, 0)
+                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                       &per_cu, k_forward_split<float, false>, kFwdBlock, 0);
     if (e != hipSuccess || per_cu <= 0) return 0;
     cache[key] = per_cu * ncu;
     return per_cu * ncu;
@@ -835,20 +851,14 @@ bool split_preferred(const rr_tables* t, const rr_series* se, int32_t npv, int32
     // 1024 rows; the per-tile kernel stays ahead on supersampled series.
     const int64_t ntiles = (int64_t(se->npt) + kFwdTile - 1) / kFwdTile;
     if (se->max_nss != 1 || (ntiles <= 2 && npv > 1024)) return false;
-    return split_capacity(precision) > 0;
+    return split_capacity(precision, false) > 0;
 }
 
-hipError_t launch_forward_split(const rr_tables* t, const rr_series* se, const double* pv,
-                                int32_t npv, int32_t npar, const PvConst* pvc,
-                                int32_t precision, void* out, hipStream_t s) {
-    const GridDev g = grid_dev(t);
-    FwdJob job = {};
-    job.times = se->times; job.lcids = se->lcids; job.pv = pv; job.pvc = pvc; job.out = out;
-    job.npt = se->npt; job.npar = npar; job.pv0 = 0; job.npv = npv;
-    job.ntiles = (se->npt + kFwdTile - 1) / kFwdTile; job.max_nss = se->max_nss; job.spread = 1;
-    if (se->max_nss != 1) return hipErrorInvalidValue;    // see split_preferred
-    int cap = split_capacity(precision);
+SplitPlan plan_forward_split(const rr_series* se, int32_t npv, int32_t precision) {
+    SplitPlan sp;
+    int cap = split_capacity(precision, false);
     if (cap <= 0) cap = 2048;
+    const int64_t ntiles = (int64_t(se->npt) + kFwdTile - 1) / kFwdTile;
     // The transit workgroups (at most 16 per row, one per 64 exposures of a
     // row) start first; the streaming workgroups, kSplitRows rows of one
     // time tile each (2 for small problems, so that there are enough of
@@ -858,27 +868,64 @@ hipError_t launch_forward_split(const rr_tables* t, const rr_series* se, const d
     // 16 tiles or more, else at most 2048 -- fewer leave too much serial
     // work per lane, more queue behind each other or spend their time on
     // set-up.
+    const int64_t max_sh = std::max<int64_t>(1, (int64_t(se->npt) + 63) / 64);
+    const int64_t n_transit =
+        npv >= 512 && ntiles >= 16 ? int64_t(cap) : std::min<int64_t>(cap, 2048);
+    sp.shares = int32_t(std::min<int64_t>({16, max_sh, std::max<int64_t>(1, n_transit / npv)}));
+    const int64_t tiles_total = ntiles * npv;
+    sp.rows_per = std::max<int32_t>(
+        1, std::min<int32_t>(tiles_total < 2 * int64_t(cap) ? 2 : kSplitRows, npv));
+    sp.blocks = int64_t(npv) * sp.shares + ntiles * ((npv + sp.rows_per - 1) / sp.rows_per);
+    // Each workgroup can derive its rows' constants itself, at the cost of
+    // that latency at its start: measured, this beats a setup launch before
+    // the kernel only when every workgroup is resident at once (otherwise
+    // the later ones pay it again behind the first).
+    const int cap_self = split_capacity(precision, true);
+    sp.self_setup = cap_self > 0 && sp.blocks <= int64_t(cap_self);
+    return sp;
+}
+
+hipError_t launch_forward_split(const rr_tables* t, const rr_series* se, const SplitPlan& sp,
+                                const double* pv, int32_t npv, int32_t npar,
+                                const PvConst* pvc, int32_t precision, void* out,
+                                hipStream_t s) {
+    const GridDev g = grid_dev(t);
+    FwdJob job = {};
+    job.times = se->times; job.lcids = se->lcids; job.pv = pv; job.pvc = pvc; job.out = out;
+    job.npt = se->npt; job.npar = npar; job.pv0 = 0; job.npv = npv;
+    job.ntiles = (se->npt + kFwdTile - 1) / kFwdTile; job.max_nss = se->max_nss; job.spread = 1;
+    if (se->max_nss != 1) return hipErrorInvalidValue;    // see split_preferred
+    if (!sp.self_setup && !pvc) return hipErrorInvalidValue;
+    if (sp.shares < 1 || sp.rows_per < 1) return hipErrorInvalidValue;
+    const int64_t ntiles = job.ntiles;
+    const int64_t blocks =
+        int64_t(npv) * sp.shares + ntiles * ((npv + sp.rows_per - 1) / sp.rows_per);
+    if (blocks != sp.blocks || blocks >= (int64_t(1) << 31)) return hipErrorInvalidValue;
     SplitInfo si;
     si.lcs = se->lcs;
     si.buckets = se->buckets;
-    const int64_t max_sh = std::max<int64_t>(1, (int64_t(se->npt) + 63) / 64);
-    const int64_t n_transit =
-        npv >= 512 && job.ntiles >= 16 ? int64_t(cap) : std::min<int64_t>(cap, 2048);
-    si.shares = int32_t(std::min<int64_t>({16, max_sh, std::max<int64_t>(1, n_transit / npv)}));
-    const int64_t tiles_total = int64_t(job.ntiles) * npv;
-    si.rows_per = std::min<int32_t>(tiles_total < 2 * int64_t(cap) ? 2 : kSplitRows, npv);
-    const int64_t n_tr = int64_t(npv) * si.shares;
-    const int64_t n_st = int64_t(job.ntiles) * ((npv + si.rows_per - 1) / si.rows_per);
-    if (n_tr + n_st >= (int64_t(1) << 31)) return hipErrorInvalidValue;
-    const dim3 grid{unsigned(n_tr + n_st), 1u, 1u};
+    si.shares = sp.shares;
+    si.rows_per = sp.rows_per;
+    si.k_lo = t->grid.k0;
+    si.k_hi = t->grid.k1;
+    const dim3 grid{unsigned(blocks), 1u, 1u};
     const dim3 block{unsigned(kFwdBlock), 1u, 1u};
     const KernelEvents ev = kernel_events();
-    if (precision == RR_FP64)
-        launch_timed(k_forward_split<double>, grid, block, 0, s, ev.before, ev.after, job, se->lc,
-                     g, t->T64, t->inv_istar, si);
-    else
-        launch_timed(k_forward_split<float>, grid, block, 0, s, ev.before, ev.after, job, se->lc,
-                     g, t->T32, t->inv_istar, si);
+    if (precision == RR_FP64) {
+        if (sp.self_setup)
+            launch_timed(k_forward_split<double, true>, grid, block, 0, s, ev.before, ev.after,
+                         job, se->lc, g, t->T64, t->inv_istar, si);
+        else
+            launch_timed(k_forward_split<double, false>, grid, block, 0, s, ev.before, ev.after,
+                         job, se->lc, g, t->T64, t->inv_istar, si);
+    } else {
+        if (sp.self_setup)
+            launch_timed(k_forward_split<float, true>, grid, block, 0, s, ev.before, ev.after,
+                         job, se->lc, g, t->T32, t->inv_istar, si);
+        else
+            launch_timed(k_forward_split<float, false>, grid, block, 0, s, ev.before, ev.after,
+                         job, se->lc, g, t->T32, t->inv_istar, si);
+    }
     return hipGetLastError();
 }
 

@@ -114,6 +114,7 @@ struct SplitInfo {
     const int32_t* buckets;    // device
     int32_t shares;
     int32_t rows_per;          // rows per streaming workgroup
+    double k_lo, k_hi;         // accepted k range of the rows (the tables')
 };
 
 // Scalars of the table grid needed on the device.
@@ -271,15 +272,27 @@ hipError_t launch_fill(double* p, int64_t n, hipStream_t s);
 hipError_t launch_istar_set(rr_tables* t, const double* src, hipStream_t s);
 // I_star from the profile samples (the interpolant's exact integral).
 hipError_t launch_istar_from_profile(rr_tables* t, hipStream_t s);
-// Whether rr_evaluate_series takes the split launch for this size: when the
-// per-tile kernel's workgroups (npv x tiles of 512 times) number at most
-// 2.5 x the split kernel's resident workgroups (measured crossover, both
-// precisions); beyond that the per-tile kernel is faster.
+// Whether rr_evaluate_series takes the split launch for this size: series
+// with one subsample per exposure, except two time tiles or fewer under
+// more than 1024 rows (measured, both precisions); the per-tile kernel
+// otherwise.
 bool split_preferred(const rr_tables* t, const rr_series* se, int32_t npv, int32_t precision);
-// Split launch over a registered, indexed series (rr_evaluate_series).
-hipError_t launch_forward_split(const rr_tables* t, const rr_series* se, const double* pv,
-                                int32_t npv, int32_t npar, const PvConst* pvc,
-                                int32_t precision, void* out, hipStream_t s);
+// Shape of a split launch over a registered, indexed series: transit
+// workgroups per row, rows per streaming workgroup, the grid size, and
+// whether the workgroups derive their rows' constants themselves (then no
+// per-row setup precedes the launch).
+struct SplitPlan {
+    int32_t shares = 1, rows_per = 1;
+    int64_t blocks = 0;
+    bool self_setup = false;
+};
+SplitPlan plan_forward_split(const rr_series* se, int32_t npv, int32_t precision);
+// The split launch (rr_evaluate_series); pvc (the per-row setup's output)
+// is read unless sp.self_setup.
+hipError_t launch_forward_split(const rr_tables* t, const rr_series* se, const SplitPlan& sp,
+                                const double* pv, int32_t npv, int32_t npar,
+                                const PvConst* pvc, int32_t precision, void* out,
+                                hipStream_t s);
 hipError_t launch_forward_jobs(const rr_tables* t, const JobTable& jt,
                                int32_t nblocks_total, int32_t precision, hipStream_t s);
 hipError_t launch_pv_setup_jobs(const rr_tables* t, const SetupTable& st,

@@ -209,10 +209,12 @@ def test_kernel_query(rr):
     tab = rr.Tables(w["mu_s"], w["I_s"], wl.TEST_GRID)
     ser = rr.TimeSeries(w["times"])
     for prec in ("mixed", "fp64"):
-        assert ser.kernel(tab, 8, prec) == "split"
+        # 8 rows: 128 transit + 24 streaming workgroups, all resident at once
+        assert ser.kernel(tab, 8, prec) == "split_fused"
         assert ser.kernel(tab, 4096, prec) == "split"         # 6 tiles of 512
     short = rr.TimeSeries(w["times"][:1000])
-    assert short.kernel(tab, 1024, "mixed") == "split"
+    # (whether the split launch is fused depends on the device's capacity)
+    assert short.kernel(tab, 1024, "mixed") in ("split", "split_fused")
     assert short.kernel(tab, 1025, "mixed") == "tiles"
     sup = rr.TimeSeries(w["times"], nss=[3], exptimes=[0.02])
     assert sup.kernel(tab, 8, "mixed") == "tiles"
@@ -228,17 +230,39 @@ def test_kernel_query(rr):
     tab.close()
 
 
-def test_graph_replay_matches_eager(rr):
-    """Evaluator.capture records one call (setup and the split launch) as a
-    HIP graph; every replay, with eager evaluations and new rows written in
-    place between replays, gives the eager call's fluxes bit for bit."""
-    import torch
-    w = wl.population(npv=64, npt=6000, seed_extra=33)
-    w2 = wl.population(npv=64, npt=6000, seed_extra=34)
+def test_fused_launch_matches_setup_launch(rr):
+    """The split launch gives the same bits whether its workgroups derive
+    the rows' constants themselves (few rows: every workgroup resident at
+    once) or read them from the per-row setup (many rows): the first rows of
+    a 1024-row call equal an 8-row call on the same rows, both precisions."""
+    w = wl.population(npv=1024, npt=6000, seed_extra=35)
     tab = rr.Tables(w["mu_s"], w["I_s"], wl.TEST_GRID)
     ser = rr.TimeSeries(w["times"])
     for prec in ("mixed", "fp64"):
-        ev = rr.Evaluator(tab, ser, 64, prec)
+        assert ser.kernel(tab, 1024, prec) == "split"
+        assert ser.kernel(tab, 8, prec) == "split_fused"
+        print(f"fused vs setup launch {prec}", flush=True)
+        full = rr.evaluate(tab, ser, w["pv"], prec)
+        few = rr.evaluate(tab, ser, w["pv"][:8], prec)
+        assert np.array_equal(full[:8].cpu().numpy(), few.cpu().numpy(), equal_nan=True), prec
+    ser.close()
+    tab.close()
+
+
+@pytest.mark.parametrize("npv,kind", [(64, "split_fused"), (1024, "split")])
+def test_graph_replay_matches_eager(rr, npv, kind):
+    """Evaluator.capture records one call (the fused split launch, or the
+    per-row setup and the split launch) as a HIP graph; every replay, with
+    eager evaluations and new rows written in place between replays, gives
+    the eager call's fluxes bit for bit."""
+    import torch
+    w = wl.population(npv=npv, npt=6000, seed_extra=33)
+    w2 = wl.population(npv=npv, npt=6000, seed_extra=34)
+    tab = rr.Tables(w["mu_s"], w["I_s"], wl.TEST_GRID)
+    ser = rr.TimeSeries(w["times"])
+    for prec in ("mixed", "fp64"):
+        assert ser.kernel(tab, npv, prec) == kind
+        ev = rr.Evaluator(tab, ser, npv, prec)
         pv = torch.as_tensor(w["pv"], device="cuda").clone()
         ev.capture(pv)
         for it in range(5):
