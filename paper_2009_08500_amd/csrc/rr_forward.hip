@@ -26,6 +26,7 @@
 // The kernels are templated on the bulk real type: double (RR_FP64) or float
 // (RR_MIXED: the time reduction stays FP64, the rest is FP32).
 #include <algorithm>
+#include <cmath>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -858,30 +859,40 @@ SplitPlan plan_forward_split(const rr_series* se, int32_t npv, int32_t precision
     SplitPlan sp;
     int cap = split_capacity(precision, false);
     if (cap <= 0) cap = 2048;
+    const int cap_self = split_capacity(precision, true);
     const int64_t ntiles = (int64_t(se->npt) + kFwdTile - 1) / kFwdTile;
-    // The transit workgroups (at most 16 per row, one per 64 exposures of a
-    // row) start first; the streaming workgroups, kSplitRows rows of one
-    // time tile each (2 for small problems, so that there are enough of
-    // them), take the slots as transit workgroups finish.  Measured on the
-    // population workloads (16 to 4096 rows, 1000 to 50 000 times): as many
-    // transit workgroups as are resident at once for 512 rows or more over
-    // 16 tiles or more, else at most 2048 -- fewer leave too much serial
-    // work per lane, more queue behind each other or spend their time on
-    // set-up.
-    const int64_t max_sh = std::max<int64_t>(1, (int64_t(se->npt) + 63) / 64);
-    const int64_t n_transit =
-        npv >= 512 && ntiles >= 16 ? int64_t(cap) : std::min<int64_t>(cap, 2048);
-    sp.shares = int32_t(std::min<int64_t>({16, max_sh, std::max<int64_t>(1, n_transit / npv)}));
     const int64_t tiles_total = ntiles * npv;
+    const int64_t max_sh = std::max<int64_t>(1, (int64_t(se->npt) + 63) / 64);
+    // Streaming workgroups take kSplitRows rows of one time tile each (2
+    // for small problems, so that there are enough of them).
     sp.rows_per = std::max<int32_t>(
         1, std::min<int32_t>(tiles_total < 2 * int64_t(cap) ? 2 : kSplitRows, npv));
+    // Two regimes, from sweeps of both precisions over the population
+    // workloads (16 to 4096 rows, 1000 to 50 000 times, 2 to 16 transit
+    // workgroups per row, 4 to 16 rows per streaming workgroup):
+    //  * up to 5 x the fused kernel's resident workgroups in time tiles
+    //    (tiles x rows), every workgroup derives its rows' constants
+    //    itself and no setup launch precedes the kernel.  Transit
+    //    workgroups per row: ceil(sqrt(8192 / rows)), at least 1024 in all
+    //    (16 per row at 64 rows, 8 at 128, 6 at 256, 4 at 512); more queue
+    //    behind each other or spend their time on set-up, fewer leave too
+    //    much serial work per lane.
+    //  * beyond that the later workgroups would pay the set-up latency again
+    //    behind the first, so the setup kernel runs first and, for 512 rows
+    //    or more over 16 tiles or more, there are as many transit
+    //    workgroups as are resident at once, else at most 2048.
+    if (cap_self > 0 && tiles_total <= 5 * int64_t(cap_self)) {
+        sp.self_setup = true;
+        const int64_t by_rows = int64_t(std::ceil(std::sqrt(8192.0 / double(npv))));
+        const int64_t by_total = (1024 + int64_t(npv) - 1) / npv;
+        sp.shares = int32_t(std::min<int64_t>({16, max_sh, std::max(by_rows, by_total)}));
+    } else {
+        const int64_t n_transit =
+            npv >= 512 && ntiles >= 16 ? int64_t(cap) : std::min<int64_t>(cap, 2048);
+        sp.shares =
+            int32_t(std::min<int64_t>({16, max_sh, std::max<int64_t>(1, n_transit / npv)}));
+    }
     sp.blocks = int64_t(npv) * sp.shares + ntiles * ((npv + sp.rows_per - 1) / sp.rows_per);
-    // Each workgroup can derive its rows' constants itself, at the cost of
-    // that latency at its start: measured, this beats a setup launch before
-    // the kernel only when every workgroup is resident at once (otherwise
-    // the later ones pay it again behind the first).
-    const int cap_self = split_capacity(precision, true);
-    sp.self_setup = cap_self > 0 && sp.blocks <= int64_t(cap_self);
     return sp;
 }
 
