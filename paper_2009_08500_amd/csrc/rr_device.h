@@ -314,18 +314,25 @@ __host__ __device__ inline PvConst make_pv_const(const double* row, int npb, dou
         ok = ok && is_finite(k) && (k < k_small ? k > 0.0 : (k >= k0 && k <= k1));
         kmax = k > kmax ? k : kmax;
     }
+    // Few divisions, and most of them off the dependent chain: the
+    // reciprocals of p = a (1 - e^2) and P do not wait for sin w.
     double sw = 0.0, cw = 1.0;
     if (ok) sincos(w, &sw, &cw);
-    const double q = ok ? sqrt(1.0 - e * e) : 1.0;
-    const double cosi = ok ? b * (1.0 + e * sw) / (a * (1.0 - e * e)) : 0.0;
-    ok = ok && fabs(cosi) <= 1.0;
-    c.t0 = t0; c.P = P; c.invP = 1.0 / P; c.n = 2.0 * Num<double>::pi / P;
-    c.a = a; c.e = e; c.cosw = cw; c.sinw = sw; c.q = q; c.cosi = cosi;
-    // conjunction: f_tr = pi/2 - w, so cos f_tr = sin w and sin f_tr = cos w
+    const double ome2 = 1.0 - e * e;
+    const double q = ok ? sqrt(ome2) : 1.0;
+    const double p = a * ome2;                       // semi-latus rectum
+    const double inv_p = ok ? 1.0 / p : 0.0;
+    // conjunction: f_tr = pi/2 - w, so cos f_tr = sin w and sin f_tr = cos w,
+    // and r_tr = p / (1 + e sin w)
     const double den = 1.0 + e * sw;
-    c.cE = (e + sw) / den;
-    c.sE = q * cw / den;
-    c.rtr = a * (1.0 - e * e) / den;
+    const double cosi = ok ? b * den * inv_p : 0.0;
+    ok = ok && fabs(cosi) <= 1.0;
+    c.t0 = t0; c.P = P; c.invP = 1.0 / P; c.n = 2.0 * Num<double>::pi * c.invP;
+    c.a = a; c.e = e; c.cosw = cw; c.sinw = sw; c.q = q; c.cosi = cosi;
+    const double inv_den = 1.0 / den;
+    c.cE = (e + sw) * inv_den;
+    c.sE = q * cw * inv_den;
+    c.rtr = p * inv_den;
     c.kmax = kmax;
     int32_t flags = ok ? kValid : 0;
     c.flo = 0.0;
@@ -347,36 +354,42 @@ __host__ __device__ inline PvConst make_pv_const(const double* row, int npb, dou
         // sin E = q sin f/(1 + e cos f), and the mean-anomaly offsets from
         // conjunction are dM = dE - e (sin E - sin E_tr) with dE the angle from
         // E_tr to E (one atan2 each).  The arc contains periapsis iff
-        // cos f_tr = sin w >= cos theta.
+        // cos f_tr = sin w >= cos theta.  With r = p / g, g = 1 + e cos f,
+        // (1 + k)^2 / r^2 = (1 + k)^2 g^2 / p^2: rmin = a (1 - e) is g = 1 + e,
+        // and a larger rmin is a smaller g.
         const double ci2 = cosi * cosi, si2 = 1.0 - ci2;
         const double opk2 = (1.0 + kmax) * (1.0 + kmax) * (1.0 + 2e-6);
-        double rmin = a * (1.0 - e);
+        const double opk2_p2 = opk2 * inv_p * inv_p;
+        const double inv_si2 = si2 > 0.0 ? 1.0 / si2 : 0.0;
+        double gmax = 1.0 + e;
         double sth = 1.0, cth = 0.0;                 // theta = pi/2: the front half
         bool never = false;
         for (int it = 0; it < 2; ++it) {
-            const double num = opk2 / (rmin * rmin) - ci2;
+            const double num = opk2_p2 * gmax * gmax - ci2;
             if (num <= 0.0) { never = true; break; }
-            const double s2 = si2 > 0.0 ? num / si2 : 2.0;
+            const double s2 = si2 > 0.0 ? num * inv_si2 : 2.0;
             if (s2 < 1.0) { sth = sqrt(s2); cth = sqrt(1.0 - s2); }
             else { sth = 1.0; cth = 0.0; }
             if (e == 0.0) break;
             const double cmax = sw >= cth ? 1.0 : fmax(sw * cth - cw * sth, sw * cth + cw * sth);
-            const double rnew = a * (1.0 - e * e) / (1.0 + e * cmax);
-            if (rnew <= rmin) break;
-            rmin = rnew;
+            const double gnew = 1.0 + e * cmax;
+            if (gnew >= gmax) break;
+            gmax = gnew;
         }
         if (never) {
             c.wn = 0.0;                  // no exposure is ever inside
         } else {
             // dE in float: its error (a few 1e-7 rad) is far inside the
-            // margin of 2e-6 of a period added on each side
+            // margin of 2e-6 of a period added on each side.  The atan2
+            // takes cos E and sin E times 1 + e cos f > 0 (the same angle),
+            // so only sin E itself needs the division.
             auto dmean = [&](double sign) {
                 const double cf = sw * cth - sign * cw * sth;
                 const double sf = cw * cth + sign * sw * sth;
-                const double inv = 1.0 / (1.0 + e * cf);
-                const double cEx = (e + cf) * inv, sEx = q * sf * inv;
-                const float dE = atan2f(float(sEx * c.cE - cEx * c.sE),
-                                        float(cEx * c.cE + sEx * c.sE));
+                const double cEu = e + cf, sEu = q * sf;
+                const float dE = atan2f(float(sEu * c.cE - cEu * c.sE),
+                                        float(cEu * c.cE + sEu * c.sE));
+                const double sEx = sEu / (1.0 + e * cf);
                 return double(dE) - e * (sEx - c.sE);
             };
             const double inv2pi = 0.5 / Num<double>::pi;
