@@ -868,25 +868,42 @@ SplitPlan plan_forward_split(const rr_series* se, int32_t npv, int32_t precision
     sp.rows_per = std::max<int32_t>(
         1, std::min<int32_t>(tiles_total < 2 * int64_t(cap) ? 2 : kSplitRows, npv));
     // Two regimes, from sweeps of both precisions over the population
-    // workloads (16 to 4096 rows, 1000 to 50 000 times, 2 to 16 transit
+    // workloads (16 to 4096 rows, 1000 to 50 000 times, 1 to 16 transit
     // workgroups per row, 4 to 16 rows per streaming workgroup):
-    //  * up to 5 x the fused kernel's resident workgroups in time tiles
-    //    (tiles x rows), every workgroup derives its rows' constants
-    //    itself and no setup launch precedes the kernel.  Transit
-    //    workgroups per row: ceil(sqrt(8192 / rows)), at least 1024 in all
-    //    (16 per row at 64 rows, 8 at 128, 6 at 256, 4 at 512); more queue
-    //    behind each other or spend their time on set-up, fewer leave too
-    //    much serial work per lane.
-    //  * beyond that the later workgroups would pay the set-up latency again
-    //    behind the first, so the setup kernel runs first and, for 512 rows
-    //    or more over 16 tiles or more, there are as many transit
-    //    workgroups as are resident at once, else at most 2048.
-    if (cap_self > 0 && tiles_total <= 5 * int64_t(cap_self)) {
-        sp.self_setup = true;
-        const int64_t by_rows = int64_t(std::ceil(std::sqrt(8192.0 / double(npv))));
+    //  * every workgroup derives its rows' constants itself and no setup
+    //    launch precedes the kernel, as long as that launch has at most
+    //    twice as many workgroups as the kernel keeps resident (8192 in
+    //    float, 4096 in double here); beyond that too many of them pay the
+    //    set-up's latency again behind the first.  Transit workgroups per
+    //    row: ceil(sqrt(2 x resident x min(tiles, 40) / (40 rows))), fewer
+    //    for series shorter than 40 tiles (20 000 exposures), whose rows
+    //    have fewer transits, and at least 1024 in all; in float over 40
+    //    tiles or more that is 16 per row at 64 rows, 8 at 128, 6 at 256, 4
+    //    at 512, 3 at 1024.  More queue behind
+    //    each other or spend their time on set-up, fewer leave too much
+    //    serial work per lane.  From 768 rows over 32 tiles or more the
+    //    streaming workgroups take 8 rows, so that fewer of them pay the
+    //    set-up.
+    //  * otherwise the setup kernel runs first and, for 512 rows or more
+    //    over 16 tiles or more, there are as many transit workgroups as are
+    //    resident at once, else at most 2048.
+    if (cap_self > 0) {
+        const double len = double(std::min<int64_t>(ntiles, 40));
+        const int64_t by_rows =
+            int64_t(std::ceil(std::sqrt(2.0 * double(cap_self) * len / (40.0 * double(npv)))));
         const int64_t by_total = (1024 + int64_t(npv) - 1) / npv;
-        sp.shares = int32_t(std::min<int64_t>({16, max_sh, std::max(by_rows, by_total)}));
-    } else {
+        const int64_t shares =
+            std::min<int64_t>({16, max_sh, std::max<int64_t>({1, by_rows, by_total})});
+        const int32_t rows =
+            npv >= 768 && ntiles >= 32 ? std::min<int32_t>(2 * kSplitRows, npv) : sp.rows_per;
+        const int64_t blocks = int64_t(npv) * shares + ntiles * ((npv + rows - 1) / rows);
+        if (blocks <= 2 * int64_t(cap_self)) {
+            sp.self_setup = true;
+            sp.shares = int32_t(shares);
+            sp.rows_per = rows;
+        }
+    }
+    if (!sp.self_setup) {
         const int64_t n_transit =
             npv >= 512 && ntiles >= 16 ? int64_t(cap) : std::min<int64_t>(cap, 2048);
         sp.shares =

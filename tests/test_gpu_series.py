@@ -234,24 +234,24 @@ def test_fused_launch_matches_setup_launch(rr):
     """The split launch gives the same bits whether its workgroups derive
     the rows' constants themselves (fewer rows) or read them from the
     per-row setup (many rows), and whatever its sizing: the first rows of a
-    2048-row call equal 8-, 200- and 600-row calls on the same rows, both
-    precisions."""
-    w = wl.population(npv=2048, npt=6000, seed_extra=35)
+    4096-row call equal 8-, 200-, 600- and 1000-row calls on the same rows,
+    both precisions."""
+    w = wl.population(npv=4096, npt=6000, seed_extra=35)
     tab = rr.Tables(w["mu_s"], w["I_s"], wl.TEST_GRID)
     ser = rr.TimeSeries(w["times"])
     for prec in ("mixed", "fp64"):
-        assert ser.kernel(tab, 2048, prec) == "split"
+        assert ser.kernel(tab, 4096, prec) == "split"
         assert ser.kernel(tab, 8, prec) == "split_fused"
         print(f"fused vs setup launch {prec}", flush=True)
         full = rr.evaluate(tab, ser, w["pv"], prec).cpu().numpy()
-        for n in (8, 200, 600):
+        for n in (8, 200, 600, 1000):
             few = rr.evaluate(tab, ser, w["pv"][:n], prec).cpu().numpy()
             assert np.array_equal(full[:n], few, equal_nan=True), (prec, n, ser.kernel(tab, n, prec))
     ser.close()
     tab.close()
 
 
-@pytest.mark.parametrize("npv,kind", [(64, "split_fused"), (2048, "split")])
+@pytest.mark.parametrize("npv,kind", [(64, "split_fused"), (4096, "split")])
 def test_graph_replay_matches_eager(rr, npv, kind):
     """Evaluator.capture records one call (the fused split launch, or the
     per-row setup and the split launch) as a HIP graph; every replay, with
