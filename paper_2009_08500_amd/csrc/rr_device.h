@@ -300,6 +300,7 @@ __host__ __device__ inline bool is_finite(double x) { return (x - x) == 0.0; }
 // [0, 1), a k outside [k0, k1] or |cos i| > 1.
 // A radius ratio below k_small (small-planet rows, Sect. 3.4.2) only has to
 // be positive; any other must lie in [k0, k1].
+template <class Ops = HwOps>
 __host__ __device__ inline PvConst make_pv_const(const double* row, int npb, double k0,
                                                  double k1, double k_small = 0.0) {
     PvConst c = {};
@@ -347,6 +348,11 @@ __host__ __device__ inline PvConst make_pv_const(const double* row, int npb, dou
         // second pass narrows the population's windows by under 1 %).  An
         // empty arc means the planet never overlaps the star.
         //
+        // The arc only has to contain the true one (margins below), so its
+        // sin, cos (float square roots) and the arctangents (the float
+        // polynomial above, 1.1e-7 relative) run in float: their errors, a
+        // few 1e-7 rad, sit far inside the margins, and the arc ends enter
+        // only through their direction.
         // Only sin and cos of theta are needed: the arc's ends f = f_tr +- theta
         // have cos f = sin w cos theta -+ cos w sin theta and
         // sin f = cos w cos theta +- sin w sin theta, their eccentric
@@ -368,8 +374,13 @@ __host__ __device__ inline PvConst make_pv_const(const double* row, int npb, dou
             const double num = opk2_p2 * gmax * gmax - ci2;
             if (num <= 0.0) { never = true; break; }
             const double s2 = si2 > 0.0 ? num * inv_si2 : 2.0;
-            if (s2 < 1.0) { sth = sqrt(s2); cth = sqrt(1.0 - s2); }
-            else { sth = 1.0; cth = 0.0; }
+            if (s2 < 1.0) {
+                sth = double(Ops::sqrt(float(s2)));
+                cth = double(Ops::sqrt(float(1.0 - s2)));
+            } else {
+                sth = 1.0;
+                cth = 0.0;
+            }
             if (e == 0.0) break;
             const double cmax = sw >= cth ? 1.0 : fmax(sw * cth - cw * sth, sw * cth + cw * sth);
             const double gnew = 1.0 + e * cmax;
@@ -387,8 +398,8 @@ __host__ __device__ inline PvConst make_pv_const(const double* row, int npb, dou
                 const double cf = sw * cth - sign * cw * sth;
                 const double sf = cw * cth + sign * sw * sth;
                 const double cEu = e + cf, sEu = q * sf;
-                const float dE = atan2f(float(sEu * c.cE - cEu * c.sE),
-                                        float(cEu * c.cE + sEu * c.sE));
+                const float dE = atan2_poly<Ops>(float(sEu * c.cE - cEu * c.sE),
+                                                 float(cEu * c.cE + sEu * c.sE));
                 const double sEx = sEu / (1.0 + e * cf);
                 return double(dE) - e * (sEx - c.sE);
             };
