@@ -349,9 +349,10 @@ __host__ __device__ inline PvConst make_pv_const(const double* row, int npb, dou
         // empty arc means the planet never overlaps the star.
         //
         // The arc only has to contain the true one (margins below), so its
-        // sin, cos (float square roots) and the arctangents (the float
-        // polynomial above, 1.1e-7 relative) run in float: their errors, a
-        // few 1e-7 rad, sit far inside the margins, and the arc ends enter
+        // sin, cos (float square roots), the arctangents (the float
+        // polynomial above, 1.1e-7 relative) and the reciprocals of sin^2 i
+        // and 1 + e cos f run in float: their errors, a few 1e-7 rad, sit
+        // far inside the margins, and the arc ends enter the arctangents
         // only through their direction.
         // Only sin and cos of theta are needed: the arc's ends f = f_tr +- theta
         // have cos f = sin w cos theta -+ cos w sin theta and
@@ -366,7 +367,7 @@ __host__ __device__ inline PvConst make_pv_const(const double* row, int npb, dou
         const double ci2 = cosi * cosi, si2 = 1.0 - ci2;
         const double opk2 = (1.0 + kmax) * (1.0 + kmax) * (1.0 + 2e-6);
         const double opk2_p2 = opk2 * inv_p * inv_p;
-        const double inv_si2 = si2 > 0.0 ? 1.0 / si2 : 0.0;
+        const double inv_si2 = si2 > 0.0 ? double(Ops::rcp(float(si2))) : 0.0;
         double gmax = 1.0 + e;
         double sth = 1.0, cth = 0.0;                 // theta = pi/2: the front half
         bool never = false;
@@ -400,7 +401,7 @@ __host__ __device__ inline PvConst make_pv_const(const double* row, int npb, dou
                 const double cEu = e + cf, sEu = q * sf;
                 const float dE = atan2_poly<Ops>(float(sEu * c.cE - cEu * c.sE),
                                                  float(cEu * c.cE + sEu * c.sE));
-                const double sEx = sEu / (1.0 + e * cf);
+                const double sEx = sEu * double(Ops::rcp(float(1.0 + e * cf)));
                 return double(dE) - e * (sEx - c.sE);
             };
             const double inv2pi = 0.5 / Num<double>::pi;
