@@ -869,35 +869,37 @@ SplitPlan plan_forward_split(const rr_series* se, int32_t npv, int32_t precision
         1, std::min<int32_t>(tiles_total < 2 * int64_t(cap) ? 2 : kSplitRows, npv));
     // Two regimes, from sweeps of both precisions over the population
     // workloads (16 to 4096 rows, 1000 to 50 000 times, 1 to 16 transit
-    // workgroups per row, 4 to 16 rows per streaming workgroup):
+    // workgroups per row, 4 to 16 rows per streaming workgroup).  With
+    // `ref` the float fused kernel's resident workgroups (4096 here; the
+    // double kernel holds half as many, yet measured best with the same
+    // counts):
     //  * every workgroup derives its rows' constants itself and no setup
     //    launch precedes the kernel, as long as that launch has at most
-    //    twice as many workgroups as the kernel keeps resident (8192 in
-    //    float, 4096 in double here); beyond that too many of them pay the
-    //    set-up's latency again behind the first.  Transit workgroups per
-    //    row: ceil(sqrt(2 x resident x min(tiles, 40) / (40 rows))), fewer
-    //    for series shorter than 40 tiles (20 000 exposures), whose rows
-    //    have fewer transits, and at least 1024 in all; in float over 40
-    //    tiles or more that is 16 per row at 64 rows, 8 at 128, 6 at 256, 4
-    //    at 512, 3 at 1024.  More queue behind
-    //    each other or spend their time on set-up, fewer leave too much
-    //    serial work per lane.  From 768 rows over 32 tiles or more the
-    //    streaming workgroups take 8 rows, so that fewer of them pay the
-    //    set-up.
+    //    2 ref workgroups; beyond that too many of them pay the set-up's
+    //    latency again behind the first.  Transit workgroups per row:
+    //    ceil(sqrt(2 ref x min(tiles, 40) / (40 rows))), fewer for series
+    //    shorter than 40 tiles (20 000 exposures), whose rows have fewer
+    //    transits, and at least 1024 in all; over 40 tiles or more that is
+    //    16 per row at 64 rows, 8 at 128, 6 at 256, 4 at 512, 3 at 1024.
+    //    More queue behind each other or spend their time on set-up, fewer
+    //    leave too much serial work per lane.  From 768 rows over 32 tiles
+    //    or more the streaming workgroups take 8 rows, so that fewer of
+    //    them pay the set-up.
     //  * otherwise the setup kernel runs first and, for 512 rows or more
     //    over 16 tiles or more, there are as many transit workgroups as are
     //    resident at once, else at most 2048.
-    if (cap_self > 0) {
+    const int ref = split_capacity(RR_MIXED, true);
+    if (cap_self > 0 && ref > 0) {
         const double len = double(std::min<int64_t>(ntiles, 40));
         const int64_t by_rows =
-            int64_t(std::ceil(std::sqrt(2.0 * double(cap_self) * len / (40.0 * double(npv)))));
+            int64_t(std::ceil(std::sqrt(2.0 * double(ref) * len / (40.0 * double(npv)))));
         const int64_t by_total = (1024 + int64_t(npv) - 1) / npv;
         const int64_t shares =
             std::min<int64_t>({16, max_sh, std::max<int64_t>({1, by_rows, by_total})});
         const int32_t rows =
             npv >= 768 && ntiles >= 32 ? std::min<int32_t>(2 * kSplitRows, npv) : sp.rows_per;
         const int64_t blocks = int64_t(npv) * shares + ntiles * ((npv + rows - 1) / rows);
-        if (blocks <= 2 * int64_t(cap_self)) {
+        if (blocks <= 2 * int64_t(ref)) {
             sp.self_setup = true;
             sp.shares = int32_t(shares);
             sp.rows_per = rows;
