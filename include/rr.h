@@ -222,11 +222,13 @@ RR_API int rr_evaluate_series(const rr_tables* t, const rr_series* s, const doub
  * RR_KERNEL_SPLIT (1: the split launch of transit and streaming
  * workgroups, after the per-vector setup) or RR_KERNEL_SPLIT_FUSED (2: the
  * split launch alone, its workgroups deriving their vectors' constants
- * themselves; taken when all of its workgroups are resident at once, so
- * small calls cost one launch).  All three give the same bits.  For
- * benchmarks and profiles that name the kernel they time.  Enqueues
- * nothing (the choice may query the device's occupancy once); errors as
- * rr_evaluate_series's checks. */
+ * themselves; taken while the launch has at most twice as many workgroups
+ * as the float kernel keeps resident, where it measured faster, so such a
+ * call is one launch).  The two split launches give the same bits; the
+ * per-tile kernel agrees with them within a rounding of the flux (see
+ * rr_evaluate_series).  For benchmarks and profiles that name the kernel
+ * they time.  Enqueues nothing (the choice may query the device's
+ * occupancy once); errors as rr_evaluate_series's checks. */
 #define RR_KERNEL_TILES 0
 #define RR_KERNEL_SPLIT 1
 #define RR_KERNEL_SPLIT_FUSED 2
