@@ -120,6 +120,24 @@ def test_supersampled_passbands(rr):
     run_case(rr, w)
 
 
+def test_four_passbands_one_subsample(rr):
+    """The heterogeneous workload's four light curves and passbands with one
+    subsample each: the split launch (fused for these sizes) over several
+    indexed light curves with their own passbands and exposure times, and
+    rows with a radius ratio per passband."""
+    w = wl.heterogeneous(npv=40, days=8.0, seed_extra=37)
+    w["nss"] = np.ones_like(w["nss"])
+    w["name"] = "four passbands, nss 1"
+    multi = rr.TimeSeries(w["times"], lcids=w["lcids"], pbids=w["pbids"], nss=w["nss"],
+                          exptimes=w["exptimes"])
+    tab = rr.Tables(w["mu_s"], w["I_s"], wl.TEST_GRID)
+    for prec in ("mixed", "fp64"):
+        assert multi.kernel(tab, 40, prec) == "split_fused"
+    multi.close()
+    tab.close()
+    run_case(rr, w)
+
+
 def test_gaps_repeats_and_an_empty_light_curve(rr):
     rng = np.random.default_rng(27)
     base = wl.population(npv=24, npt=10, seed_extra=27)
