@@ -267,7 +267,9 @@ RR_API int rr_evaluate_noalloc(const rr_tables* t, const double* times_d,
  *   variant 0, 1, 2   each lane owns 4, 8, 16 exposures (a workgroup, one
  *                     wave64, owns 256, 512, 1024 consecutive times); the
  *                     subsamples of supersampled exposures are spread over
- *                     the lanes where a wave's flagged exposures share nss;
+ *                     the lanes where a wave's flagged exposures share nss
+ *                     and are few enough for that to be the cheaper
+ *                     schedule (else summed by one lane, as below);
  *   variant 3, 4, 5   the same tiles with every exposure's subsamples
  *                     summed by one lane.
  * rr_evaluate is variant 1.  Smaller tiles give more waves for small

@@ -279,8 +279,10 @@ def select_variant(tables, series, pv, precision="mixed", reps=20, stream=None):
     every variant on these inputs (``reps`` launches each, after one
     untimed) and returns (best, ms) with ms[v] the mean milliseconds per
     forward launch of variant v.  Variants 0, 1, 2 give each lane 4, 8, 16
-    exposures (1 is rr_evaluate's); 3, 4, 5 are the same with supersampled
-    exposures evaluated one per lane instead of spread over lanes.  Waits
+    exposures (1 is rr_evaluate's), spreading the subsamples of
+    supersampled exposures over lanes where a wave's flags are sparse enough
+    for that to pay; 3, 4, 5 are the same with supersampled exposures always
+    evaluated one per lane.  Waits
     for the stream."""
     prec = PRECISIONS[precision]
     if not isinstance(series, TimeSeries):

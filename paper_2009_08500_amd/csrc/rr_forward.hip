@@ -310,7 +310,8 @@ __device__ inline void forward_block(const FwdJob& job, const LcInfo& lc, int ip
 
     if constexpr (kSubPar) {
         // Supersampled exposures: if every flagged exposure of the wave has
-        // the same nss in [2, 32], spread the subsamples over the lanes --
+        // the same nss in [2, 32] and the wave's flags are sparse enough to
+        // gain from it, spread the subsamples over the lanes --
         // G = 64 / nss exposures per round, lane L on subsample L % nss of
         // exposure L / nss -- and let the first lane of each group sum the
         // group's terms in subsample order (so the result is the same as
@@ -334,7 +335,24 @@ __device__ inline void forward_block(const FwdJob& job, const LcInfo& lc, int ip
             pass2_pairs();
             return;
         }
-        if (job.spread && nmin == nmax && N >= 2 && N <= 32) {
+        // Spreading takes ceil(flagged / (64 / N)) rounds of one subsample
+        // per lane, each with its gathers and an N-term reduction (measured
+        // at ~1.5 subsamples of the per-lane loop); the per-lane loop N
+        // times the largest number of flagged exposures of one lane.  The
+        // wave takes the cheaper (both give the same bits).
+        bool spread = job.spread && nmin == nmax && N >= 2 && N <= 32;
+        if (spread) {
+            int mine = __popc(todo), most = mine, flagged = mine;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                const int a = __shfl_xor(most, off);
+                most = a > most ? a : most;
+                flagged += __shfl_xor(flagged, off);
+            }
+            const int G = 64 / N;
+            spread = 3 * ((flagged + G - 1) / G) < 2 * most * N;
+        }
+        if (spread) {
             __shared__ uint16_t packed[kFwdBlock / 64][kSpan];
             uint16_t* pk = packed[threadIdx.x >> 6];
             const uint64_t below = __lanemask_lt();
