@@ -752,6 +752,11 @@ def single_lc_leg(rr, wl, steps, warmup):
     return res
 
 
+def note(msg):
+    """A progress line on stderr (stdout carries only the result line)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -776,6 +781,7 @@ def main():
                               launches=args.steps)), flush=True)
         return
     lib = rr.lib()
+    note("library loaded; population workload")
     w = wl.population()
     grid = wl.DEFAULT_GRID
     npv, npt = w["pv"].shape[0], w["times"].size
@@ -791,6 +797,7 @@ def main():
                                                             args.steps, args.warmup, lib)
         res[prec] = dict(wall=wall, wall_graph=wall_graph, step_ms=step_ms, kern_ms=kern_ms)
         outs[prec] = out
+        note(f"population {prec} timed")
     out32, out64 = outs["mixed"], outs["fp64"]
     points = npv * npt * nss
 
@@ -860,22 +867,31 @@ def main():
     line["in_transit_fraction"] = float(np.mean(o64 < 1.0))
     if not args.no_serving:
         line["serving"] = serving_leg(rr, wl, args.serving_requests, args.serving_burst)
+        note("serving leg done")
     if not args.no_serving:
         line["single_light_curve"] = single_lc_leg(rr, wl, min(args.steps, 200), 20)
+        note("single light curve leg done")
     legs = set() if args.no_extra else set(args.legs.split(","))
     if "heterogeneous" in legs:
         line["heterogeneous"] = heterogeneous_leg(rr, wl, min(args.steps, 50), 5, lib)
+        note("heterogeneous leg done")
     if "per_vector_ld" in legs:
         line["per_vector_ld"] = per_vector_ld_leg(rr, wl, min(args.steps, 50), 5, lib)
+        note("per-vector LD leg done")
     if "direct" in legs:
         line["direct_model"] = direct_leg(rr, wl, min(args.steps, 20), 2)
+        note("direct model leg done")
     if "small_planet" in legs:
         line["small_planet"] = small_planet_leg(rr, wl, min(args.steps, 20), 2)
+        note("small-planet leg done")
     if "variants" in legs:
         line["variant_selection"] = variant_leg(rr, wl)
+        note("variant leg done")
     if "loglik" in legs:
         line["loglik_grad"] = loglik_leg(rr, wl, 10, 2)
+        note("log-likelihood leg done")
     if not args.no_cpu_baseline:
+        note("oracle baseline on the host")
         cb, acc = cpu_baseline(w, grid, args.cpu_seconds, o64, o32)
         line["cpu_baseline"] = cb
         line["accuracy_vs_oracle"] = acc
