@@ -455,11 +455,18 @@ RR_API int rr_evaluate_series(const rr_tables* t, const rr_series* se, const dou
         pvc = static_cast<PvConst*>(ws);
         e = launch_pv_setup(t, pv_d, npv, npar, pvc, stream);
     }
+    // Per-tile kernel on a supersampled series: 4 exposures per lane (twice
+    // the waves) while the call has at most 16 384 waves of 8 exposures per
+    // lane, where it measured faster (heterogeneous series of 64 rows 22.7
+    // -> 15.6 us, 30-minute exposures at nss 10 over 256 x 20 000 48.7 ->
+    // 42.8 us in float), else rr_evaluate's 8.
+    const int64_t waves8 = int64_t(npv) * ((se->npt + kFwdBlock * 8 - 1) / (kFwdBlock * 8));
+    const int variant = se->max_nss > 1 && waves8 <= 16384 ? 0 : kDefaultFwdVariant;
     if (e == hipSuccess)
         e = split ? launch_forward_split(t, se, sp, pv_d, npv, npar, pvc, precision, out_d,
                                          stream)
                   : launch_forward(t, se->times, se->lcids, se->npt, lc, pv_d, npv, npar, pvc,
-                                   precision, out_d, stream);
+                                   precision, out_d, stream, nullptr, nullptr, 0, variant);
     if (e != hipSuccess) return hip_fail(e, "forward kernels");
     return RR_OK;
 }
