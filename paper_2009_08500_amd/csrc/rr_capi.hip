@@ -312,7 +312,7 @@ RR_API int rr_evaluate(const rr_tables* t, const double* times_d,
                                     sizeof(PvConst) * size_t(npv), &ws);
     if (e != hipSuccess) return e == hipErrorOutOfMemory ? RR_ENOMEM : hip_fail(e, "workspace");
     PvConst* pvc = static_cast<PvConst*>(ws);
-    e = launch_pv_setup(t, pv_d, npv, npar, pvc, stream);
+    e = launch_pv_setup(t, pv_d, npv, npar, pvc, precision, stream);
     if (e == hipSuccess)
         e = launch_forward(t, times_d, lcids_d, npt, lc, pv_d, npv, npar, pvc,
                            precision, out_d, stream);
@@ -341,7 +341,7 @@ RR_API int rr_evaluate_noalloc(const rr_tables* t, const double* times_d,
         pvc = g_noalloc_scratch[t->device];
     }
     if (!pvc) return elimit("no fixed device array on this device");
-    hipError_t e = launch_pv_setup(t, pv_d, npv, npar, pvc, stream);
+    hipError_t e = launch_pv_setup(t, pv_d, npv, npar, pvc, precision, stream);
     if (e == hipSuccess)
         e = launch_forward(t, times_d, lcids_d, npt, lc, pv_d, npv, npar, pvc,
                            precision, out_d, stream);
@@ -453,7 +453,7 @@ RR_API int rr_evaluate_series(const rr_tables* t, const rr_series* se, const dou
         if (e != hipSuccess)
             return e == hipErrorOutOfMemory ? RR_ENOMEM : hip_fail(e, "workspace");
         pvc = static_cast<PvConst*>(ws);
-        e = launch_pv_setup(t, pv_d, npv, npar, pvc, stream);
+        e = launch_pv_setup(t, pv_d, npv, npar, pvc, precision, stream);
     }
     // Per-tile kernel on a supersampled series: 4 exposures per lane (twice
     // the waves) while the call has at most 16 384 waves of 8 exposures per
@@ -508,7 +508,7 @@ RR_API int rr_evaluate_variant(const rr_tables* t, const double* times_d,
                                     sizeof(PvConst) * size_t(npv), &ws);
     if (e != hipSuccess) return e == hipErrorOutOfMemory ? RR_ENOMEM : hip_fail(e, "workspace");
     PvConst* pvc = static_cast<PvConst*>(ws);
-    e = launch_pv_setup(t, pv_d, npv, npar, pvc, stream);
+    e = launch_pv_setup(t, pv_d, npv, npar, pvc, precision, stream);
     if (e == hipSuccess)
         e = launch_forward(t, times_d, lcids_d, npt, lc, pv_d, npv, npar, pvc, precision,
                            out_d, stream, nullptr, nullptr, 0, variant);
@@ -541,7 +541,7 @@ RR_API int rr_select_variant(const rr_tables* t, const double* times_d,
                                     sizeof(PvConst) * size_t(npv), &ws);
     if (e != hipSuccess) return e == hipErrorOutOfMemory ? RR_ENOMEM : hip_fail(e, "workspace");
     PvConst* pvc = static_cast<PvConst*>(ws);
-    e = launch_pv_setup(t, pv_d, npv, npar, pvc, stream);
+    e = launch_pv_setup(t, pv_d, npv, npar, pvc, precision, stream);
     if (e != hipSuccess) return hip_fail(e, "setup kernel");
     // without supersampling the one-lane-per-exposure variants launch the
     // same kernels as the others: only J is tried
@@ -610,7 +610,8 @@ RR_API int rr_evaluate_direct(const rr_tables* t, const double* times_d,
     PvConst* pvc = reinterpret_cast<PvConst*>(base + o_pvc);
     void* rows = base + o_rows;
     // any k in (0, 1]: the smallest positive double as the lower bound
-    e = launch_pv_setup_k(pv_d, npv, npar, 4.9406564584124654e-324, 1.0, pvc, stream);
+    e = launch_pv_setup_k(pv_d, npv, npar, 4.9406564584124654e-324, 1.0, pvc, precision,
+                          stream);
     if (e == hipSuccess) e = launch_direct_rows(t, pv_d, npv, npar, precision, rows, stream);
     if (e == hipSuccess)
         e = launch_forward(t, times_d, lcids_d, npt, lc, pv_d, npv, npar, pvc, precision,
@@ -648,7 +649,8 @@ RR_API int rr_evaluate_small_planet(const rr_tables* t, const double* times_d,
     char* base = static_cast<char*>(ws);
     PvConst* pvc = reinterpret_cast<PvConst*>(base + o_pvc);
     void* rows = base + o_rows;
-    e = launch_pv_setup_k(pv_d, npv, npar, t->grid.k0, t->grid.k1, pvc, stream, k_small);
+    e = launch_pv_setup_k(pv_d, npv, npar, t->grid.k0, t->grid.k1, pvc, precision, stream,
+                          k_small);
     if (e == hipSuccess)
         e = launch_small_planet_rows(t, pv_d, npv, npar, k_small, precision, rows, stream);
     if (e == hipSuccess)
@@ -713,7 +715,7 @@ RR_API int rr_evaluate_ld(const rr_tables* t, const double* times_d,
     PvConst* pvc = reinterpret_cast<PvConst*>(base + o_pvc);
     double* inv_is = reinterpret_cast<double*>(base + o_iis);
     void* ldw = base + o_ldw;
-    e = launch_pv_setup(t, pv_d, npv, npar, pvc, stream);
+    e = launch_pv_setup(t, pv_d, npv, npar, pvc, precision, stream);
     if (e == hipSuccess)
         e = launch_pv_ld(t, prof_d, pv_d, npv, npar, precision,
                          reinterpret_cast<double*>(base + o_ldp),
@@ -852,8 +854,9 @@ static int loglik_impl(const rr_tables* t, const double* times_d,
     A.seg_flag = segs ? reinterpret_cast<int32_t*>(base + o_sfl) : nullptr;
     A.logl = logl_d; A.grad = grad_d;
     e = sp ? launch_pv_setup_k(pv_d, npv, npar, t->grid.k0, t->grid.k1,
-                               const_cast<PvConst*>(A.pvc), stream, k_small)
-           : launch_pv_setup(t, pv_d, npv, npar, const_cast<PvConst*>(A.pvc), stream);
+                               const_cast<PvConst*>(A.pvc), precision, stream, k_small)
+           : launch_pv_setup(t, pv_d, npv, npar, const_cast<PvConst*>(A.pvc), precision,
+                             stream);
     if (e == hipSuccess && sp)
         e = launch_small_planet_adj_rows(t, pv_d, npv, npar, k_small, precision, base + o_rows,
                                          reinterpret_cast<double*>(base + o_iisr), stream);

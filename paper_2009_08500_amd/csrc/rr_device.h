@@ -300,7 +300,11 @@ __host__ __device__ inline bool is_finite(double x) { return (x - x) == 0.0; }
 // [0, 1), a k outside [k0, k1] or |cos i| > 1.
 // A radius ratio below k_small (small-planet rows, Sect. 3.4.2) only has to
 // be positive; any other must lie in [k0, k1].
-template <class Ops = HwOps>
+// kF32 (the mixed precision's setup, whose constants feed float orbit
+// arithmetic): sin w, cos w (of w first reduced to [-pi, pi] in double) and
+// sqrt(1 - e^2) in float; every forward path of one precision derives its
+// constants with the same kF32, so they share their bits.
+template <bool kF32 = false, class Ops = HwOps>
 __host__ __device__ inline PvConst make_pv_const(const double* row, int npb, double k0,
                                                  double k1, double k_small = 0.0) {
     PvConst c = {};
@@ -318,9 +322,22 @@ __host__ __device__ inline PvConst make_pv_const(const double* row, int npb, dou
     // Few divisions, and most of them off the dependent chain: the
     // reciprocals of p = a (1 - e^2) and P do not wait for sin w.
     double sw = 0.0, cw = 1.0;
-    if (ok) sincos(w, &sw, &cw);
     const double ome2 = 1.0 - e * e;
-    const double q = ok ? sqrt(ome2) : 1.0;
+    double q = 1.0;
+    if (ok) {
+        if (kF32) {
+            const double inv2pi = 0.5 / Num<double>::pi;
+            const double wr = w - 2.0 * Num<double>::pi * rint(w * inv2pi);
+            float sf, cf;
+            sincosf(float(wr), &sf, &cf);
+            sw = sf;
+            cw = cf;
+            q = double(Ops::sqrt(float(ome2)));
+        } else {
+            sincos(w, &sw, &cw);
+            q = sqrt(ome2);
+        }
+    }
     const double p = a * ome2;                       // semi-latus rectum
     const double inv_p = ok ? 1.0 / p : 0.0;
     // conjunction: f_tr = pi/2 - w, so cos f_tr = sin w and sin f_tr = cos w,

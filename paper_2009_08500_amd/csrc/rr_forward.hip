@@ -44,12 +44,13 @@ constexpr int kFwdJ[3] = {4, 8, 16};
 static_assert(kTimesPerThread % 4 == 0 && kTimesPerThread <= 32,
               "pass 1 packs 4 float or 2 double outputs per 16-B store");
 
+template <bool kF32>
 __global__ void k_pv_setup(const double* __restrict__ pv, int32_t npv,
                            int32_t npar, double k0, double k1, double k_small,
                            PvConst* __restrict__ out) {
     const int ipv = blockIdx.x * blockDim.x + threadIdx.x;
     if (ipv >= npv) return;
-    out[ipv] = make_pv_const(pv + int64_t(ipv) * npar, npar - 6, k0, k1, k_small);
+    out[ipv] = make_pv_const<kF32>(pv + int64_t(ipv) * npar, npar - 6, k0, k1, k_small);
 }
 
 // Per-row, per-passband constants of pass 2: the two k-rows of T that
@@ -440,10 +441,11 @@ __device__ inline bool win_in(double gph, const Win& w) { return gph - floor(gph
 // Constants of row ipv in the split launch: read from the per-row setup's
 // output, or (kSelf) derived here from the parameter row by the same
 // function, so both give the same bits.
-template <bool kSelf>
+template <typename R, bool kSelf>
 __device__ inline PvConst split_row_const(const FwdJob& job, const SplitInfo& si, int ipv) {
     if (kSelf)
-        return make_pv_const(job.pv + int64_t(ipv) * job.npar, job.npar - 6, si.k_lo, si.k_hi);
+        return make_pv_const<std::is_same<R, float>::value>(job.pv + int64_t(ipv) * job.npar,
+                                                            job.npar - 6, si.k_lo, si.k_hi);
     return job.pvc[ipv];
 }
 
@@ -512,7 +514,7 @@ __device__ inline void stream_rows(const FwdJob& job, const LcInfo& lc, const Sp
         if (k == 0) {
             const int rl = ipv + lane;
             if (rl < r1) {
-                const PvConst pl = split_row_const<kSelf>(job, si, rl);
+                const PvConst pl = split_row_const<R, kSelf>(job, si, rl);
                 c_t0 = pl.t0; c_invP = pl.invP; c_flo = pl.flo; c_wn = pl.wn;
                 c_ok = pl.flags & kValid;
             }
@@ -595,7 +597,7 @@ __device__ inline void transit_share(const FwdJob& job, const LcInfo& lc, const 
                                      const R* __restrict__ T,
                                      const double* __restrict__ inv_istar) {
     const int lane = threadIdx.x & 63;
-    const PvConst p = split_row_const<kSelf>(job, si, ipv);
+    const PvConst p = split_row_const<R, kSelf>(job, si, ipv);
     if (!(p.flags & kValid)) return;
     const double* __restrict__ times = job.times;
     R* __restrict__ orow = static_cast<R*>(job.out) + int64_t(ipv) * job.npt;
@@ -759,7 +761,8 @@ __global__ void k_pv_setup_jobs(SetupTable st, double k0, double k1) {
     const SetupJob& sj = st.j[jj];
     const int ipv = t - sj.thread0;
     if (ipv < 0 || ipv >= sj.npv) return;
-    sj.pvc[ipv] = make_pv_const(sj.pv + int64_t(ipv) * sj.npar, sj.npar - 6, k0, k1);
+    sj.pvc[ipv] = sj.f32 ? make_pv_const<true>(sj.pv + int64_t(ipv) * sj.npar, sj.npar - 6, k0, k1)
+                         : make_pv_const<false>(sj.pv + int64_t(ipv) * sj.npar, sj.npar - 6, k0, k1);
 }
 
 inline unsigned nblocks(int64_t n) { return unsigned((n + kBlock - 1) / kBlock); }
@@ -767,14 +770,19 @@ inline unsigned nblocks(int64_t n) { return unsigned((n + kBlock - 1) / kBlock);
 }  // namespace
 
 hipError_t launch_pv_setup(const rr_tables* t, const double* pv, int32_t npv,
-                           int32_t npar, PvConst* pvc, hipStream_t s) {
-    return launch_pv_setup_k(pv, npv, npar, t->grid.k0, t->grid.k1, pvc, s);
+                           int32_t npar, PvConst* pvc, int32_t precision, hipStream_t s) {
+    return launch_pv_setup_k(pv, npv, npar, t->grid.k0, t->grid.k1, pvc, precision, s);
 }
 
 hipError_t launch_pv_setup_k(const double* pv, int32_t npv, int32_t npar, double k_lo,
-                             double k_hi, PvConst* pvc, hipStream_t s, double k_small) {
-    hipLaunchKernelGGL(k_pv_setup, dim3(nblocks(npv)), dim3(kBlock), 0, s, pv, npv,
-                       npar, k_lo, k_hi, k_small, pvc);
+                             double k_hi, PvConst* pvc, int32_t precision, hipStream_t s,
+                             double k_small) {
+    if (precision == RR_FP64)
+        hipLaunchKernelGGL(k_pv_setup<false>, dim3(nblocks(npv)), dim3(kBlock), 0, s, pv, npv,
+                           npar, k_lo, k_hi, k_small, pvc);
+    else
+        hipLaunchKernelGGL(k_pv_setup<true>, dim3(nblocks(npv)), dim3(kBlock), 0, s, pv, npv,
+                           npar, k_lo, k_hi, k_small, pvc);
     return hipGetLastError();
 }
 

@@ -98,7 +98,7 @@ struct JobTable {
 struct SetupJob {
     const double* pv;
     PvConst* pvc;
-    int32_t npv, npar, thread0, pad;
+    int32_t npv, npar, thread0, f32;   // f32: the mixed precision's setup
 };
 struct SetupTable {
     int32_t njobs;
@@ -226,13 +226,14 @@ rr::GridDev grid_dev(const rr_tables* t);
 // Kernel launchers (rr_prep.hip, rr_forward.hip).
 hipError_t launch_prepare_grid_weights(rr_tables* t, hipStream_t s);
 hipError_t launch_prepare_profile(rr_tables* t, hipStream_t s);
-// Per-row constants; k must lie in [k_lo, k_hi] (the tables' k range by
-// default; the direct model takes (0, 1]), or in (0, k_small) for
-// small-planet rows.
+// Per-row constants for the forward paths of `precision`; k must lie in
+// [k_lo, k_hi] (the tables' k range by default; the direct model takes
+// (0, 1]), or in (0, k_small) for small-planet rows.
 hipError_t launch_pv_setup(const rr_tables* t, const double* pv, int32_t npv,
-                           int32_t npar, PvConst* pvc, hipStream_t s);
+                           int32_t npar, PvConst* pvc, int32_t precision, hipStream_t s);
 hipError_t launch_pv_setup_k(const double* pv, int32_t npv, int32_t npar, double k_lo,
-                             double k_hi, PvConst* pvc, hipStream_t s, double k_small = 0.0);
+                             double k_hi, PvConst* pvc, int32_t precision, hipStream_t s,
+                             double k_small = 0.0);
 // Dynamic LDS of one log-likelihood workgroup: the k-interpolated LD
 // vectors and their k-derivatives, plus (prof) each wave's copy of
 // d logL / d ldw and d logL / d I_star.

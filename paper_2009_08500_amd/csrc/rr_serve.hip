@@ -218,6 +218,7 @@ bool rr_server::step() {
             sj.npv = r->npv;
             sj.npar = r->npar;
             sj.thread0 = nthreads;
+            sj.f32 = r->precision == RR_FP64 ? 0 : 1;
             nthreads += r->npv;
             {
                 std::lock_guard<std::mutex> lk(mu);

@@ -16,10 +16,13 @@ struct HostOps {
 extern "C" {
 int probe_pvconst_size() { return int(sizeof(rr::PvConst)); }
 // rows[n][npar] -> flags, window start and width (phase units) per row
-void probe_windows(const double* rows, int n, int npar, double k0, double k1,
+// f32: the mixed precision's setup (float sin w, cos w and sqrt(1 - e^2))
+void probe_windows(const double* rows, int n, int npar, double k0, double k1, int f32,
                    int* flags, double* flo, double* wn) {
     for (int i = 0; i < n; ++i) {
-        const rr::PvConst c = rr::make_pv_const<HostOps>(rows + size_t(i) * npar, npar - 6, k0, k1);
+        const rr::PvConst c =
+            f32 ? rr::make_pv_const<true, HostOps>(rows + size_t(i) * npar, npar - 6, k0, k1)
+                : rr::make_pv_const<false, HostOps>(rows + size_t(i) * npar, npar - 6, k0, k1);
         flags[i] = c.flags;
         flo[i] = c.flo;
         wn[i] = c.wn;

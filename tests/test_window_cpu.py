@@ -33,18 +33,20 @@ def probe(tmp_path_factory):
     subprocess.run(cmd, check=True, capture_output=True)
     lib = ctypes.CDLL(out)
     lib.probe_windows.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
-                                  ctypes.c_double, ctypes.c_double,
+                                  ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
     return lib
 
 
-def windows(lib, rows, k0=0.01, k1=0.30):
+def windows(lib, rows, k0=0.01, k1=0.30, f32=0):
+    """The setup's validity flags and window per row: FP64 (f32 = 0) or
+    the mixed precision's setup (float sin w, cos w and sqrt(1 - e^2))."""
     rows = np.ascontiguousarray(rows, np.float64)
     n, npar = rows.shape
     flags = np.zeros(n, np.int32)
     flo = np.zeros(n)
     wn = np.zeros(n)
-    lib.probe_windows(rows.ctypes.data, n, npar, k0, k1, flags.ctypes.data,
+    lib.probe_windows(rows.ctypes.data, n, npar, k0, k1, int(f32), flags.ctypes.data,
                       flo.ctypes.data, wn.ctypes.data)
     return flags, flo, wn
 
@@ -74,9 +76,10 @@ def random_rows(n, seed):
     return np.array(rows)
 
 
-def test_window_contains_every_overlap(probe):
+@pytest.mark.parametrize("f32", [0, 1])
+def test_window_contains_every_overlap(probe, f32):
     rows = random_rows(240, 11)
-    flags, flo, wn = windows(probe, rows)
+    flags, flo, wn = windows(probe, rows, f32=f32)
     checked = 0
     for row, f, lo, width in zip(rows, flags, flo, wn):
         if not f & 1:
@@ -100,10 +103,11 @@ def test_window_contains_every_overlap(probe):
     assert checked > 150
 
 
-def test_window_is_tight_for_the_population(probe):
+@pytest.mark.parametrize("f32", [0, 1])
+def test_window_is_tight_for_the_population(probe, f32):
     import workloads as wl
     pv = wl.draw_orbits(np.random.default_rng(5), 64)
-    flags, flo, wn = windows(probe, pv)
+    flags, flo, wn = windows(probe, pv, f32=f32)
     assert np.all(flags & 1) and not np.any(flags & K_ALWAYS)
     for row, lo, width in zip(pv, flo, wn):
         P = row[1]
