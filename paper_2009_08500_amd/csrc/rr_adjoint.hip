@@ -870,7 +870,7 @@ hipError_t launch_adjoint(const AdjointArgs& A, int32_t precision, hipStream_t s
 // D[j][q] = sum_m W[ik][j][m] (1 - ak_q) g_q[m] + W[ik+1][j][m] ak_q g_q[m]
 // (g_q = dlogL/dldw of row q, zero for rows on another k-row), two
 // v_mfma_f64_16x16x4f64 chains into one accumulator; lane layout as in
-// k_pv_tables_mfma.  Block = 4 waves = 64 bins x 16 rows.
+// the matrix-core part of k_pv_tables.  Block = 4 waves = 64 bins x 16 rows.
 typedef double v4d __attribute__((ext_vector_type(4)));
 template <typename WT>
 __global__ __launch_bounds__(kBlock) void k_pv_ldp_grad_mfma(

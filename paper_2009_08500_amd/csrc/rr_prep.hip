@@ -181,7 +181,7 @@ hipError_t launch_prepare_grid_weights(rr_tables* t, hipStream_t s) {
 // T_r[s][m] = sum_j W[ik_r + s][j][m] ldp[r][j], s = 0, 1, around its k
 // (Sect. 3.1.2: T = W . l, then the k-interpolation in the forward kernel).
 // k_pv_prep sorts the rows by ik, so that rows with equal ik share the W
-// reads of one matrix-core tile (k_pv_tables_mfma, k_pv_tables below).
+// reads of one matrix-core tile (the two parts of k_pv_tables below).
 // Stable counting sort of the rows by ik, by one workgroup of kBlock
 // threads (thread t owns bins 16 t .. 16 t + 15 of at most 4096): the
 // histogram and its scan by all waves, then one wave places the rows in
@@ -285,25 +285,22 @@ __global__ __launch_bounds__(kBlock) void k_pv_prep(const double* __restrict__ m
 }
 
 // Rows of a sorted 16-row tile with at most two distinct k-rows go to the
-// matrix cores (k_pv_tables_mfma, which then reads each W value once for up
+// matrix cores (pv_tables_mfma, which then reads each W value once for up
 // to 16 rows); the rows of the other tiles (k spread over many k-rows, where
-// a tile would need a pass per k-row) to k_pv_tables, one workgroup per
-// (row, 256 m).  Both kernels evaluate the same test on the sorted keys, so
+// a tile would need a pass per k-row) to pv_tables_rows, one workgroup per
+// (row, 256 m).  Both parts evaluate the same test on the sorted keys, so
 // every row is written by exactly one of them.
-// k_pv_tables: rows taken in sorted order, with an XCD-aware block order: blocks go round-robin to the eight XCDs, so block
+// pv_tables_rows: rows taken in sorted order, with an XCD-aware block order: blocks go round-robin to the eight XCDs, so block
 // p works on sorted item (p mod 8) * (blocks / 8) + p / 8 (rounded for a
 // remainder) and each XCD walks a contiguous stretch of the sorted rows,
 // whose W rows its L2 then serves to the following rows of equal ik.
 constexpr int kXcds = 8;
 template <typename R, typename WT>
-__global__ __launch_bounds__(kBlock) void k_pv_tables(const WT* __restrict__ W,
-                                                      const double* __restrict__ ldp,
-                                                      const int32_t* __restrict__ ikr,
-                                                      const int32_t* __restrict__ perm,
-                                                      int32_t nz, GridDev g,
-                                                      R* __restrict__ out) {
-    __shared__ double lp[4096];
-    const int64_t nb = gridDim.x, p = blockIdx.x;
+__device__ inline void pv_tables_rows(const WT* __restrict__ W, const double* __restrict__ ldp,
+                                      const int32_t* __restrict__ ikr,
+                                      const int32_t* __restrict__ perm, int32_t nz, GridDev g,
+                                      R* __restrict__ out, int64_t nb, int64_t p,
+                                      double* __restrict__ lp) {
     const int64_t q = nb / kXcds, rem = nb % kXcds;
     const int64_t x = p % kXcds;
     const int64_t L = (x < rem ? x * (q + 1) : rem * (q + 1) + (x - rem) * q) + p / kXcds;
@@ -353,15 +350,13 @@ __global__ __launch_bounds__(kBlock) void k_pv_tables(const WT* __restrict__ W,
 // (checked on the device).  Block = 4 waves = 64 m x 16 rows.
 typedef double v4d __attribute__((ext_vector_type(4)));
 template <typename R, typename WT>
-__global__ __launch_bounds__(kBlock) void k_pv_tables_mfma(const WT* __restrict__ W,
-                                                           const double* __restrict__ ldp,
-                                                           const int32_t* __restrict__ ikr,
-                                                           const int32_t* __restrict__ perm,
-                                                           int64_t nr, int32_t nz, GridDev g,
-                                                           R* __restrict__ out) {
+__device__ inline void pv_tables_mfma(const WT* __restrict__ W, const double* __restrict__ ldp,
+                                      const int32_t* __restrict__ ikr,
+                                      const int32_t* __restrict__ perm, int64_t nr, int32_t nz,
+                                      GridDev g, R* __restrict__ out, int64_t bid) {
     const int nmb = (g.ng + 63) / 64;
-    const int64_t rt = int64_t(blockIdx.x) / nmb;            // row tile
-    const int mb = int(int64_t(blockIdx.x) - rt * nmb);
+    const int64_t rt = bid / nmb;                              // row tile
+    const int mb = int(bid - rt * nmb);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int m0 = mb * 64 + wave * 16;
     const int ka = lane >> 4, col = lane & 15;
@@ -416,6 +411,27 @@ __global__ __launch_bounds__(kBlock) void k_pv_tables_mfma(const WT* __restrict_
             o[g.ng + m] = R(d1[i]);
         }
     }
+}
+
+// One launch for both: blocks [0, n_mfma) take matrix-core tiles, the
+// others the per-row work (n_mfma is a multiple of the XCD count, so the
+// per-row blocks keep their XCD-aware order).  Each row is written by
+// exactly one of the two, as the same test on the sorted keys decides.
+template <typename R, typename WT>
+__global__ __launch_bounds__(kBlock) void k_pv_tables(const WT* __restrict__ W,
+                                                      const double* __restrict__ ldp,
+                                                      const int32_t* __restrict__ ikr,
+                                                      const int32_t* __restrict__ perm,
+                                                      int64_t nr, int32_t nz, GridDev g,
+                                                      int64_t n_mfma, R* __restrict__ out) {
+    __shared__ double lp[4096];
+    const int64_t b = blockIdx.x;
+    if (b < n_mfma) {
+        pv_tables_mfma<R, WT>(W, ldp, ikr, perm, nr, nz, g, out, b);
+        return;
+    }
+    pv_tables_rows<R, WT>(W, ldp, ikr, perm, nz, g, out, int64_t(gridDim.x) - n_mfma,
+                          b - n_mfma, lp);
 }
 
 // Direct model (Sect. 3.1.1): the LD-weighted vector of row r = (vector,
@@ -652,26 +668,22 @@ hipError_t launch_pv_ld(const rr_tables* t, const double* prof, const double* pv
                        t->nmu, t->zm, t->nz, pv, npv, npar, g, ldp, istar, inv_istar, ikr, perm);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const dim3 grid(unsigned(((nr + 15) / 16) * ((g.ng + 63) / 64)));
-    const dim3 grid_rows(unsigned(nr * ((g.ng + kBlock - 1) / kBlock)));
-    // both kernels read the same weights (FP64, or the FP32 copy with w32),
-    // so a row's values do not depend on which kernel its tile went to
-    if (precision == RR_FP64) {
-        hipLaunchKernelGGL((k_pv_tables_mfma<double, double>), grid, dim3(kBlock), 0, s, t->W,
-                           ldp, ikr, perm, nr, t->nz, g, static_cast<double*>(rows));
-        hipLaunchKernelGGL((k_pv_tables<double, double>), grid_rows, dim3(kBlock), 0, s, t->W,
-                           ldp, ikr, perm, t->nz, g, static_cast<double*>(rows));
-    } else if (w32) {
-        hipLaunchKernelGGL((k_pv_tables_mfma<float, float>), grid, dim3(kBlock), 0, s, t->W32,
-                           ldp, ikr, perm, nr, t->nz, g, static_cast<float*>(rows));
-        hipLaunchKernelGGL((k_pv_tables<float, float>), grid_rows, dim3(kBlock), 0, s,
-                           t->W32, ldp, ikr, perm, t->nz, g, static_cast<float*>(rows));
-    } else {
-        hipLaunchKernelGGL((k_pv_tables_mfma<float, double>), grid, dim3(kBlock), 0, s, t->W,
-                           ldp, ikr, perm, nr, t->nz, g, static_cast<float*>(rows));
-        hipLaunchKernelGGL((k_pv_tables<float, double>), grid_rows, dim3(kBlock), 0, s,
-                           t->W, ldp, ikr, perm, t->nz, g, static_cast<float*>(rows));
-    }
+    // matrix-core tiles rounded up to whole rounds of the XCDs, then the
+    // per-row blocks; both parts read the same weights (FP64, or the FP32
+    // copy with w32), so a row's values do not depend on which part took it
+    const int64_t n_mfma = ((nr + 15) / 16 * ((g.ng + 63) / 64) + kXcds - 1) / kXcds * kXcds;
+    const int64_t n_rows = nr * ((g.ng + kBlock - 1) / kBlock);
+    if (n_mfma + n_rows >= (int64_t(1) << 31)) return hipErrorInvalidValue;
+    const dim3 grid(unsigned(n_mfma + n_rows));
+    if (precision == RR_FP64)
+        hipLaunchKernelGGL((k_pv_tables<double, double>), grid, dim3(kBlock), 0, s, t->W, ldp,
+                           ikr, perm, nr, t->nz, g, n_mfma, static_cast<double*>(rows));
+    else if (w32)
+        hipLaunchKernelGGL((k_pv_tables<float, float>), grid, dim3(kBlock), 0, s, t->W32, ldp,
+                           ikr, perm, nr, t->nz, g, n_mfma, static_cast<float*>(rows));
+    else
+        hipLaunchKernelGGL((k_pv_tables<float, double>), grid, dim3(kBlock), 0, s, t->W, ldp,
+                           ikr, perm, nr, t->nz, g, n_mfma, static_cast<float*>(rows));
     return hipGetLastError();
 }
 
