@@ -188,11 +188,16 @@ hipError_t launch_prepare_grid_weights(rr_tables* t, hipStream_t s) {
 // row order, 64 at a time -- a lane's rank among the lanes with its key
 // comes from a ballot per key bit -- so equal keys keep their row order
 // and the tiles (and which kernel takes each) depend on the inputs only.
+// The keys of the first kSortLds rows also go to LDS (as 16-bit values,
+// nk <= 4096), so that the placing wave's serial loop reads them there
+// rather than waiting on a global load in every step.
+constexpr int kSortLds = 8192;
 __device__ inline void sort_rows(const double* __restrict__ pv, int32_t npv, int32_t npar,
                                  const GridDev& g, int32_t* __restrict__ ikr,
                                  int32_t* __restrict__ perm) {
     constexpr int kPer = 4096 / kBlock;
     __shared__ int cnt[4096];
+    __shared__ uint16_t keys[kSortLds];
     __shared__ int wsum[kBlock / 64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t n = int64_t(npv) * g.npb;
@@ -207,6 +212,7 @@ __device__ inline void sort_rows(const double* __restrict__ pv, int32_t npv, int
         if (uf > g.nk - 2) uf = g.nk - 2;
         const int ik = int(uf);
         ikr[r] = ik;
+        if (r < kSortLds) keys[r] = uint16_t(ik);
         atomicAdd(&cnt[ik], 1);
     }
     __syncthreads();
@@ -238,7 +244,7 @@ __device__ inline void sort_rows(const double* __restrict__ pv, int32_t npv, int
     for (int64_t r0 = 0; r0 < n; r0 += 64) {
         const int64_t r = r0 + lane;
         const bool in = r < n;
-        const int key = in ? ikr[r] : 0;
+        const int key = in ? (r < kSortLds ? int(keys[r]) : ikr[r]) : 0;
         uint64_t same = __ballot(in);            // lanes with this lane's key
 #pragma unroll
         for (int b = 0; b < 12; ++b) {           // keys < nk <= 4096
@@ -260,9 +266,10 @@ __device__ inline void sort_rows(const double* __restrict__ pv, int32_t npv, int
     }
 }
 
-// One launch for the per-vector preparation: workgroup r < nr interpolates
-// row r's profile to the bin means and integrates its I_star (the table
-// kernels' arithmetic); workgroup nr sorts the rows by ik.
+// One launch for the per-vector preparation: workgroup 0 sorts the rows by
+// ik (the longest serial chain, so it is dispatched first), and workgroup
+// r + 1 interpolates row r's profile to the bin means and integrates its
+// I_star (the table kernels' arithmetic).
 __global__ __launch_bounds__(kBlock) void k_pv_prep(const double* __restrict__ mu_s,
                                                     const double* __restrict__ prof,
                                                     int32_t nmu, const double* __restrict__ zm,
@@ -274,11 +281,12 @@ __global__ __launch_bounds__(kBlock) void k_pv_prep(const double* __restrict__ m
                                                     int32_t* __restrict__ ikr,
                                                     int32_t* __restrict__ perm) {
     const int64_t nr = int64_t(npv) * g.npb;
-    const int64_t r = blockIdx.x;
-    if (r == nr) {
+    if (blockIdx.x == 0) {
         sort_rows(pv, npv, npar, g, ikr, perm);
         return;
     }
+    const int64_t r = int64_t(blockIdx.x) - 1;
+    if (r >= nr) return;
     const double* f = prof + r * nmu;
     for (int j = threadIdx.x; j < nz; j += kBlock) ldp[r * nz + j] = profile_at_bin(mu_s, f, nmu, zm[j]);
     istar_block(mu_s, f, nmu, istar + r, inv_istar + r);
