@@ -693,7 +693,9 @@ def serving_leg(rr, wl, nreq, nburst):
     for prec in ("mixed", "fp64"):
         for device in (True, False):
             key = f"{prec}_{'device' if device else 'host'}_output"
-            run(prec, device, range(min(nburst, 64)), None)        # untimed warm-up
+            # untimed warm-up over the same requests: the first pass grows the
+            # server's and the rings' memory, which the timed burst must not see
+            run(prec, device, range(nburst), None)
             el, _, _, _ = run(prec, device, range(nburst), None)
             sat = nburst / el
             entry = dict(saturated_requests_per_s=sat,

@@ -233,9 +233,6 @@ bool rr_server::step() {
             last_error = RR_EDEVICE;
     }
     // 4. one tick if fewer than two are in flight
-    active.erase(std::remove_if(active.begin(), active.end(),
-                                [](Request* r) { return r->next_row >= r->npv; }),
-                 active.end());
     if (!active.empty() && ticks.size() < 2) {
         std::vector<TickReq> want(active.size());
         for (size_t i = 0; i < active.size(); ++i)
@@ -282,6 +279,13 @@ bool rr_server::step() {
             nticks += 1;
             did = true;
         }
+        // A request leaves `active` as soon as its last rows are launched,
+        // before any tick of it can complete: once finish() has marked it
+        // done, the caller may release (delete) it at any moment, so no
+        // list of the worker may still hold it then.
+        active.erase(std::remove_if(active.begin(), active.end(),
+                                    [](Request* r) { return r->next_row >= r->npv; }),
+                     active.end());
     }
     return did;
 }
@@ -290,16 +294,27 @@ void rr_server::run() {
     (void)hipSetDevice(device);
     while (true) {
         const bool did = step();
-        std::unique_lock<std::mutex> lk(mu);
-        const bool idle = incoming.empty() && pending.empty() && active.empty() &&
-                          ticks.empty() && copying.empty();
-        if (stop && idle) break;
-        if (!did) {
-            if (idle)
+        hipEvent_t oldest = nullptr;
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            const bool idle = incoming.empty() && pending.empty() && active.empty() &&
+                              ticks.empty() && copying.empty();
+            if (stop && idle) break;
+            if (did) continue;
+            if (idle) {
                 cv_work.wait_for(lk, std::chrono::milliseconds(2));
+                continue;
+            }
+            // Both tick slots busy and nothing else to watch: the next thing
+            // that can happen is the oldest tick completing, so wait for it
+            // on the event rather than sleeping (a timed sleep lasts tens of
+            // us, longer than a short tick, and would leave the GPU idle).
+            if (incoming.empty() && copying.empty() && ticks.size() >= 2 && ticks.front().ev)
+                oldest = ticks.front().ev;
             else
                 cv_work.wait_for(lk, std::chrono::microseconds(20));
         }
+        if (oldest) (void)hipEventSynchronize(oldest);
     }
 }
 
