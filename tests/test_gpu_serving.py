@@ -204,3 +204,48 @@ def test_failed_launch_completes_requests_with_error(env):
     srv.wait(again)
     assert np.array_equal(again.out.numpy(), ok.out.numpy())
     srv.close()
+
+
+def test_release_as_soon_as_done(env):
+    """A waiting thread releases every request the moment it completes while
+    the submitting thread keeps queueing more: every request completes (the
+    wait's time limit turns a lost request into a failure, not a hang), with
+    its values, and the server's count matches.  Guards the rule that the
+    worker holds no reference to a request once it can complete."""
+    import queue
+    import threading
+    import torch
+    rr, tab, otab, series, reqs = env
+    srv = rr.Server(tab, budget_bytes=1 << 28, max_tick_blocks=64)
+    combos = []
+    for k in range(4):
+        se = series[k]
+        sid = srv.add_series(se["times"], se["lcids"], se["pbids"], se["nss"], se["exptimes"])
+        pv = reqs[k]["pv"][:3]
+        combos.append((sid, pv, evaluate_direct(rr, tab, se, pv, "mixed")))
+    n = 400
+    q = queue.Queue()
+    bad = []
+
+    def waiter():
+        for _ in range(n):
+            i, h = q.get()
+            try:
+                out = srv.wait(h, timeout=30.0)
+                torch.cuda.synchronize()
+                if not np.array_equal(out.cpu().numpy(), combos[i % 4][2]):
+                    bad.append(i)
+                srv.release(h)
+            except Exception as e:          # noqa: BLE001 -- reported below
+                bad.append((i, repr(e)))
+
+    th = threading.Thread(target=waiter)
+    th.start()
+    for i in range(n):
+        sid, pv, _ = combos[i % 4]
+        q.put((i, srv.submit(sid, pv, "mixed", device_out=True)))
+    th.join(timeout=90.0)
+    assert not th.is_alive()
+    assert bad == []
+    assert srv.stats()["completed"] == n
+    srv.close()
