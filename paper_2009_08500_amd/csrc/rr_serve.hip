@@ -295,6 +295,7 @@ void rr_server::run() {
     while (true) {
         const bool did = step();
         hipEvent_t oldest = nullptr;
+        bool poll = false;
         {
             std::unique_lock<std::mutex> lk(mu);
             const bool idle = incoming.empty() && pending.empty() && active.empty() &&
@@ -305,16 +306,30 @@ void rr_server::run() {
                 cv_work.wait_for(lk, std::chrono::milliseconds(2));
                 continue;
             }
-            // Both tick slots busy and nothing else to watch: the next thing
-            // that can happen is the oldest tick completing, so wait for it
-            // on the event rather than sleeping (a timed sleep lasts tens of
-            // us, longer than a short tick, and would leave the GPU idle).
+            // A timed sleep lasts tens of us, longer than a short tick, so
+            // while ticks are in flight the worker does not sleep: with both
+            // tick slots busy and nothing else to watch it waits on the
+            // oldest tick's event (nothing else can happen first); with a
+            // slot free it polls that event for a while, taking a new
+            // request or a finished copy at the next step.
             if (incoming.empty() && copying.empty() && ticks.size() >= 2 && ticks.front().ev)
                 oldest = ticks.front().ev;
+            else if (!ticks.empty() && ticks.front().ev)
+                poll = true;
             else
                 cv_work.wait_for(lk, std::chrono::microseconds(20));
         }
-        if (oldest) (void)hipEventSynchronize(oldest);
+        if (oldest) {
+            (void)hipEventSynchronize(oldest);
+        } else if (poll) {
+            const auto until = std::chrono::steady_clock::now() + std::chrono::microseconds(50);
+            while (hipEventQuery(ticks.front().ev) == hipErrorNotReady &&
+                   std::chrono::steady_clock::now() < until) {
+                std::this_thread::yield();
+                std::lock_guard<std::mutex> lk(mu);
+                if (!incoming.empty()) break;
+            }
+        }
     }
 }
 
