@@ -167,3 +167,23 @@ def test_deterministic_and_independent_of_batch(rr, precision):
         assert np.abs(c[0] - a[50]).max() <= 1e-13
     else:
         assert np.abs(c[0].astype(np.float64) - a[50]).max() <= 2e-7
+
+
+def test_more_rows_than_the_sort_keeps_in_lds(rr):
+    """8300 rows: the sorting workgroup keeps the keys of the first 8192 rows
+    in LDS and reads the rest from memory.  Two identical calls agree
+    bitwise (a stable sort), rows on both sides of that bound match the oracle,
+    and the last rows alone give the same fluxes to rounding."""
+    w = wl.population_ld(npv=8300, npt=64)
+    tab = rr.Tables(w["mu_s"], w["I_s"], wl.TEST_GRID)
+    otab = orr.Tables(w["mu_s"], w["I_s"], **wl.TEST_GRID)
+    ser = rr.TimeSeries(w["times"])
+    pv, prof = w["pv"], w["prof_pv"]
+    f64 = rr.evaluate_ld(tab, ser, pv, prof, "fp64").cpu().numpy()
+    f32 = rr.evaluate_ld(tab, ser, pv, prof, "mixed").cpu().numpy()
+    assert np.array_equal(f64, rr.evaluate_ld(tab, ser, pv, prof, "fp64").cpu().numpy())
+    rows = np.array([0, 4097, 8191, 8192, 8250, 8299])
+    ref = orr.evaluate_ld(otab, w["times"], pv[rows], prof[rows])
+    check(ref, f64[rows], f32[rows].astype(np.float64))
+    tail = rr.evaluate_ld(tab, ser, pv[8192:], prof[8192:], "fp64").cpu().numpy()
+    assert np.abs(tail - f64[8192:]).max() <= 1e-13
