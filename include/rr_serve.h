@@ -79,7 +79,10 @@ RR_API int rr_server_poll(rr_server* s, int64_t request_id, int32_t* status,
 RR_API int rr_server_wait(rr_server* s, int64_t request_id, double timeout_s,
                           double* latency_s);
 
-/* Forget a finished request (its id becomes unknown). */
+/* Forget a finished request (its id becomes unknown); RR_EBUSY while it is
+ * still in flight.  Safe from any thread as soon as the request is done: the
+ * server keeps no reference to a request once its last rows have launched
+ * beyond the completion that marks it done. */
 RR_API int rr_server_release(rr_server* s, int64_t request_id);
 
 /* stats[0..4] = completed requests, completed light-curve points
