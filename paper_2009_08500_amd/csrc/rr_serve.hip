@@ -112,6 +112,7 @@ struct rr_server {
     std::vector<Request*> active;
     std::vector<Request*> copying;
     std::deque<Tick> ticks;
+    std::vector<hipEvent_t> tick_events;   // completed ticks' events, for reuse
     int tick_stream = 0;
     std::atomic<int> fail_next_tick{0};   // test hook: fail the next tick's launch
     // statistics (guarded by mu)
@@ -178,7 +179,7 @@ bool rr_server::step() {
                 copying.push_back(r);
             }
         }
-        if (tk.ev) (void)hipEventDestroy(tk.ev);
+        if (tk.ev) tick_events.push_back(tk.ev);
         ticks.pop_front();
         did = true;
     }
@@ -263,7 +264,14 @@ bool rr_server::step() {
             if (e == hipSuccess && fail_next_tick.exchange(0)) e = hipErrorLaunchFailure;
             for (int p = 0; p < 2 && e == hipSuccess; ++p)
                 e = launch_forward_jobs(t, jt[p], nb[p], p == 0 ? RR_FP64 : RR_MIXED, s);
-            if (e == hipSuccess) e = hipEventCreateWithFlags(&tk.ev, hipEventDisableTiming);
+            if (e == hipSuccess) {
+                if (!tick_events.empty()) {
+                    tk.ev = tick_events.back();
+                    tick_events.pop_back();
+                } else {
+                    e = hipEventCreateWithFlags(&tk.ev, hipEventDisableTiming);
+                }
+            }
             if (e == hipSuccess) e = hipEventRecord(tk.ev, s);
             if (e != hipSuccess) {
                 // whatever did launch finishes before the tick counts as
@@ -450,7 +458,8 @@ static int submit_impl(rr_server* s, int32_t series_id, const double* pv, int32_
         set_error("request footprint exceeds the server's memory budget");
         return RR_ELIMIT;
     }
-    if (hipEventCreateWithFlags(&r->done_ev, hipEventDisableTiming) != hipSuccess) {
+    // the copy-completion event serves host outputs only
+    if (!out_dev && hipEventCreateWithFlags(&r->done_ev, hipEventDisableTiming) != hipSuccess) {
         delete r;
         return hip_fail(hipErrorUnknown, "hipEventCreate");
     }
@@ -524,7 +533,7 @@ RR_API int rr_server_release(rr_server* s, int64_t request_id) {
     auto it = s->reqs.find(request_id);
     if (it == s->reqs.end()) return RR_ENOTFOUND;
     if (it->second->state != kDone) { set_error("request still in flight"); return RR_EBUSY; }
-    (void)hipEventDestroy(it->second->done_ev);
+    if (it->second->done_ev) (void)hipEventDestroy(it->second->done_ev);
     delete it->second;
     s->reqs.erase(it);
     return RR_OK;
@@ -556,6 +565,7 @@ RR_API void rr_server_destroy(rr_server* s) {
     if (s->setup_stream) (void)hipStreamDestroy(s->setup_stream);
     if (s->copy_stream) (void)hipStreamDestroy(s->copy_stream);
     if (s->setup_ev) (void)hipEventDestroy(s->setup_ev);
+    for (hipEvent_t ev : s->tick_events) (void)hipEventDestroy(ev);
     for (auto& se : s->series) {
         if (se.times) (void)hipFree(se.times);
         if (se.lcids) (void)hipFree(se.lcids);
