@@ -261,9 +261,9 @@ RR_API int rr_evaluate_noalloc(const rr_tables* t, const double* times_d,
 /* rr_evaluate with a chosen forward-kernel variant.  The variants differ
  * only in how work maps onto the GPU, never in the arithmetic of an
  * exposure, so every variant writes the values of rr_evaluate (bit for bit
- * in FP64 and without supersampling; for supersampled series in RR_MIXED
- * the float code of the two subsample paths may round differently, within
- * the mixed path's accuracy):
+ * without supersampling; for supersampled series the compiler may contract
+ * the arithmetic of the two subsample paths differently, so values may
+ * differ by an ulp in FP64 and by float rounding in RR_MIXED):
  *   variant 0, 1, 2   each lane owns 4, 8, 16 exposures (a workgroup, one
  *                     wave64, owns 256, 512, 1024 consecutive times); the
  *                     subsamples of supersampled exposures are spread over

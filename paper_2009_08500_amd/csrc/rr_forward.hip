@@ -340,7 +340,9 @@ __device__ inline void forward_block(const FwdJob& job, const LcInfo& lc, int ip
         // per lane, each with its gathers and an N-term reduction (measured
         // at ~1.5 subsamples of the per-lane loop); the per-lane loop N
         // times the largest number of flagged exposures of one lane.  The
-        // wave takes the cheaper (both give the same bits).
+        // wave takes the cheaper (both sum the same terms in the same order;
+        // their values agree to an ulp, as the compiler may contract the two
+        // copies of the subsample arithmetic differently).
         bool spread = job.spread && nmin == nmax && N >= 2 && N <= 32;
         if (spread) {
             int mine = __popc(todo), most = mine, flagged = mine;

@@ -44,13 +44,14 @@ def test_variants_equal_evaluate(rr, npt):
 
 
 def test_supersampled_variants(rr):
-    """Four passbands, nss 10 and 1.  In FP64 spreading subsamples over
-    lanes and one lane per exposure give the same bits (the same terms
-    summed in the same order).  In mixed precision the float arithmetic of
-    the two code paths may be contracted differently by the compiler, and
-    the tile size decides which path an exposure near a light-curve
-    boundary takes, so the variants agree to float rounding; every variant
-    is held to the oracle as rr_evaluate is."""
+    """Four passbands, nss 10 and 1.  Spreading subsamples over lanes and
+    one lane per exposure sum the same terms in the same order, but each
+    variant is its own instantiation of the kernel, whose arithmetic the
+    compiler may contract differently, and the tile size decides which
+    path an exposure near a light-curve boundary takes: in FP64 the
+    variants agree to an ulp of the flux (on 256 rows over 27 days, 2-30
+    of 10.6 M values differ, by 1.1e-16), in mixed precision to float
+    rounding; every variant is held to the oracle as rr_evaluate is."""
     from oracle import roadrunner as orr
     w = wl.heterogeneous(npv=8, days=3.0)
     kw = dict(lcids=w["lcids"], pbids=w["pbids"], nss=w["nss"], exptimes=w["exptimes"])
@@ -64,7 +65,7 @@ def test_supersampled_variants(rr):
     for v in range(rr.NUM_VARIANTS):
         o64 = rr.evaluate(tab, ser, w["pv"], "fp64", variant=v).cpu().numpy()
         o32 = rr.evaluate(tab, ser, w["pv"], "mixed", variant=v).cpu().numpy().astype(np.float64)
-        assert np.array_equal(o64, ref64), v
+        assert np.abs(o64 - ref64).max() <= 2.3e-16, (v, np.abs(o64 - ref64).max())
         assert np.abs(o32 - ref32).max() <= 1e-6, (v, np.abs(o32 - ref32).max())
         assert np.abs(o64 - oref).max() <= 1e-9
         assert np.abs(o32 - oref).max() <= 1e-6
