@@ -690,6 +690,12 @@ def serving_leg(rr, wl, nreq, nburst):
 
     rng = np.random.default_rng(2009085004)
     unit = rng.exponential(1.0, nreq)                  # the same arrival pattern, scaled
+    # The submitting and the waiting thread share the interpreter lock; with
+    # the default 5 ms switch interval one of them can hold it through many
+    # requests while the other waits, which made the burst's rate swing
+    # between runs.  A short interval keeps the two alternating.
+    switch = sys.getswitchinterval()
+    sys.setswitchinterval(1e-4)
     for prec in ("mixed", "fp64"):
         for device in (True, False):
             key = f"{prec}_{'device' if device else 'host'}_output"
@@ -712,6 +718,7 @@ def serving_leg(rr, wl, nreq, nburst):
                     ring_stalls=stalls)
             res[key] = entry
             print(f"serving {key}: " + json.dumps(entry), file=sys.stderr, flush=True)
+    sys.setswitchinterval(switch)
     st = srv.stats()
     res["grouped_launches"] = st["ticks"]
     res["device_errors"] = st["last_error"]
