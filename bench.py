@@ -771,7 +771,8 @@ def main():
     if args.gpus != 1:
         print("bench.py measures one GPU only: every run here has a single MI355X; "
               "the path would shard over parameter vectors (one slice per GPU, "
-              "tables replicated) -- see the design notes.", file=sys.stderr)
+              "tables replicated; only gradients with respect to the shared profile "
+              "would be summed across GPUs).", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch

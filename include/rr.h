@@ -85,7 +85,8 @@ extern "C" {
 /* Precision policies for rr_evaluate / rr_loglik_grad. */
 #define RR_FP64  0  /* every step in FP64; output double                  */
 #define RR_MIXED 1  /* FP64 phase reduction, FP32 orbit/area/tables,
-                       output float (see the design notes for the bound)  */
+                       output float; held to 1 ppm (absolute flux) of the
+                       FP64 model by the parity tests                      */
 
 /* Table resolution (Sect. 3.1.1, Sect. 3.1.2, Sect. 3.3).
  * zcut   radius dividing the inner region (bins of constant dz) from the
